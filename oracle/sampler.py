@@ -1,0 +1,97 @@
+"""One MLMC level sample (oracle; test infrastructure only).
+
+Algorithm 1 (level estimate with circulant embedding) and Algorithm 2
+(smoothed variant) of Sections 3.4-3.5, per sample:
+
+  Y = Q_f                       (SINGLE: level 0, or plain Monte Carlo)
+  Y = Q_{h_l} - Q_{h_{l-1}}     (PAIR: both from the same field sample)
+
+with the fine and coarse coefficients restricted from one field (step
+4(e)).  Smoothing is expressed by two drop counts of the fine level's
+embedding: tau_f for the field solved on the fine mesh and tau_c for the
+field solved on the coarse mesh.  Reading of eq. (mlmc-estimator-smoothed)
+(listed in the design doc): on levels l < L both use tau_l; on the finest level
+L the fine term is unsmoothed (tau_f = 0) and the coarse term keeps tau_L;
+when tau_f != tau_c the two fields come from two DFTs of the same xi.
+
+Sample index i maps to pair q = floor(i/2), component i mod 2 in PAIR field
+mode, and to q = i in HARTLEY field mode.
+
+desc keys: cov, nu, lam, sigma2, m, level (0 SINGLE / 1 PAIR), tau_f,
+tau_c (-1 = default n), psd, period, max_pad, field_mode, bc, qoi, qx, qy,
+f, stream.
+"""
+
+import numpy as np
+
+from . import embedding, field, fem, qoi
+
+SINGLE = 0
+PAIR_LEVEL = 1
+
+
+class Plan:
+    """Embedding set-up of a level (Algorithm 1 steps 1-3 + masks)."""
+
+    def __init__(self, desc):
+        self.desc = dict(desc)
+        st = embedding.setup(self.desc)
+        self.n = st["n"]
+        self.J = st["J"]
+        self.lam = st["lam"]
+        self.info = st
+        n = self.n
+        tf = self.desc.get("tau_f", 0)
+        tc = self.desc.get("tau_c", 0)
+        self.tau_f = embedding.tau_default(n) if tf < 0 else int(tf)
+        self.tau_c = embedding.tau_default(n) if tc < 0 else int(tc)
+        self.keep_f = embedding.mask(self.lam, self.tau_f)
+        self.keep_c = embedding.mask(self.lam, self.tau_c)
+        self.a_f = embedding.amplitudes(self.lam, self.keep_f)
+        self.a_c = embedding.amplitudes(self.lam, self.keep_c)
+
+    def fields(self, seed, i):
+        """(Z_f, Z_c) nodal fields of sample i; Z_c is None for SINGLE."""
+        d = self.desc
+        m = d["m"]
+        mode = d.get("field_mode", field.PAIR)
+        if mode == field.PAIR:
+            q, comp = i // 2, i % 2
+        else:
+            q, comp = i, 0
+        xi = field.xi(seed, q, d.get("stream", 0), self.n, mode)
+        zf = field.fields(self.a_f, xi, m, mode)[comp]
+        if d.get("level", SINGLE) == SINGLE:
+            return zf, None
+        if self.tau_c == self.tau_f:
+            zc_full = zf
+        else:
+            zc_full = field.fields(self.a_c, xi, m, mode)[comp]
+        return zf, field.restrict_coarse(zc_full)
+
+    def solve_q(self, z, m):
+        d = self.desc
+        k = np.exp(z)
+        bc = d.get("bc", fem.DIRICHLET0)
+        u, A, b = fem.solve(k, m, bc, d.get("f", 1.0))
+        return qoi.evaluate(d.get("qoi", qoi.INTEGRAL), u, m, A, b,
+                            d.get("qx", 7.0 / 15.0), d.get("qy", 7.0 / 15.0))
+
+    def sample(self, seed, i):
+        """(Y, Q_f, Q_c) of sample i (Q_c = 0 for SINGLE)."""
+        m = self.desc["m"]
+        zf, zc = self.fields(seed, i)
+        qf = self.solve_q(zf, m)
+        if zc is None:
+            return qf, qf, 0.0
+        qc = self.solve_q(zc, m // 2)
+        return qf - qc, qf, qc
+
+
+def level_samples(desc, seed, first, count):
+    """Y, Q_f, Q_c arrays for samples first .. first+count-1."""
+    plan = Plan(desc)
+    out = np.array([plan.sample(seed, first + t) for t in range(count)])
+    if count == 0:
+        return np.zeros(0), np.zeros(0), np.zeros(0)
+    return out[:, 0], out[:, 1], out[:, 2]
