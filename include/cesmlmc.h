@@ -1,0 +1,187 @@
+/*
+ * cesmlmc -- MLMC level sampler with (smoothed) circulant embedding on
+ * MI355X (gfx950).  C ABI.
+ *
+ * The operations follow Istratuca & Teckentrup, "Smoothed Circulant
+ * Embedding with Applications to Multilevel Monte Carlo Methods for PDEs
+ * with Random Coefficients":
+ *   covariance model          Section 2.1, eqs. (matern-cov-function),
+ *                             (p-norm-cov-function)
+ *   embedding + eigenvalues   Section 2.1.2; Algorithm 1 steps 1-3
+ *   padding / periodisation   Section 2.2, eq. (periodic-cov-fun)
+ *   smoothing (tau dropped)   Section 2.4, eq. (tau-definition); Algorithm 2
+ *   field sample              Algorithm 1 step 4(a)-(f)
+ *   PDE and its discretisation Section 3.1 eq. (pde-model), Section 3.2
+ *   level difference Y        Section 3.4 (Y_l = Q_{h_l} - Q_{h_{l-1}}),
+ *                             eq. (mlmc-estimator-smoothed)
+ *
+ * Conventions
+ *   - Every function returns an int status: CES_OK (0) or a negative
+ *     CES_ERR_* code; ces_last_error() gives a message (thread-local).
+ *   - No C++ types or exceptions cross this boundary.
+ *   - "dev" pointers are device (HBM) pointers owned by the caller;
+ *     "host" pointers are ordinary host memory owned by the caller.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  Calls that
+ *     take a stream only enqueue work unless stated otherwise.
+ *   - Contexts and plans are created and destroyed by the library.  A
+ *     context is used by one host thread at a time.  A plan is immutable
+ *     after creation and belongs to its context.
+ *   - Nodal arrays are (m+1) x (m+1) with the x index fastest
+ *     (p = i1 + (m+1) i2), the lexicographic order of Section 2.1.2.
+ *   - Determinism: sample i of a plan is a pure function of
+ *     (plan, seed, i); it does not depend on count, first_sample or
+ *     batching.
+ */
+#ifndef CESMLMC_H
+#define CESMLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CES_OK = 0,
+    CES_ERR_ARG = -1,     /* invalid argument (message says which)          */
+    CES_ERR_NOT_PSD = -2, /* no nonnegative embedding within max_pad_factor */
+    CES_ERR_NOMEM = -3,   /* device memory budget or allocation exhausted   */
+    CES_ERR_NOCONV = -4,  /* a solve hit cg_max_iter (per-sample status)    */
+    CES_ERR_DEVICE = -5,  /* HIP runtime error                              */
+    CES_ERR_BUSY = -6
+};
+
+enum { CES_COV_MATERN = 0, CES_COV_SEPEXP = 1 };
+/* SINGLE: Y = Q_f on mesh h = 1/m_fine.  PAIR: Y = Q_f - Q_c with the
+ * coarse mesh 2h, both from one field sample (Algorithm 1 step 4(e)). */
+enum { CES_LEVEL_SINGLE = 0, CES_LEVEL_PAIR = 1 };
+/* Nonnegativity policy of Algorithm 1 step 3(a)-(b).  Accept iff
+ * min Lambda >= -1e-13 max Lambda.  GROW pads J = 0, m/2, m while
+ * 2(m+J) <= max_pad_factor m; CLAMP keeps J = 0 and zeroes negatives;
+ * FAIL returns CES_ERR_NOT_PSD. */
+enum { CES_PSD_GROW = 0, CES_PSD_CLAMP = 1, CES_PSD_FAIL = 2 };
+/* Cutoff norm of the smooth periodisation (Section 2.2): EUCLID uses the
+ * 2-norm with plateau sqrt(2) and kappa = 2 ell - sqrt(2); INF uses the
+ * max-norm with plateau 1 and kappa = 2 ell - 1. */
+enum { CES_PERIOD_EUCLID = 0, CES_PERIOD_INF = 1 };
+/* PAIR: complex xi, one DFT gives samples 2q (real part) and 2q+1
+ * (imaginary part).  HARTLEY: real xi, Z = Re v + Im v (Algorithm 1
+ * step 4(d)), one DFT per sample. */
+enum { CES_FIELD_PAIR = 0, CES_FIELD_HARTLEY = 1 };
+/* FP64: field and multigrid in double.  MIXED: field and multigrid in
+ * float, conjugate-gradient iterates, residual and QoI in double. */
+enum { CES_PREC_FP64 = 0, CES_PREC_MIXED = 1 };
+/* DIRICHLET0: u = 0 on the boundary.  FLOWCELL: u = 1 at x1 = 0, u = 0 at
+ * x1 = 1, zero flux at x2 = 0 and x2 = 1 (Section 3.1). */
+enum { CES_BC_DIRICHLET0 = 0, CES_BC_FLOWCELL = 1 };
+/* QoIs of Sections 3.1 and 4 on the P1 solution: integral of u,
+ * u(qoi_x, qoi_y), L2 norm, outward flux through x1 = 1. */
+enum { CES_QOI_INTEGRAL = 0, CES_QOI_POINT = 1, CES_QOI_L2 = 2, CES_QOI_OUTFLUX = 3 };
+
+typedef struct ces_context_s* ces_context;
+typedef struct ces_plan_s* ces_plan;
+
+/* One level of the estimator (problem statement of Sections 2.1, 3.1 and
+ * 3.5).  Initialise with ces_level_desc_default(). */
+typedef struct {
+    int32_t struct_size;   /* sizeof(ces_level_desc) */
+    int32_t cov_kind;      /* CES_COV_* */
+    double nu;             /* Matern smoothness nu > 0 (ignored for SEPEXP) */
+    double lambda;         /* length scale lambda > 0 */
+    double sigma2;         /* marginal variance sigma^2 > 0 */
+    int32_t m_fine;        /* intervals per side, h = 1/m_fine; power of two, 4..4096 */
+    int32_t level_kind;    /* CES_LEVEL_*; PAIR needs m_fine >= 8 */
+    int64_t tau_fine;      /* eigenvalues dropped for the fine-mesh field; -1 = n (sqrt(s)) */
+    int64_t tau_coarse;    /* eigenvalues dropped for the coarse-mesh field; -1 = n */
+    int32_t psd_policy;    /* CES_PSD_* */
+    int32_t periodization; /* CES_PERIOD_* */
+    int32_t max_pad_factor;/* cap on n / m_fine for GROW (2..4) */
+    int32_t field_mode;    /* CES_FIELD_* */
+    int32_t precision;     /* CES_PREC_* */
+    int32_t bc;            /* CES_BC_* */
+    int32_t qoi;           /* CES_QOI_* */
+    double qoi_x, qoi_y;   /* point of CES_QOI_POINT */
+    double f_value;        /* constant source term f */
+    double cg_rtol;        /* stop when ||r||_2 <= cg_rtol ||r_0||_2 */
+    int32_t cg_max_iter;   /* iteration cap per solve */
+    uint32_t stream;       /* level tag: fourth Philox counter word */
+} ces_level_desc;
+
+typedef struct {
+    int32_t n;             /* embedding size per axis, n = 2(m + J) */
+    int32_t J;             /* padding */
+    double lam_min;        /* min / max eigenvalue before clamping */
+    double lam_max;
+    int64_t n_clamped;     /* eigenvalues set to zero by the policy */
+    int64_t tau_fine;      /* resolved drop counts */
+    int64_t tau_coarse;
+    double boundary_gap;   /* relative gap between the last kept and the first
+                              dropped eigenvalue of the coarse mask (0 if tie) */
+    int32_t mg_levels;     /* multigrid levels of the fine solve */
+    int32_t reserved;
+    size_t bytes_per_sample; /* device workspace per in-flight sample */
+} ces_plan_info;
+
+/* Fill *d with defaults: Matern nu=1/2, lambda=0.1, sigma2=1, m=32, SINGLE,
+ * tau 0/0, GROW, EUCLID, pad 4, PAIR field, MIXED, DIRICHLET0, INTEGRAL at
+ * (7/15, 7/15), f=1, rtol 1e-10, 500 iterations, stream 0. */
+void ces_level_desc_default(ces_level_desc* d);
+
+/* Bind to HIP device `device`.  mem_budget_bytes caps the library's own
+ * workspace (0 = 90% of free device memory). */
+int ces_context_create(int device, size_t mem_budget_bytes, ces_context* out);
+int ces_context_destroy(ces_context ctx);
+
+/* Algorithm 1 steps 1-3 (+ Algorithm 2 masks): covariance column, FP64 2-D
+ * DFT on the device, nonnegativity policy, orbit symmetrisation, masks,
+ * amplitudes sqrt(Lambda)/n.  Synchronous.  CES_ERR_NOT_PSD possible. */
+int ces_plan_create(ces_context ctx, const ces_level_desc* desc, ces_plan* out);
+int ces_plan_info_get(ces_plan plan, ces_plan_info* info);
+int ces_plan_destroy(ces_plan plan);
+
+/* Level samples i = first_sample .. first_sample+count-1 (Algorithm 1
+ * step 4 per sample, Section 3.4 difference).  y_dev[t] = Y of sample
+ * first_sample+t.  q_fine_dev, q_coarse_dev (Q_f, Q_c; Q_c = 0 for SINGLE),
+ * iters_dev (CG iterations of the fine solve) and status_dev (0, or
+ * CES_ERR_NOCONV if either solve hit cg_max_iter) may be NULL.
+ * Asynchronous on hip_stream; the call returns once the work is enqueued
+ * except for a bounded number of convergence polls. */
+int ces_sample(ces_plan plan, uint64_t seed, uint64_t first_sample, int64_t count,
+               double* y_dev, double* q_fine_dev, double* q_coarse_dev,
+               int32_t* iters_dev, int32_t* status_dev, void* hip_stream);
+
+/* ---- parity hooks (same kernels as ces_sample) ------------------------ */
+
+/* Box-Muller normals of Philox counter (e, q mod 2^32, q >> 32, stream),
+ * key = seed, for e = first_e .. first_e+count-1: out_dev[2t] = g0,
+ * out_dev[2t+1] = g1. */
+int ces_normals(uint64_t seed, uint64_t q, uint32_t stream, uint64_t first_e, int64_t count,
+                double* out_dev, void* hip_stream);
+
+/* Symmetrised eigenvalues (n*n doubles, after clamping) into host memory. */
+int ces_plan_eigenvalues(ces_plan plan, double* host_out);
+
+/* Masks (n*n bytes, 1 = kept) of the fine and coarse fields; either may be
+ * NULL. */
+int ces_plan_mask(ces_plan plan, uint8_t* host_fine, uint8_t* host_coarse);
+
+/* Gaussian fields Z (before exp) of sample `sample`: z_fine_dev gets
+ * (m+1)^2 doubles, z_coarse_dev (m/2+1)^2 doubles (PAIR plans; may be NULL). */
+int ces_field(ces_plan plan, uint64_t seed, uint64_t sample, double* z_fine_dev,
+              double* z_coarse_dev, void* hip_stream);
+
+/* Solve -div(k grad u) = f with the plan's boundary condition on the fine
+ * (grid = 0, m = m_fine) or coarse (grid = 1, m = m_fine/2) mesh for
+ * `count` coefficient arrays k_dev (count x (m+1)^2 doubles, k > 0).
+ * u_dev receives count x (m+1)^2 doubles (boundary values included);
+ * iters_dev (may be NULL) the CG iterations, negative if not converged. */
+int ces_solve(ces_plan plan, int32_t grid, int64_t count, const double* k_dev, double* u_dev,
+              int32_t* iters_dev, void* hip_stream);
+
+const char* ces_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CESMLMC_H */

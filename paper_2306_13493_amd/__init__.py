@@ -1,0 +1,205 @@
+"""MI355X-native MLMC level sampler with (smoothed) circulant embedding.
+
+Python binding of libcesmlmc (include/cesmlmc.h): argument marshalling
+only.  Every step of the sampler runs in the library's HIP kernels; torch
+provides device buffers and streams.
+
+    import paper_2306_13493_amd as ces
+    ctx = ces.Context(0)
+    plan = ctx.plan(cov="matern", nu=1.0, lam=0.1, m=256, precision="mixed")
+    out = plan.sample(seed=0, first=0, count=4096)   # torch tensors on cuda
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import CesError, LevelDesc, PlanInfo, check, load
+
+COV = {"matern": 0, "sepexp": 1}
+LEVEL = {"single": 0, "pair": 1}
+PSD = {"grow": 0, "clamp": 1, "fail": 2}
+PERIOD = {"euclid": 0, "inf": 1}
+FIELD = {"pair": 0, "hartley": 1}
+PREC = {"fp64": 0, "mixed": 1}
+BC = {"dirichlet0": 0, "flowcell": 1}
+QOI = {"integral": 0, "point": 1, "l2": 2, "outflux": 3}
+
+
+def _enum(table, v):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+def level_desc(cov="matern", nu=0.5, lam=0.1, sigma2=1.0, m=32, level="single", tau_fine=0,
+               tau_coarse=0, psd="grow", period="euclid", max_pad=4, field="pair", precision="mixed",
+               bc="dirichlet0", qoi="integral", qoi_x=7.0 / 15.0, qoi_y=7.0 / 15.0, f=1.0, cg_rtol=1e-10,
+               cg_max_iter=500, stream=0):
+    """Build a ces_level_desc (library defaults, then the given fields)."""
+    lib = load()
+    d = LevelDesc()
+    lib.ces_level_desc_default(ctypes.byref(d))
+    d.cov_kind = _enum(COV, cov)
+    d.nu = float(nu)
+    d.lambda_ = float(lam)
+    d.sigma2 = float(sigma2)
+    d.m_fine = int(m)
+    d.level_kind = _enum(LEVEL, level)
+    d.tau_fine = int(tau_fine)
+    d.tau_coarse = int(tau_coarse)
+    d.psd_policy = _enum(PSD, psd)
+    d.periodization = _enum(PERIOD, period)
+    d.max_pad_factor = int(max_pad)
+    d.field_mode = _enum(FIELD, field)
+    d.precision = _enum(PREC, precision)
+    d.bc = _enum(BC, bc)
+    d.qoi = _enum(QOI, qoi)
+    d.qoi_x = float(qoi_x)
+    d.qoi_y = float(qoi_y)
+    d.f_value = float(f)
+    d.cg_rtol = float(cg_rtol)
+    d.cg_max_iter = int(cg_max_iter)
+    d.stream = int(stream)
+    return d
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A device binding (ces_context)."""
+
+    def __init__(self, device=0, mem_budget=0):
+        self.lib = load()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        check(self.lib.ces_context_create(self.device, int(mem_budget), ctypes.byref(h)))
+        self.handle = h
+
+    def plan(self, desc=None, **kw):
+        return Plan(self, desc if desc is not None else level_desc(**kw))
+
+    def close(self):
+        if self.handle:
+            self.lib.ces_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """An immutable level plan (ces_plan): embedding, eigenvalues, masks."""
+
+    def __init__(self, ctx, desc):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.desc = desc
+        h = ctypes.c_void_p()
+        check(self.lib.ces_plan_create(ctx.handle, ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        info = PlanInfo()
+        check(self.lib.ces_plan_info_get(h, ctypes.byref(info)))
+        self.info = info
+
+    @property
+    def n(self):
+        return self.info.n
+
+    @property
+    def m(self):
+        return self.desc.m_fine
+
+    def sample(self, seed, first, count, stream=None, out=None):
+        """Y, Q_f, Q_c, iterations and status of samples first..first+count-1
+        as device tensors (dict)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.ctx.device)
+        if out is None:
+            out = {
+                "y": torch.empty(count, dtype=torch.float64, device=dev),
+                "q_fine": torch.empty(count, dtype=torch.float64, device=dev),
+                "q_coarse": torch.empty(count, dtype=torch.float64, device=dev),
+                "iters": torch.empty(count, dtype=torch.int32, device=dev),
+                "status": torch.empty(count, dtype=torch.int32, device=dev),
+            }
+        check(self.lib.ces_sample(self.handle, int(seed), int(first), int(count), _ptr(out["y"]),
+                                  _ptr(out.get("q_fine")), _ptr(out.get("q_coarse")), _ptr(out.get("iters")),
+                                  _ptr(out.get("status")), _stream_ptr(stream)))
+        return out
+
+    def eigenvalues(self):
+        n = self.n
+        a = np.empty((n, n), dtype=np.float64)
+        check(self.lib.ces_plan_eigenvalues(self.handle, a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
+    def masks(self):
+        n = self.n
+        f = np.empty((n, n), dtype=np.uint8)
+        c = np.empty((n, n), dtype=np.uint8)
+        check(self.lib.ces_plan_mask(self.handle, f.ctypes.data_as(ctypes.c_void_p),
+                                     c.ctypes.data_as(ctypes.c_void_p)))
+        return f, c
+
+    def field(self, seed, sample, stream=None):
+        """(Z_fine, Z_coarse or None) of one sample as float64 device tensors."""
+        torch = _torch()
+        dev = torch.device("cuda", self.ctx.device)
+        m = self.m
+        zf = torch.empty((m + 1, m + 1), dtype=torch.float64, device=dev)
+        zc = None
+        if self.desc.level_kind == LEVEL["pair"]:
+            zc = torch.empty((m // 2 + 1, m // 2 + 1), dtype=torch.float64, device=dev)
+        check(self.lib.ces_field(self.handle, int(seed), int(sample), _ptr(zf), _ptr(zc), _stream_ptr(stream)))
+        return zf, zc
+
+    def solve(self, k, grid=0, stream=None):
+        """Solve for float64 device coefficients k of shape (count, m+1, m+1)."""
+        torch = _torch()
+        k = k.contiguous()
+        count = k.shape[0]
+        u = torch.empty_like(k)
+        iters = torch.empty(count, dtype=torch.int32, device=k.device)
+        check(self.lib.ces_solve(self.handle, int(grid), int(count), _ptr(k), _ptr(u), _ptr(iters),
+                                 _stream_ptr(stream)))
+        return u, iters
+
+    def close(self):
+        if self.handle:
+            self.lib.ces_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def normals(seed, q, stream_tag, first_e, count, device=0, stream=None):
+    """(count, 2) float64 device tensor of Box-Muller pairs (parity hook)."""
+    torch = _torch()
+    lib = load()
+    out = torch.empty((count, 2), dtype=torch.float64, device=torch.device("cuda", device))
+    check(lib.ces_normals(int(seed), int(q), int(stream_tag), int(first_e), int(count), _ptr(out),
+                          _stream_ptr(stream)))
+    return out
+
+
+__all__ = ["Context", "Plan", "level_desc", "normals", "CesError", "LevelDesc", "PlanInfo", "load"]

@@ -1,0 +1,63 @@
+// Shared device/host helpers of the cesmlmc HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ces {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by +i
+template <typename T>
+__device__ __forceinline__ cplx<T> cmuli(cplx<T> a) { return {-a.y, a.x}; }
+
+constexpr int kBlock = 256;  // threads per workgroup of every kernel here
+
+// Deterministic block-wide sum (fixed shuffle tree within each wave64, then
+// waves in order).  `red` must hold kBlock/64 values.  All threads get it.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    T s = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_max(T v, T* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        T o = __shfl_down(v, off, 64);
+        v = o > v ? o : v;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    T s = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = red[w] > s ? red[w] : s;
+    __syncthreads();
+    return s;
+}
+
+inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace ces

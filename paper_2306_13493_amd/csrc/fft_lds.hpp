@@ -1,0 +1,123 @@
+// Workgroup-local 1-D DFTs in LDS (the transforms of Algorithm 1 steps 3
+// and 4(c), taken one axis at a time as in Section 2.1.2).
+//
+// Sign: V_p = sum_j v_j exp(+2 pi i j p / N) (the Fourier matrix of the
+// paper has a positive exponent); no normalisation.
+//
+// Mixed-radix (4, 2, 3) Stockham autosort: stage with radix R over
+// sub-length Ns takes inputs v_r = x[j + r N/R], twiddles them by
+// W_{Ns R}^{r k} (k = j mod Ns), applies the R-point DFT and writes
+// y[(j - k) R + k + r Ns].  One LDS buffer: each thread first reads all its
+// butterflies of the stage into registers, the workgroup synchronises, then
+// writes -- so L lines of N points need only L N complex words of LDS.
+// Twiddles come from a table tw[t] = exp(+2 pi i t / N) computed in double
+// on the host (rounded once to float for the float transforms).
+#pragma once
+
+#include "common.hpp"
+
+namespace ces {
+
+struct FftPlan {
+    int n;
+    int nst;
+    int rad[24];
+};
+
+inline FftPlan make_fft_plan(int n) {
+    FftPlan p{};
+    p.n = n;
+    int r = n;
+    while (r % 4 == 0 && r > 1) { p.rad[p.nst++] = 4; r /= 4; }
+    if (r % 2 == 0) { p.rad[p.nst++] = 2; r /= 2; }
+    while (r % 3 == 0) { p.rad[p.nst++] = 3; r /= 3; }
+    if (r != 1) p.nst = -1;  // unsupported size
+    return p;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cplx<T>* v) {
+    if constexpr (R == 2) {
+        const cplx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        const cplx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        const cplx<T> t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, cmuli(t3));
+        v[3] = csub(t1, cmuli(t3));
+    } else {  // R == 3, W = exp(+2 pi i / 3)
+        const T h = T(0.5);
+        const T s3 = T(0.86602540378443864676);  // sqrt(3)/2
+        const cplx<T> a = v[0];
+        const cplx<T> sum = cadd(v[1], v[2]);
+        const cplx<T> dif = csub(v[1], v[2]);
+        const cplx<T> m = {a.x - h * sum.x, a.y - h * sum.y};
+        const cplx<T> rot = {-s3 * dif.y, s3 * dif.x};  // i sqrt(3)/2 (b - c)
+        v[0] = cadd(a, sum);
+        v[1] = cadd(m, rot);
+        v[2] = csub(m, rot);
+    }
+}
+
+// One Stockham stage over `lines` lines of length n held back to back in buf.
+// MB = maximum butterflies per thread (compile time, registers).
+template <typename T, int R, int MB>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int lines, int Ns,
+                                          const cplx<T>* __restrict__ tw) {
+    const int NR = n / R;
+    const int total = NR * lines;
+    const int stride = n / (Ns * R);
+    cplx<T> v[MB][R];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const int g = threadIdx.x + b * (int)blockDim.x;
+        if (g < total) {
+            const int line = g / NR;
+            const int j = g - line * NR;
+            const cplx<T>* x = buf + line * n;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = x[j + r * NR];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const int g = threadIdx.x + b * (int)blockDim.x;
+        if (g < total) {
+            const int line = g / NR;
+            const int j = g - line * NR;
+            const int k = j % Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * stride]);
+            }
+            dft_small<T, R>(v[b]);
+            cplx<T>* y = buf + line * n + (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) y[r * Ns] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+// In-place DFT of `lines` consecutive lines of length fp.n in LDS.
+// E bounds the complex values per thread: lines * n <= E * blockDim.x.
+template <typename T, int E>
+__device__ void fft_lines(cplx<T>* buf, int lines, const FftPlan& fp, const cplx<T>* __restrict__ tw) {
+    int Ns = 1;
+    for (int s = 0; s < fp.nst; ++s) {
+        const int R = fp.rad[s];
+        if (R == 4)
+            fft_stage<T, 4, (E + 3) / 4>(buf, fp.n, lines, Ns, tw);
+        else if (R == 2)
+            fft_stage<T, 2, (E + 1) / 2>(buf, fp.n, lines, Ns, tw);
+        else
+            fft_stage<T, 3, (E + 2) / 3>(buf, fp.n, lines, Ns, tw);
+        Ns *= R;
+    }
+}
+
+}  // namespace ces

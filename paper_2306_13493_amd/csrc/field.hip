@@ -1,0 +1,286 @@
+// Field sampling kernels: Algorithm 1 step 3 (FP64 eigenvalue DFT of the
+// embedding's first column) and step 4(a)-(f) (normals, scaling by the
+// square-root eigenvalues, 2-D DFT, Hartley / pair combination,
+// restriction to the fine and coarse meshes, exponential).
+//
+// The 2-D DFT is two passes of workgroup-local 1-D DFTs (fft_lds.hpp):
+//   rows:    for each embedding row j2, transform along j1 and keep only the
+//            m+1 outputs p1 <= m that the restriction reads; store them
+//            transposed, work[p1][j2] (contiguous along j2).
+//   columns: for each kept p1, transform along j2, keep p2 <= m, combine
+//            and write exp(Z) at the mesh nodes.
+// Pruning the first pass to m+1 of n outputs cuts the intermediate and the
+// second pass to (m+1)/n ~ 1/2..1/4 of a full transform.
+#include "internal.hpp"
+#include "philox_bm.hpp"
+
+namespace ces {
+
+namespace {
+
+int lowbit(int n) { return n & (-n); }
+int pow2floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+template <typename T>
+__device__ __forceinline__ T dev_exp(T z);
+template <>
+__device__ __forceinline__ float dev_exp<float>(float z) { return expf(z); }
+template <>
+__device__ __forceinline__ double dev_exp<double>(double z) { return exp(z); }
+
+template <typename T, int E, int MODE, int NF>
+__global__ __launch_bounds__(kBlock) void k_field_rows(FieldBatch<T> b, int L) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int n = b.n;
+    const int u = blockIdx.y;
+    const uint64_t q = b.q0 + (uint64_t)u;
+    const int j2_0 = blockIdx.x * L;
+    for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
+        const int line = t / n;
+        const int j1 = t - line * n;
+        const uint32_t e = (uint32_t)j1 + (uint32_t)n * (uint32_t)(j2_0 + line);
+        double g0, g1;
+        normal_pair(b.seed, q, b.stream, e, g0, g1);
+        const double xr = g0;
+        const double xi = (MODE == MODE_PAIR) ? g1 : 0.0;
+        const double a = (double)b.af[e];
+        buf[line * n + j1] = cplx<T>{(T)(a * xr), (T)(a * xi)};
+        if constexpr (NF == 2) {
+            const double c = (double)b.ac[e];
+            buf[(L + line) * n + j1] = cplx<T>{(T)(c * xr), (T)(c * xi)};
+        }
+    }
+    __syncthreads();
+    fft_lines<T, E>(buf, NF * L, b.fp, b.tw);
+    const int mp1 = b.m + 1;
+    for (int t = threadIdx.x; t < NF * mp1 * L; t += blockDim.x) {
+        const int line = t % L;
+        const int rest = t / L;
+        const int p1 = rest % mp1;
+        const int f = rest / mp1;
+        b.work[((size_t)(f * b.units + u) * mp1 + p1) * n + j2_0 + line] = buf[(f * L + line) * n + p1];
+    }
+}
+
+template <typename T, int E, int MODE, int NF, bool ZOUT>
+__global__ __launch_bounds__(kBlock) void k_field_cols(FieldBatch<T> b, int L) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int n = b.n;
+    const int mp1 = b.m + 1;
+    const int p1_0 = blockIdx.x * L;
+    const int u = blockIdx.y;
+    const int f = blockIdx.z;
+    const int lines = min(L, mp1 - p1_0);
+    const cplx<T>* src = b.work + ((size_t)(f * b.units + u) * mp1 + p1_0) * n;
+    for (int t = threadIdx.x; t < lines * n; t += blockDim.x) buf[t] = src[t];
+    __syncthreads();
+    fft_lines<T, E>(buf, lines, b.fp, b.tw);
+    const bool fine = (f == 0);
+    const bool coarse = b.coarse && (f == NF - 1);
+    const int mc = b.m / 2, mcp1 = mc + 1;
+    for (int t = threadIdx.x; t < lines * mp1; t += blockDim.x) {
+        const int l = t % lines;
+        const int p2 = t / lines;
+        const int p1 = p1_0 + l;
+        const cplx<T> v = buf[l * n + p2];
+        const bool even = ((p1 | p2) & 1) == 0;
+        if (MODE == MODE_PAIR) {
+            const T z0 = v.x, z1 = v.y;
+            const size_t s0 = 2 * (size_t)u, s1 = s0 + 1;
+            if (fine) {
+                const size_t o = (size_t)p1 + (size_t)mp1 * p2;
+                if (ZOUT) {
+                    b.zf[s0 * mp1 * mp1 + o] = (double)z0;
+                    b.zf[s1 * mp1 * mp1 + o] = (double)z1;
+                } else {
+                    b.kf[s0 * b.kf_stride + o] = dev_exp<T>(z0);
+                    b.kf[s1 * b.kf_stride + o] = dev_exp<T>(z1);
+                }
+            }
+            if (coarse && even) {
+                const size_t o = (size_t)(p1 >> 1) + (size_t)mcp1 * (p2 >> 1);
+                if (ZOUT) {
+                    b.zc[s0 * mcp1 * mcp1 + o] = (double)z0;
+                    b.zc[s1 * mcp1 * mcp1 + o] = (double)z1;
+                } else {
+                    b.kc[s0 * b.kc_stride + o] = dev_exp<T>(z0);
+                    b.kc[s1 * b.kc_stride + o] = dev_exp<T>(z1);
+                }
+            }
+        } else {
+            const T z = v.x + v.y;
+            const size_t s0 = (size_t)u;
+            if (fine) {
+                const size_t o = (size_t)p1 + (size_t)mp1 * p2;
+                if (ZOUT) b.zf[s0 * mp1 * mp1 + o] = (double)z;
+                else b.kf[s0 * b.kf_stride + o] = dev_exp<T>(z);
+            }
+            if (coarse && even) {
+                const size_t o = (size_t)(p1 >> 1) + (size_t)mcp1 * (p2 >> 1);
+                if (ZOUT) b.zc[s0 * mcp1 * mcp1 + o] = (double)z;
+                else b.kc[s0 * b.kc_stride + o] = dev_exp<T>(z);
+            }
+        }
+    }
+}
+
+template <int E>
+__global__ __launch_bounds__(kBlock) void k_eig_rows(const double* __restrict__ s, int L, FftPlan fp,
+                                                     const cplx<double>* __restrict__ tw,
+                                                     cplx<double>* __restrict__ work) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
+    const int n = fp.n;
+    const int j2_0 = blockIdx.x * L;
+    for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
+        buf[t] = cplx<double>{s[(size_t)j2_0 * n + t], 0.0};
+    }
+    __syncthreads();
+    fft_lines<double, E>(buf, L, fp, tw);
+    for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
+        const int line = t % L;
+        const int p1 = t / L;
+        work[(size_t)p1 * n + j2_0 + line] = buf[line * n + p1];
+    }
+}
+
+template <int E>
+__global__ __launch_bounds__(kBlock) void k_eig_cols(const cplx<double>* __restrict__ work, int L, FftPlan fp,
+                                                     const cplx<double>* __restrict__ tw,
+                                                     double* __restrict__ lam, double* __restrict__ imag_blk) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double red[kBlock / 64];
+    cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
+    const int n = fp.n;
+    const int p1_0 = blockIdx.x * L;
+    for (int t = threadIdx.x; t < L * n; t += blockDim.x) buf[t] = work[(size_t)p1_0 * n + t];
+    __syncthreads();
+    fft_lines<double, E>(buf, L, fp, tw);
+    double im = 0.0;
+    for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
+        const int l = t % L;
+        const int p2 = t / L;
+        const cplx<double> v = buf[l * n + p2];
+        lam[(size_t)p2 * n + p1_0 + l] = v.x;
+        im = fmax(im, fabs(v.y));
+    }
+    im = block_max(im, red);
+    if (threadIdx.x == 0) imag_blk[blockIdx.x] = im;
+}
+
+__global__ __launch_bounds__(kBlock) void k_normals(uint64_t seed, uint64_t q, uint32_t stream,
+                                                    uint64_t first_e, long long count, double* out) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    double g0, g1;
+    normal_pair(seed, q, stream, (uint32_t)(first_e + (uint64_t)t), g0, g1);
+    out[2 * t] = g0;
+    out[2 * t + 1] = g1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_convert_d2f(const double* __restrict__ in, float* __restrict__ out,
+                                                        long long count) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) out[t] = (float)in[t];
+}
+
+template <typename KernelT>
+hipError_t allow_lds(KernelT kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T, int E, int MODE, int NF>
+hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2) {
+    const size_t lds1 = (size_t)NF * L1 * b.n * sizeof(cplx<T>);
+    const size_t lds2 = (size_t)L2 * b.n * sizeof(cplx<T>);
+    auto kr = k_field_rows<T, E, MODE, NF>;
+    hipError_t e = allow_lds(kr, lds1);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kr, dim3(b.n / L1, b.units), dim3(kBlock), lds1, st, b, L1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dim3 g2(cdiv(b.m + 1, L2), b.units, NF);
+    if (b.zf) {
+        auto kc = k_field_cols<T, E, MODE, NF, true>;
+        if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
+        hipLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, b, L2);
+    } else {
+        auto kc = k_field_cols<T, E, MODE, NF, false>;
+        if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
+        hipLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, b, L2);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int MODE, int NF>
+hipError_t field_launch_nf(const FieldBatch<T>& b, hipStream_t st) {
+    // lines per workgroup: a power of two dividing n, with NF*L*n <= 16*256
+    // values per workgroup (E = 16) when possible, else one line (E = 32).
+    const int cap = 16 * kBlock;
+    int L1 = pow2floor(std::max(1, cap / (NF * b.n)));
+    L1 = std::min(L1, lowbit(b.n));
+    int L2 = pow2floor(std::max(1, cap / b.n));
+    if (NF * L1 * b.n <= cap && L2 * b.n <= cap) return field_launch_e<T, 16, MODE, NF>(b, st, L1, L2);
+    if (NF * b.n <= 2 * cap) return field_launch_e<T, 32, MODE, NF>(b, st, 1, 1);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_field(const FieldBatch<T>& b, hipStream_t st) {
+    if (b.units <= 0) return hipSuccess;
+    if (b.mode == MODE_PAIR)
+        return b.nf == 2 ? field_launch_nf<T, MODE_PAIR, 2>(b, st) : field_launch_nf<T, MODE_PAIR, 1>(b, st);
+    return b.nf == 2 ? field_launch_nf<T, MODE_HARTLEY, 2>(b, st) : field_launch_nf<T, MODE_HARTLEY, 1>(b, st);
+}
+template hipError_t launch_field<float>(const FieldBatch<float>&, hipStream_t);
+template hipError_t launch_field<double>(const FieldBatch<double>&, hipStream_t);
+
+hipError_t launch_eigen_fft(const double* s, int n, const FftPlan& fp, const cplx<double>* tw,
+                            cplx<double>* work, double* lam, double* imag_blk, int* nblk, hipStream_t st) {
+    const int cap = 16 * kBlock;
+    int L = std::min(pow2floor(std::max(1, cap / n)), lowbit(n));
+    hipError_t e;
+    if (L * n <= cap) {
+        const size_t lds = (size_t)L * n * sizeof(cplx<double>);
+        if ((e = allow_lds(k_eig_rows<16>, lds)) != hipSuccess) return e;
+        if ((e = allow_lds(k_eig_cols<16>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_eig_rows<16>, dim3(n / L), dim3(kBlock), lds, st, s, L, fp, tw, work);
+        hipLaunchKernelGGL(k_eig_cols<16>, dim3(n / L), dim3(kBlock), lds, st, work, L, fp, tw, lam, imag_blk);
+    } else if (n <= 2 * cap) {
+        L = 1;
+        const size_t lds = (size_t)n * sizeof(cplx<double>);
+        if ((e = allow_lds(k_eig_rows<32>, lds)) != hipSuccess) return e;
+        if ((e = allow_lds(k_eig_cols<32>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_eig_rows<32>, dim3(n), dim3(kBlock), lds, st, s, 1, fp, tw, work);
+        hipLaunchKernelGGL(k_eig_cols<32>, dim3(n), dim3(kBlock), lds, st, work, 1, fp, tw, lam, imag_blk);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    *nblk = n / L;
+    return hipGetLastError();
+}
+
+hipError_t launch_normals(uint64_t seed, uint64_t q, uint32_t stream, uint64_t first_e, long long count,
+                          double* out, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_normals, dim3(cdiv(count, kBlock)), dim3(kBlock), 0, st, seed, q, stream, first_e,
+                       count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_d2f(const double* in, float* out, long long count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_convert_d2f, dim3(cdiv(count, kBlock)), dim3(kBlock), 0, st, in, out, count);
+    return hipGetLastError();
+}
+
+}  // namespace ces

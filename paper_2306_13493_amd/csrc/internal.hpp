@@ -1,0 +1,96 @@
+// Host-side interfaces between the translation units of the library.
+#pragma once
+
+#include <memory>
+#include <string>
+
+#include "common.hpp"
+#include "fft_lds.hpp"
+
+namespace ces {
+
+enum { MODE_PAIR = 0, MODE_HARTLEY = 1 };
+enum { BC_DIRICHLET0 = 0, BC_FLOWCELL = 1 };
+enum { Q_INTEGRAL = 0, Q_POINT = 1, Q_L2 = 2, Q_OUTFLUX = 3 };
+
+// ---------------------------------------------------------------- field --
+// One batch of DFT units (pairs in PAIR mode, samples in HARTLEY mode):
+// xi from Philox/Box-Muller, w = a (.) xi, 2-D DFT pruned to the first m+1
+// outputs per axis, Z restricted to the fine nodes and to the even (coarse)
+// nodes, k = exp(Z).
+template <typename T>
+struct FieldBatch {
+    int n = 0, m = 0;
+    int mode = MODE_PAIR;
+    int nf = 1;              // DFTs per unit: 1, or 2 when fine/coarse masks differ
+    bool coarse = false;     // also write the coarse-mesh field
+    const T* af = nullptr;   // amplitudes sqrt(Lambda)/n (fine mask), n*n
+    const T* ac = nullptr;   // amplitudes of the coarse mask (nf == 2)
+    const cplx<T>* tw = nullptr;
+    FftPlan fp{};
+    uint64_t seed = 0;
+    uint64_t q0 = 0;         // first unit index of the batch
+    uint32_t stream = 0;
+    int units = 0;           // units in this batch
+    cplx<T>* work = nullptr; // nf * units * (m+1) * n
+    // outputs per slot (slot = 2u + c in PAIR mode, u in HARTLEY mode)
+    T* kf = nullptr; long long kf_stride = 0;   // exp(Z) on (m+1)^2 nodes
+    T* kc = nullptr; long long kc_stride = 0;   // exp(Z) on (m/2+1)^2 nodes
+    double* zf = nullptr;    // if set: Z (not exp) as double, stride (m+1)^2
+    double* zc = nullptr;    // if set: Z coarse as double, stride (m/2+1)^2
+};
+template <typename T>
+hipError_t launch_field(const FieldBatch<T>& b, hipStream_t st);
+
+// FP64 2-D DFT (+ sign) of a real n x n array s (Algorithm 1 step 3):
+// lam = Re(DFT s), imag_blk[blk] = per-block max |Im|.  work: n*n complex.
+hipError_t launch_eigen_fft(const double* s, int n, const FftPlan& fp, const cplx<double>* tw,
+                            cplx<double>* work, double* lam, double* imag_blk, int* nblk,
+                            hipStream_t st);
+
+hipError_t launch_normals(uint64_t seed, uint64_t q, uint32_t stream, uint64_t first_e,
+                          long long count, double* out, hipStream_t st);
+
+hipError_t launch_convert_d2f(const double* in, float* out, long long count, hipStream_t st);
+
+// --------------------------------------------------------------- solver --
+struct SolverCfg {
+    int m = 0;          // intervals per side of the mesh
+    int bc = BC_DIRICHLET0;
+    double f = 1.0;
+    double rtol = 1e-10;
+    int maxit = 500;
+    int qoi = Q_INTEGRAL;
+    double qx = 7.0 / 15.0, qy = 7.0 / 15.0;
+};
+
+// Batched PCG (double) preconditioned by a geometric multigrid V(2,2) cycle
+// in T, for S samples of one mesh at a time.
+class Solver {
+public:
+    virtual ~Solver() = default;
+    virtual int capacity() const = 0;
+    virtual size_t bytes() const = 0;
+    virtual int mg_levels() const = 0;
+    // k: capacity x kstride values of T (slot s at k + s*kstride).
+    // Runs to convergence for slots [0, S).  Polls the device a bounded
+    // number of times.  Returns hipSuccess or the first HIP error.
+    virtual hipError_t solve(const void* k, long long kstride, int S, hipStream_t st) = 0;
+    // QoI of the last solve for slots [0, S): q[s], iters[s] (-it if not
+    // converged); either may be null.
+    virtual hipError_t qoi(const void* k, long long kstride, int S, double* q, int* iters,
+                           hipStream_t st) = 0;
+    // Nodal solution (double, (m+1)^2 per slot, dense).
+    virtual const double* x() const = 0;
+    virtual long long xstride() const = 0;
+};
+// is_double selects T = double (plain path) or float (mixed path).
+std::unique_ptr<Solver> make_solver(const SolverCfg& cfg, int capacity, bool is_double,
+                                    std::string* err);
+
+// y[i] = qf[i] - qc[i] (or qf if qc null) scattered to out slots.
+hipError_t launch_finalize(const double* qf, const double* qc, const int* itf, const int* itc,
+                           int slot0, int nslots, long long out0, double* y, double* yf, double* yc,
+                           int* iters, int* status, hipStream_t st);
+
+}  // namespace ces

@@ -1,0 +1,1113 @@
+// Batched solver for -div(k grad u) = f on the unit square (Section 3.1),
+// P1 elements on the right-diagonal mesh with nodal (trapezoidal)
+// quadrature of k (Section 3.2).  With that quadrature the stiffness
+// matrix couples only axis-neighbours (the diagonal couplings cancel), so
+// A is a 5-point operator with edge conductances
+//   c_E(i,j) = [T above] (k_ij + k_i+1,j + k_i+1,j+1)/6 + [T below] (k_i,j-1 + k_i+1,j + k_ij)/6
+//   c_N(i,j) = [T right] (k_ij + k_i+1,j+1 + k_i,j+1)/6 + [T left] (k_i-1,j + k_ij + k_i,j+1)/6
+// ([T ...] = the adjacent triangle exists), (A u)_p = sum_q c_pq (u_p - u_q)
+// and load b_p = f (#triangles at p) h^2/6.
+//
+// Method: conjugate gradients in double, preconditioned by one geometric
+// multigrid V(2,2) cycle in T (float on the mixed path, double on the
+// plain path): red-black Gauss-Seidel (red, black, red, black before the
+// coarse correction, the reverse after, so the preconditioner is
+// symmetric), restriction = transpose of bilinear prolongation, coarse
+// operators rediscretised from the geometric mean of k over the
+// full-weighting stencil, exact solve on the 2 x 2 mesh.
+//
+// Work layout: one launch handles a whole batch of samples (blockIdx.y =
+// sample); fine levels are tiled (64 x 16 or 64 x 8 nodes per workgroup)
+// and the four half-sweeps of a smoothing step run in LDS on the tile plus
+// a 4-node halo (temporal blocking: one HBM read of z, rhs and k and one
+// write of z per smoothing step); all levels with m <= 32 (16 in double)
+// run in one workgroup per sample entirely in LDS.  Dot products are
+// per-tile partial sums reduced in a fixed order, so every result is
+// independent of the batch composition.  Converged samples switch their
+// workgroups off (per-sample active flag).
+#include <vector>
+
+#include "internal.hpp"
+
+namespace ces {
+
+namespace {
+
+struct Scal {
+    double bb, rz, rz_old, pq, rr, zq;
+    int it, active, status, pad;
+};
+
+struct Lvl {
+    int m, w;
+    long long ss;   // per-sample stride of this level's arrays
+    int ylo, yhi;   // unknown rows (columns are always 1 .. m-1)
+};
+
+__device__ __forceinline__ bool is_unknown(int gx, int gy, int m, int bc) {
+    return gx >= 1 && gx <= m - 1 && (bc == BC_FLOWCELL ? (gy >= 0 && gy <= m) : (gy >= 1 && gy <= m - 1));
+}
+
+// Dirichlet data of the flow cell: u = 1 on x1 = 0, 0 elsewhere.
+__device__ __forceinline__ double dirichlet_value(int gx, int bc) {
+    return (bc == BC_FLOWCELL && gx == 0) ? 1.0 : 0.0;
+}
+
+template <typename T, typename KF>
+__device__ __forceinline__ T cond_e(int gx, int gy, int m, const KF& K) {
+    if (gx < 0 || gx >= m || gy < 0 || gy > m) return T(0);
+    const T up = (gy < m) ? K(gx, gy) + K(gx + 1, gy) + K(gx + 1, gy + 1) : T(0);
+    const T dn = (gy > 0) ? K(gx, gy - 1) + K(gx + 1, gy) + K(gx, gy) : T(0);
+    return (up + dn) * T(1.0 / 6.0);
+}
+template <typename T, typename KF>
+__device__ __forceinline__ T cond_n(int gx, int gy, int m, const KF& K) {
+    if (gx < 0 || gx > m || gy < 0 || gy >= m) return T(0);
+    const T rt = (gx < m) ? K(gx, gy) + K(gx + 1, gy + 1) + K(gx, gy + 1) : T(0);
+    const T lf = (gx > 0) ? K(gx - 1, gy) + K(gx, gy) + K(gx, gy + 1) : T(0);
+    return (rt + lf) * T(1.0 / 6.0);
+}
+
+// number of triangles touching vertex (i, j) (load weight = cnt h^2 / 6)
+__device__ __forceinline__ int tri_count(int i, int j, int m) {
+    int c = 0;
+    if (i < m && j < m) c += 2;
+    if (i >= 1 && j < m) c += 1;
+    if (i >= 1 && j >= 1) c += 2;
+    if (i < m && j >= 1) c += 1;
+    return c;
+}
+
+// ------------------------------------------------------------ LDS region
+// Nodes [ox, ox+RX) x [oy, oy+RY) of one sample's level, with k on a
+// one-node ring around it.
+template <typename T, int RX, int RY>
+struct Region {
+    T z[RY][RX];
+    T rhs[RY][RX];
+    T ce[RY][RX];
+    T cn[RY][RX];
+    T aux[RY][RX];  // inverse diagonal (smoothing) or residual (restriction)
+    T k[RY + 2][RX + 2];
+};
+
+template <typename T, int RX, int RY>
+struct RegionK {
+    const Region<T, RX, RY>& R;
+    int ox, oy;
+    __device__ T operator()(int gx, int gy) const { return R.k[gy - oy + 1][gx - ox + 1]; }
+};
+
+template <typename T, int RX, int RY>
+__device__ void region_load_k(Region<T, RX, RY>& R, const T* __restrict__ k, int ox, int oy, int m, int w) {
+    for (int t = threadIdx.x; t < (RX + 2) * (RY + 2); t += blockDim.x) {
+        const int y = t / (RX + 2), x = t - y * (RX + 2);
+        const int gx = ox - 1 + x, gy = oy - 1 + y;
+        R.k[y][x] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? k[(size_t)gy * w + gx] : T(0);
+    }
+}
+
+// conductances of every node of the region; aux = 1/diag at unknown nodes
+// that have all four neighbours inside the region (else 0).
+template <typename T, int RX, int RY>
+__device__ void region_conductances(Region<T, RX, RY>& R, int ox, int oy, int m, int bc, bool inv_diag) {
+    RegionK<T, RX, RY> K{R, ox, oy};
+    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
+        const int y = t / RX, x = t - y * RX;
+        R.ce[y][x] = cond_e<T>(ox + x, oy + y, m, K);
+        R.cn[y][x] = cond_n<T>(ox + x, oy + y, m, K);
+    }
+    __syncthreads();
+    if (inv_diag) {
+        for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
+            const int y = t / RX, x = t - y * RX;
+            T v = T(0);
+            if (x >= 1 && y >= 1 && x < RX - 1 && y < RY - 1 && is_unknown(ox + x, oy + y, m, bc)) {
+                const T d = R.ce[y][x] + R.ce[y][x - 1] + R.cn[y][x] + R.cn[y - 1][x];
+                v = T(1) / d;
+            }
+            R.aux[y][x] = v;
+        }
+    }
+}
+
+// One red-black half-sweep of colour c over [h, RX-h) x [h, RY-h).
+template <typename T, int RX, int RY>
+__device__ void region_half_sweep(Region<T, RX, RY>& R, int ox, int oy, int c, int h) {
+    const int wx = RX - 2 * h, wy = RY - 2 * h;
+    const int half = (wx + 1) / 2;
+    for (int t = threadIdx.x; t < half * wy; t += blockDim.x) {
+        const int yy = t / half;
+        const int y = h + yy;
+        const int par = (c - (ox + h) - (oy + y)) & 1;
+        const int x = h + 2 * (t - yy * half) + par;
+        if (x >= RX - h) continue;
+        const T id = R.aux[y][x];
+        if (id == T(0)) continue;
+        const T s = R.rhs[y][x] + R.ce[y][x] * R.z[y][x + 1] + R.ce[y][x - 1] * R.z[y][x - 1] +
+                    R.cn[y][x] * R.z[y + 1][x] + R.cn[y - 1][x] * R.z[y - 1][x];
+        R.z[y][x] = s * id;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ kernels ---
+template <typename T>
+struct SmoothArgs {
+    Lvl L;
+    int bc, tiles_x, ntiles;
+    const T* k;
+    long long kss;
+    const void* rhs;    // double (level 0) or T
+    T* za;              // pre-smoothed z of this level (PRE output / POST input)
+    // POST only
+    const T* zc;        // coarse correction
+    Lvl C;
+    void* zout;         // double Z (level 0) or T zb
+    double* dot;        // level-0 POST: partial r.z per tile
+    double* dot2;       // level-0 POST: partial z.q_old per tile
+    const double* q;    // level-0 POST: q_old = A p_old
+    const Scal* scal;
+};
+
+template <typename T, int TX, int TY, bool POST, bool L0>
+__global__ __launch_bounds__(kBlock) void k_smooth(SmoothArgs<T> a) {
+    constexpr int H = 4, RX = TX + 2 * H, RY = TY + 2 * H;
+    __shared__ Region<T, RX, RY> R;
+    __shared__ double red[kBlock / 64];
+    const int s = blockIdx.y;
+    if (!a.scal[s].active) return;
+    const int tile = blockIdx.x;
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int x0 = 1 + tx * TX, y0 = a.L.ylo + ty * TY;
+    const int ox = x0 - H, oy = y0 - H;
+    const int m = a.L.m, w = a.L.w;
+    region_load_k(R, a.k + (size_t)s * a.kss, ox, oy, m, w);
+    const T* rhsT = L0 ? nullptr : reinterpret_cast<const T*>(a.rhs) + (size_t)s * a.L.ss;
+    const double* rhsD = L0 ? reinterpret_cast<const double*>(a.rhs) + (size_t)s * a.L.ss : nullptr;
+    const T* zin = a.za + (size_t)s * a.L.ss;
+    const T* zc = POST ? a.zc + (size_t)s * a.C.ss : nullptr;
+    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
+        const int y = t / RX, x = t - y * RX;
+        const int gx = ox + x, gy = oy + y;
+        T r = T(0), z = T(0);
+        if (is_unknown(gx, gy, m, a.bc)) {
+            const size_t o = (size_t)gy * w + gx;
+            r = L0 ? (T)rhsD[o] : rhsT[o];
+            if (POST) {
+                // z + P zc, bilinear prolongation from the coarse nodes
+                const int I = gx >> 1, J = gy >> 1;
+                const int cw = a.C.w, cm = a.C.m;
+                auto zcv = [&](int ci, int cj) -> T {
+                    return is_unknown(ci, cj, cm, a.bc) ? zc[(size_t)cj * cw + ci] : T(0);
+                };
+                T p;
+                const bool ox1 = gx & 1, oy1 = gy & 1;
+                if (!ox1 && !oy1) p = zcv(I, J);
+                else if (ox1 && !oy1) p = T(0.5) * (zcv(I, J) + zcv(I + 1, J));
+                else if (!ox1 && oy1) p = T(0.5) * (zcv(I, J) + zcv(I, J + 1));
+                else p = T(0.25) * ((zcv(I, J) + zcv(I + 1, J)) + (zcv(I, J + 1) + zcv(I + 1, J + 1)));
+                z = zin[o] + p;
+            }
+        }
+        R.rhs[y][x] = r;
+        R.z[y][x] = z;
+    }
+    __syncthreads();
+    region_conductances(R, ox, oy, m, a.bc, true);
+    __syncthreads();
+    const int c0 = POST ? 1 : 0;
+    region_half_sweep(R, ox, oy, c0, 1);
+    region_half_sweep(R, ox, oy, 1 - c0, 2);
+    region_half_sweep(R, ox, oy, c0, 3);
+    region_half_sweep(R, ox, oy, 1 - c0, 4);
+    double acc = 0.0, acc2 = 0.0;
+    for (int t = threadIdx.x; t < TX * TY; t += blockDim.x) {
+        const int yy = t / TX, xx = t - yy * TX;
+        const int gx = x0 + xx, gy = y0 + yy;
+        if (!is_unknown(gx, gy, m, a.bc)) continue;
+        const size_t o = (size_t)gy * w + gx;
+        const T z = R.z[yy + H][xx + H];
+        if (!POST) {
+            a.za[(size_t)s * a.L.ss + o] = z;
+        } else if (L0) {
+            reinterpret_cast<double*>(a.zout)[(size_t)s * a.L.ss + o] = (double)z;
+            acc += rhsD[o] * (double)z;
+            acc2 += a.q[(size_t)s * a.L.ss + o] * (double)z;
+        } else {
+            reinterpret_cast<T*>(a.zout)[(size_t)s * a.L.ss + o] = z;
+        }
+    }
+    if (POST && L0) {
+        acc = block_sum(acc, red);
+        acc2 = block_sum(acc2, red);
+        if (threadIdx.x == 0) {
+            a.dot[(size_t)s * a.ntiles + tile] = acc;
+            a.dot2[(size_t)s * a.ntiles + tile] = acc2;
+        }
+    }
+}
+
+template <typename T>
+struct RestrictArgs {
+    Lvl L, C;
+    int bc, tiles_x;
+    const T* k;
+    long long kss;
+    const void* rhs;   // level rhs: double (level 0) or T
+    const T* z;        // pre-smoothed z of the level
+    T* rhs_c;          // coarse rhs (output)
+    const Scal* scal;
+};
+
+// rhs_c = P^T (rhs - A z) on a CTX x CTY tile of coarse nodes.
+template <typename T, int CTX, int CTY, bool L0>
+__global__ __launch_bounds__(kBlock) void k_restrict(RestrictArgs<T> a) {
+    constexpr int RX = 2 * CTX + 3, RY = 2 * CTY + 3;
+    __shared__ Region<T, RX, RY> R;
+    const int s = blockIdx.y;
+    if (!a.scal[s].active) return;
+    const int tile = blockIdx.x;
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int cx0 = 1 + tx * CTX, cy0 = a.C.ylo + ty * CTY;
+    const int ox = 2 * cx0 - 2, oy = 2 * cy0 - 2;
+    const int m = a.L.m, w = a.L.w;
+    region_load_k(R, a.k + (size_t)s * a.kss, ox, oy, m, w);
+    const T* zin = a.z + (size_t)s * a.L.ss;
+    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
+        const int y = t / RX, x = t - y * RX;
+        const int gx = ox + x, gy = oy + y;
+        T r = T(0), z = T(0);
+        if (is_unknown(gx, gy, m, a.bc)) {
+            const size_t o = (size_t)gy * w + gx;
+            r = L0 ? (T)(reinterpret_cast<const double*>(a.rhs)[(size_t)s * a.L.ss + o])
+                   : reinterpret_cast<const T*>(a.rhs)[(size_t)s * a.L.ss + o];
+            z = zin[o];
+        }
+        R.rhs[y][x] = r;
+        R.z[y][x] = z;
+    }
+    __syncthreads();
+    region_conductances(R, ox, oy, m, a.bc, false);
+    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
+        const int y = t / RX, x = t - y * RX;
+        T res = T(0);
+        if (x >= 1 && y >= 1 && x < RX - 1 && y < RY - 1 && is_unknown(ox + x, oy + y, m, a.bc)) {
+            const T zp = R.z[y][x];
+            const T az = (R.ce[y][x] * (zp - R.z[y][x + 1]) + R.ce[y][x - 1] * (zp - R.z[y][x - 1])) +
+                         (R.cn[y][x] * (zp - R.z[y + 1][x]) + R.cn[y - 1][x] * (zp - R.z[y - 1][x]));
+            res = R.rhs[y][x] - az;
+        }
+        R.aux[y][x] = res;
+    }
+    __syncthreads();
+    const int cm = a.C.m, cw = a.C.w;
+    for (int t = threadIdx.x; t < CTX * CTY; t += blockDim.x) {
+        const int b = t / CTX, aa = t - b * CTX;
+        const int I = cx0 + aa, J = cy0 + b;
+        if (!is_unknown(I, J, cm, a.bc)) continue;
+        const int x = 2 * aa + 2, y = 2 * b + 2;
+        const T v = R.aux[y][x] +
+                    T(0.5) * ((R.aux[y][x - 1] + R.aux[y][x + 1]) + (R.aux[y - 1][x] + R.aux[y + 1][x])) +
+                    T(0.25) * ((R.aux[y - 1][x - 1] + R.aux[y - 1][x + 1]) + (R.aux[y + 1][x - 1] + R.aux[y + 1][x + 1]));
+        a.rhs_c[(size_t)s * a.C.ss + (size_t)J * cw + I] = v;
+    }
+}
+
+// ------------------------------------------------ whole-V-cycle bottom ---
+template <typename T>
+struct BottomArgs {
+    int nl;            // levels handled here: m0, m0/2, ..., 2
+    int bc;
+    Lvl L[8];
+    const T* k[8];     // k of each level
+    long long kss[8];
+    const void* rhs;   // level-0-of-bottom rhs: double (global level 0) or T
+    void* zout;        // double Z (global level 0) or T zb
+    double* dot;       // global level 0: partial r.z (1 per sample)
+    double* dot2;      // global level 0: partial z.q_old
+    const double* q;   // global level 0: q_old
+    const Scal* scal;
+};
+
+template <int MB>
+struct BottomSize {
+    static constexpr int tot() {
+        int t = 0;
+        for (int mm = MB; mm >= 2; mm /= 2) t += (mm + 1) * (mm + 1);
+        return t;
+    }
+};
+
+template <typename T, int MB>
+__device__ void bottom_sweep(T* z, const T* rhs, const T* ce, const T* cn, const T* id, int m, int c) {
+    const int w = m + 1;
+    const int half = (w + 1) / 2;
+    for (int t = threadIdx.x; t < half * w; t += blockDim.x) {
+        const int y = t / half;
+        const int x = 2 * (t - y * half) + ((c - y) & 1);
+        if (x >= w) continue;
+        const int p = y * w + x;
+        const T d = id[p];
+        if (d == T(0)) continue;
+        T s = rhs[p];
+        if (x + 1 < w) s += ce[p] * z[p + 1];
+        if (x >= 1) s += ce[p - 1] * z[p - 1];
+        if (y + 1 < w) s += cn[p] * z[p + w];
+        if (y >= 1) s += cn[p - w] * z[p - w];
+        z[p] = s * d;
+    }
+    __syncthreads();
+}
+
+template <typename T, int MB, bool L0>
+__global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
+    constexpr int TOT = BottomSize<MB>::tot();
+    __shared__ T z[TOT], rhs[TOT], ce[TOT], cn[TOT], id[TOT];
+    __shared__ T tmp[(MB + 1) * (MB + 1)];
+    __shared__ double red[kBlock / 64];
+    const int s = blockIdx.x;
+    if (!a.scal[s].active) return;
+    int off[8];
+    {
+        int o = 0;
+        for (int l = 0; l < a.nl; ++l) {
+            off[l] = o;
+            o += a.L[l].w * a.L[l].w;
+        }
+    }
+    // conductances and inverse diagonals of every level
+    for (int l = 0; l < a.nl; ++l) {
+        const int m = a.L[l].m, w = a.L[l].w;
+        const T* kg = a.k[l] + (size_t)s * a.kss[l];
+        for (int t = threadIdx.x; t < w * w; t += blockDim.x) tmp[t] = kg[t];
+        __syncthreads();
+        auto K = [&](int gx, int gy) -> T { return tmp[gy * w + gx]; };
+        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+            const int y = t / w, x = t - y * w;
+            ce[off[l] + t] = cond_e<T>(x, y, m, K);
+            cn[off[l] + t] = cond_n<T>(x, y, m, K);
+            z[off[l] + t] = T(0);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+            const int y = t / w, x = t - y * w;
+            T v = T(0);
+            if (is_unknown(x, y, m, a.bc)) {
+                const int p = off[l] + t;
+                v = T(1) / (ce[p] + ce[p - 1] + cn[p] + (y >= 1 ? cn[p - w] : T(0)));
+            }
+            id[off[l] + t] = v;
+        }
+        __syncthreads();
+    }
+    {
+        const int m = a.L[0].m, w = a.L[0].w;
+        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+            const int y = t / w, x = t - y * w;
+            T r = T(0);
+            if (is_unknown(x, y, m, a.bc)) {
+                r = L0 ? (T)(reinterpret_cast<const double*>(a.rhs)[(size_t)s * a.L[0].ss + t])
+                       : reinterpret_cast<const T*>(a.rhs)[(size_t)s * a.L[0].ss + t];
+            }
+            rhs[t] = r;
+        }
+        __syncthreads();
+    }
+    // down
+    for (int l = 0; l + 1 < a.nl; ++l) {
+        const int m = a.L[l].m, w = a.L[l].w, o = off[l];
+        for (int c = 0; c < 4; ++c) bottom_sweep<T, MB>(z + o, rhs + o, ce + o, cn + o, id + o, m, c & 1);
+        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+            const int y = t / w, x = t - y * w;
+            T r = T(0);
+            if (is_unknown(x, y, m, a.bc)) {
+                const int p = o + t;
+                const T zp = z[p];
+                const T zN = y + 1 < w ? z[p + w] : T(0), zS = y >= 1 ? z[p - w] : T(0);
+                const T cS = y >= 1 ? cn[p - w] : T(0);
+                const T az = (ce[p] * (zp - z[p + 1]) + ce[p - 1] * (zp - z[p - 1])) +
+                             (cn[p] * (zp - zN) + cS * (zp - zS));
+                r = rhs[p] - az;
+            }
+            tmp[t] = r;
+        }
+        __syncthreads();
+        const int cm = a.L[l + 1].m, cwid = a.L[l + 1].w, co = off[l + 1];
+        for (int t = threadIdx.x; t < cwid * cwid; t += blockDim.x) {
+            const int J = t / cwid, I = t - J * cwid;
+            T v = T(0);
+            if (is_unknown(I, J, cm, a.bc)) {
+                const int x = 2 * I, y = 2 * J;
+                auto R = [&](int xx, int yy) -> T {
+                    return (xx >= 0 && xx < w && yy >= 0 && yy < w) ? tmp[yy * w + xx] : T(0);
+                };
+                v = R(x, y) + T(0.5) * ((R(x - 1, y) + R(x + 1, y)) + (R(x, y - 1) + R(x, y + 1))) +
+                    T(0.25) * ((R(x - 1, y - 1) + R(x + 1, y - 1)) + (R(x - 1, y + 1) + R(x + 1, y + 1)));
+            }
+            rhs[co + t] = v;
+        }
+        __syncthreads();
+    }
+    // coarsest (m = 2): exact tridiagonal solve along the unknown column x = 1
+    if (threadIdx.x == 0) {
+        const int l = a.nl - 1, w = a.L[l].w, o = off[l];
+        const int ylo = a.L[l].ylo, yhi = a.L[l].yhi;
+        T beta[3], yv[3];
+        for (int j = ylo; j <= yhi; ++j) {
+            const int p = o + j * w + 1;
+            const T d = T(1) / id[p];
+            if (j == ylo) {
+                beta[j] = d;
+                yv[j] = rhs[p];
+            } else {
+                const T cS = cn[p - w];
+                beta[j] = d - cS * cS / beta[j - 1];
+                yv[j] = rhs[p] + cS * yv[j - 1] / beta[j - 1];
+            }
+        }
+        T zn = T(0);
+        for (int j = yhi; j >= ylo; --j) {
+            const int p = o + j * w + 1;
+            const T cN = (j < yhi) ? cn[p] : T(0);
+            const T v = (yv[j] + cN * zn) / beta[j];
+            z[p] = v;
+            zn = v;
+        }
+    }
+    __syncthreads();
+    // up
+    for (int l = a.nl - 2; l >= 0; --l) {
+        const int m = a.L[l].m, w = a.L[l].w, o = off[l];
+        const int cm = a.L[l + 1].m, cwid = a.L[l + 1].w, co = off[l + 1];
+        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+            const int y = t / w, x = t - y * w;
+            if (!is_unknown(x, y, m, a.bc)) continue;
+            const int I = x >> 1, J = y >> 1;
+            auto C = [&](int ci, int cj) -> T {
+                return is_unknown(ci, cj, cm, a.bc) ? z[co + cj * cwid + ci] : T(0);
+            };
+            T p;
+            const bool ox1 = x & 1, oy1 = y & 1;
+            if (!ox1 && !oy1) p = C(I, J);
+            else if (ox1 && !oy1) p = T(0.5) * (C(I, J) + C(I + 1, J));
+            else if (!ox1 && oy1) p = T(0.5) * (C(I, J) + C(I, J + 1));
+            else p = T(0.25) * ((C(I, J) + C(I + 1, J)) + (C(I, J + 1) + C(I + 1, J + 1)));
+            z[o + t] += p;
+        }
+        __syncthreads();
+        for (int c = 0; c < 4; ++c) bottom_sweep<T, MB>(z + o, rhs + o, ce + o, cn + o, id + o, m, 1 - (c & 1));
+    }
+    // write
+    const int m = a.L[0].m, w = a.L[0].w;
+    double acc = 0.0, acc2 = 0.0;
+    for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+        const int y = t / w, x = t - y * w;
+        if (!is_unknown(x, y, m, a.bc)) continue;
+        if (L0) {
+            const size_t o = (size_t)s * a.L[0].ss + t;
+            const double r = reinterpret_cast<const double*>(a.rhs)[o];
+            reinterpret_cast<double*>(a.zout)[o] = (double)z[t];
+            acc += r * (double)z[t];
+            acc2 += a.q[o] * (double)z[t];
+        } else {
+            reinterpret_cast<T*>(a.zout)[(size_t)s * a.L[0].ss + t] = z[t];
+        }
+    }
+    if (L0) {
+        acc = block_sum(acc, red);
+        acc2 = block_sum(acc2, red);
+        if (threadIdx.x == 0) {
+            a.dot[s] = acc;
+            a.dot2[s] = acc2;
+        }
+    }
+}
+
+// coarse k: geometric mean of k over the full-weighting stencil
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarsen(const T* __restrict__ kf, long long kfss, Lvl F,
+                                                    T* __restrict__ kc, Lvl C, const Scal* scal) {
+    const int s = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C.w * C.w) return;
+    const int J = t / C.w, I = t - J * C.w;
+    const T* k = kf + (size_t)s * kfss;
+    double acc = 0.0, wsum = 0.0;
+    for (int b = -1; b <= 1; ++b)
+        for (int a = -1; a <= 1; ++a) {
+            const int x = 2 * I + a, y = 2 * J + b;
+            if (x < 0 || x > F.m || y < 0 || y > F.m) continue;
+            const double wgt = (double)((2 - abs(a)) * (2 - abs(b)));
+            acc += wgt * log((double)k[(size_t)y * F.w + x]);
+            wsum += wgt;
+        }
+    kc[(size_t)s * C.ss + t] = (T)exp(acc / wsum);
+    (void)scal;
+}
+
+// ----------------------------------------------------------- PCG (double)
+constexpr int PTX = 64, PTY = 16;
+
+template <typename T>
+struct PcgArgs {
+    Lvl L;
+    int bc, tiles_x, ntiles;
+    double f, h2;
+    const T* k;
+    long long kss;
+    double *X, *R, *Pold, *Pnew, *Q, *Z;
+    double* part;
+    Scal* scal;
+};
+
+template <typename T>
+struct KTile {
+    double k[PTY + 2][PTX + 2];
+};
+
+template <typename T>
+__device__ void load_ktile(KTile<T>& K, const T* __restrict__ k, int x0, int y0, int m, int w) {
+    for (int t = threadIdx.x; t < (PTX + 2) * (PTY + 2); t += blockDim.x) {
+        const int y = t / (PTX + 2), x = t - y * (PTX + 2);
+        const int gx = x0 - 1 + x, gy = y0 - 1 + y;
+        K.k[y][x] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? (double)k[(size_t)gy * w + gx] : 0.0;
+    }
+}
+
+// init over the full (m+1)^2 grid: x = Dirichlet lifting, r = b - A x
+// at unknowns, all other vectors zero; partial ||r||^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs<T> a) {
+    __shared__ KTile<T> K;
+    __shared__ double red[kBlock / 64];
+    const int s = blockIdx.y, tile = blockIdx.x;
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int x0 = tx * PTX, y0 = ty * PTY;
+    const int m = a.L.m, w = a.L.w;
+    load_ktile(K, a.k + (size_t)s * a.kss, x0, y0, m, w);
+    __syncthreads();
+    auto KF = [&](int gx, int gy) -> double { return K.k[gy - y0 + 1][gx - x0 + 1]; };
+    const size_t base = (size_t)s * a.L.ss;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < PTX * PTY; t += blockDim.x) {
+        const int yy = t / PTX, xx = t - yy * PTX;
+        const int gx = x0 + xx, gy = y0 + yy;
+        if (gx > m || gy > m) continue;
+        const size_t o = base + (size_t)gy * w + gx;
+        double xv = 0.0, rv = 0.0;
+        if (is_unknown(gx, gy, m, a.bc)) {
+            rv = a.f * (double)tri_count(gx, gy, m) * a.h2 * (1.0 / 6.0);
+            // neighbours carrying Dirichlet data
+            if (!is_unknown(gx + 1, gy, m, a.bc) && gx + 1 <= m) rv += cond_e<double>(gx, gy, m, KF) * dirichlet_value(gx + 1, a.bc);
+            if (!is_unknown(gx - 1, gy, m, a.bc) && gx - 1 >= 0) rv += cond_e<double>(gx - 1, gy, m, KF) * dirichlet_value(gx - 1, a.bc);
+            if (!is_unknown(gx, gy + 1, m, a.bc) && gy + 1 <= m) rv += cond_n<double>(gx, gy, m, KF) * dirichlet_value(gx, a.bc);
+            if (!is_unknown(gx, gy - 1, m, a.bc) && gy - 1 >= 0) rv += cond_n<double>(gx, gy - 1, m, KF) * dirichlet_value(gx, a.bc);
+            acc += rv * rv;
+        } else {
+            xv = dirichlet_value(gx, a.bc);
+        }
+        a.X[o] = xv;
+        a.R[o] = rv;
+        a.Pold[o] = 0.0;
+        a.Pnew[o] = 0.0;
+        a.Q[o] = 0.0;
+        a.Z[o] = 0.0;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
+}
+
+// p_new = z + beta p_old; q = A p_new; partial p_new.q (unknown-region tiles)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
+    __shared__ KTile<T> K;
+    __shared__ double P[PTY + 2][PTX + 2];
+    __shared__ double red[kBlock / 64];
+    const int s = blockIdx.y, tile = blockIdx.x;
+    const Scal sc = a.scal[s];
+    if (!sc.active) return;
+    // flexible (Polak-Ribiere) beta = z_new.(r_new - r_old) / z_old.r_old
+    //                              = -(z_new . q_old) / (p_old . q_old)
+    const double beta = first ? 0.0 : -sc.zq / sc.pq;
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int x0 = 1 + tx * PTX, y0 = a.L.ylo + ty * PTY;
+    const int m = a.L.m, w = a.L.w;
+    load_ktile(K, a.k + (size_t)s * a.kss, x0, y0, m, w);
+    const size_t base = (size_t)s * a.L.ss;
+    for (int t = threadIdx.x; t < (PTX + 2) * (PTY + 2); t += blockDim.x) {
+        const int y = t / (PTX + 2), x = t - y * (PTX + 2);
+        const int gx = x0 - 1 + x, gy = y0 - 1 + y;
+        double v = 0.0;
+        if (is_unknown(gx, gy, m, a.bc)) {
+            const size_t o = base + (size_t)gy * w + gx;
+            v = a.Z[o] + beta * a.Pold[o];
+        }
+        P[y][x] = v;
+    }
+    __syncthreads();
+    auto KF = [&](int gx, int gy) -> double { return K.k[gy - y0 + 1][gx - x0 + 1]; };
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < PTX * PTY; t += blockDim.x) {
+        const int yy = t / PTX, xx = t - yy * PTX;
+        const int gx = x0 + xx, gy = y0 + yy;
+        if (!is_unknown(gx, gy, m, a.bc)) continue;
+        const int x = xx + 1, y = yy + 1;
+        const double cE = cond_e<double>(gx, gy, m, KF), cW = cond_e<double>(gx - 1, gy, m, KF);
+        const double cN = cond_n<double>(gx, gy, m, KF), cS = cond_n<double>(gx, gy - 1, m, KF);
+        const double pc = P[y][x];
+        const double q = (cE * (pc - P[y][x + 1]) + cW * (pc - P[y][x - 1])) + (cN * (pc - P[y + 1][x]) + cS * (pc - P[y - 1][x]));
+        const size_t o = base + (size_t)gy * w + gx;
+        a.Pnew[o] = pc;
+        a.Q[o] = q;
+        acc += pc * q;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
+}
+
+// x += alpha p; r -= alpha q; partial ||r||^2
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(PcgArgs<T> a) {
+    __shared__ double red[kBlock / 64];
+    const int s = blockIdx.y, tile = blockIdx.x;
+    const Scal sc = a.scal[s];
+    if (!sc.active) return;
+    const double alpha = sc.rz / sc.pq;
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int x0 = 1 + tx * PTX, y0 = a.L.ylo + ty * PTY;
+    const int m = a.L.m, w = a.L.w;
+    const size_t base = (size_t)s * a.L.ss;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < PTX * PTY; t += blockDim.x) {
+        const int yy = t / PTX, xx = t - yy * PTX;
+        const int gx = x0 + xx, gy = y0 + yy;
+        if (!is_unknown(gx, gy, m, a.bc)) continue;
+        const size_t o = base + (size_t)gy * w + gx;
+        a.X[o] += alpha * a.Pnew[o];
+        const double r = a.R[o] - alpha * a.Q[o];
+        a.R[o] = r;
+        acc += r * r;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
+}
+
+enum { RED_BB = 0, RED_RZ = 1, RED_PQ = 2, RED_RR = 3 };
+
+template <int WHAT>
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part, const double* __restrict__ part2,
+                                                   int np, Scal* scal, double rtol2, int maxit, int* active_count) {
+    __shared__ double red[kBlock / 64];
+    const int s = blockIdx.x;
+    if (WHAT != RED_BB && !scal[s].active) return;
+    double acc = 0.0, acc2 = 0.0;
+    for (int t = threadIdx.x; t < np; t += blockDim.x) acc += part[(size_t)s * np + t];
+    acc = block_sum(acc, red);
+    if (WHAT == RED_RZ) {
+        for (int t = threadIdx.x; t < np; t += blockDim.x) acc2 += part2[(size_t)s * np + t];
+        acc2 = block_sum(acc2, red);
+    }
+    if (threadIdx.x != 0) return;
+    Scal& sc = scal[s];
+    if (WHAT == RED_BB) {
+        sc.bb = acc;
+        sc.it = 0;
+        sc.rz = sc.rz_old = sc.pq = sc.zq = 0.0;
+        sc.rr = acc;
+        sc.status = 0;
+        sc.active = acc > 0.0 ? 1 : 0;
+        if (sc.active) atomicAdd(active_count, 1);
+    } else if (WHAT == RED_RZ) {
+        sc.rz = acc;
+        sc.zq = acc2;
+    } else if (WHAT == RED_PQ) {
+        sc.pq = acc;
+    } else {
+        sc.rr = acc;
+        sc.it += 1;
+        sc.rz_old = sc.rz;
+        if (acc <= rtol2 * sc.bb) {
+            sc.active = 0;
+            sc.status = 0;
+            atomicSub(active_count, 1);
+        } else if (sc.it >= maxit) {
+            sc.active = 0;
+            sc.status = -4;
+            atomicSub(active_count, 1);
+        }
+    }
+}
+
+// QoI of the P1 solution x (double) per sample; one workgroup per sample.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ X, Lvl L, int bc, double f, int qoi,
+                                                double qx, double qy, const T* __restrict__ k, long long kss,
+                                                const Scal* scal, double* q, int* iters) {
+    __shared__ double red[kBlock / 64];
+    const int s = blockIdx.x;
+    const int m = L.m, w = L.w;
+    const double h = 1.0 / m, h2 = h * h;
+    const double* x = X + (size_t)s * L.ss;
+    double acc = 0.0;
+    if (qoi == Q_INTEGRAL) {
+        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+            const int j = t / w, i = t - j * w;
+            acc += x[t] * (double)tri_count(i, j, m);
+        }
+        acc = block_sum(acc, red) * (h2 / 6.0);
+    } else if (qoi == Q_L2) {
+        for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+            const int j = t / m, i = t - j * m;
+            const double a00 = x[j * w + i], a10 = x[j * w + i + 1], a11 = x[(j + 1) * w + i + 1],
+                         a01 = x[(j + 1) * w + i];
+            const double s1 = a00 + a10 + a11, s2 = a00 + a11 + a01;
+            acc += (a00 * a00 + a10 * a10 + a11 * a11 + s1 * s1) + (a00 * a00 + a11 * a11 + a01 * a01 + s2 * s2);
+        }
+        acc = sqrt(block_sum(acc, red) * (h2 / 24.0));
+    } else if (qoi == Q_POINT) {
+        int i = min((int)floor(qx / h), m - 1), j = min((int)floor(qy / h), m - 1);
+        const double sx = qx / h - i, sy = qy / h - j;
+        if (sx >= sy)
+            acc = (1 - sx) * x[j * w + i] + (sx - sy) * x[j * w + i + 1] + sy * x[(j + 1) * w + i + 1];
+        else
+            acc = (1 - sy) * x[j * w + i] + sx * x[(j + 1) * w + i + 1] + (sy - sx) * x[(j + 1) * w + i];
+    } else {  // outflux through x1 = 1: sum_j (b - A x) at (m, j)
+        const T* kk = k + (size_t)s * kss;
+        auto KF = [&](int gx, int gy) -> double { return (double)kk[(size_t)gy * w + gx]; };
+        for (int j = threadIdx.x; j <= m; j += blockDim.x) {
+            const int i = m;
+            const double xp = x[j * w + i];
+            double ax = cond_e<double>(i - 1, j, m, KF) * (xp - x[j * w + i - 1]);
+            if (j < m) ax += cond_n<double>(i, j, m, KF) * (xp - x[(j + 1) * w + i]);
+            if (j > 0) ax += cond_n<double>(i, j - 1, m, KF) * (xp - x[(j - 1) * w + i]);
+            acc += f * (double)tri_count(i, j, m) * h2 / 6.0 - ax;
+        }
+        acc = block_sum(acc, red);
+    }
+    if (threadIdx.x == 0) {
+        if (q) q[s] = acc;
+        if (iters) iters[s] = scal[s].status == 0 ? scal[s].it : -scal[s].it;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* qf, const double* qc, const int* itf,
+                                                     const int* itc, int slot0, int nslots, long long out0,
+                                                     double* y, double* yf, double* yc, int* iters, int* status) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslots) return;
+    const int sl = slot0 + t;
+    const double a = qf[sl];
+    const double b = qc ? qc[sl] : 0.0;
+    const long long o = out0 + t;
+    y[o] = a - b;
+    if (yf) yf[o] = a;
+    if (yc) yc[o] = b;
+    const int i1 = itf[sl];
+    const int i2 = itc ? itc[sl] : 1;
+    if (iters) iters[o] = i1;
+    if (status) status[o] = (i1 < 0 || i2 < 0) ? -4 : 0;
+}
+
+// ---------------------------------------------------------------- host --
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+template <typename T>
+class SolverImpl final : public Solver {
+public:
+    // tile shapes by precision (LDS <= 64 KiB per workgroup)
+    static constexpr int TX = 64;
+    static constexpr int TY = sizeof(T) == 4 ? 16 : 8;
+    static constexpr int CTX = 32;
+    static constexpr int CTY = sizeof(T) == 4 ? 8 : 4;
+    static constexpr int MB = sizeof(T) == 4 ? 32 : 16;
+
+    SolverImpl(const SolverCfg& cfg, int cap) : cfg_(cfg), cap_(cap) {
+        for (int mm = cfg.m; mm >= 2; mm /= 2) {
+            Lvl l;
+            l.m = mm;
+            l.w = mm + 1;
+            l.ss = (long long)align_up((size_t)l.w * l.w, 64);
+            l.ylo = cfg.bc == BC_FLOWCELL ? 0 : 1;
+            l.yhi = cfg.bc == BC_FLOWCELL ? mm : mm - 1;
+            lv_.push_back(l);
+        }
+        nlev_ = (int)lv_.size();
+        lb_ = 0;
+        while (lv_[lb_].m > MB) ++lb_;
+        const Lvl& L0 = lv_[0];
+        ptx_ = cdiv(L0.m - 1, PTX);
+        pty_ = cdiv(L0.yhi - L0.ylo + 1, PTY);
+        ptiles_ = ptx_ * pty_;
+        itx_ = cdiv(L0.m + 1, PTX);
+        ity_ = cdiv(L0.m + 1, PTY);
+        itiles_ = itx_ * ity_;
+        stx_ = cdiv(L0.m - 1, TX);
+        sty_ = cdiv(L0.yhi - L0.ylo + 1, TY);
+        rz_parts_ = lb_ == 0 ? 1 : stx_ * sty_;
+        max_parts_ = std::max(std::max(ptiles_, itiles_), rz_parts_);
+        // memory plan
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t o = off;
+            off = align_up(off + bytes, 256);
+            return o;
+        };
+        const size_t n0 = (size_t)cap * L0.ss;
+        o_X_ = take(n0 * 8); o_R_ = take(n0 * 8); o_P0_ = take(n0 * 8); o_P1_ = take(n0 * 8);
+        o_Q_ = take(n0 * 8); o_Z_ = take(n0 * 8);
+        o_za0_ = take(n0 * sizeof(T));
+        for (int l = 1; l < nlev_; ++l) {
+            const size_t nl = (size_t)cap * lv_[l].ss * sizeof(T);
+            o_k_.push_back(take(nl));
+            o_rhs_.push_back(take(nl));
+            o_za_.push_back(take(nl));
+            o_zb_.push_back(take(nl));
+        }
+        o_part_ = take((size_t)cap * max_parts_ * 8);
+        o_part2_ = take((size_t)cap * max_parts_ * 8);
+        o_scal_ = take((size_t)cap * sizeof(Scal));
+        o_q_ = take((size_t)cap * 8);
+        o_it_ = take((size_t)cap * 4);
+        o_cnt_ = take(64);
+        bytes_ = off;
+    }
+    ~SolverImpl() override {
+        if (base_) (void)hipFree(base_);
+        if (hcnt_) (void)hipHostFree(hcnt_);
+        for (auto& e : ev_)
+            if (e) (void)hipEventDestroy(e);
+    }
+    bool alloc(std::string* err) {
+        hipError_t e = hipMalloc(&base_, bytes_);
+        if (e != hipSuccess) {
+            base_ = nullptr;
+            *err = std::string("solver workspace allocation failed: ") + hipGetErrorString(e);
+            return false;
+        }
+        e = hipMemset(base_, 0, bytes_);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&hcnt_, 2 * sizeof(int), hipHostMallocDefault);
+        for (auto& ev : ev_)
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            *err = std::string("solver set-up failed: ") + hipGetErrorString(e);
+            return false;
+        }
+        return true;
+    }
+    int capacity() const override { return cap_; }
+    size_t bytes() const override { return bytes_; }
+    int mg_levels() const override { return nlev_; }
+    const double* x() const override { return ptr<double>(o_X_); }
+    long long xstride() const override { return lv_[0].ss; }
+
+    hipError_t solve(const void* kv, long long kss, int S, hipStream_t st) override {
+        if (S <= 0) return hipSuccess;
+        const T* k0 = reinterpret_cast<const T*>(kv);
+        Scal* scal = ptr<Scal>(o_scal_);
+        int* cnt = ptr<int>(o_cnt_);
+        double* part = ptr<double>(o_part_);
+        double* part2 = ptr<double>(o_part2_);
+        // coefficient hierarchy
+        for (int l = 0; l + 1 < nlev_; ++l) {
+            const T* kf = l == 0 ? k0 : ptr<T>(o_k_[l - 1]);
+            const long long fss = l == 0 ? kss : lv_[l].ss;
+            hipLaunchKernelGGL(k_coarsen<T>, dim3(cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S),
+                               dim3(kBlock), 0, st, kf, fss, lv_[l], ptr<T>(o_k_[l]), lv_[l + 1], scal);
+        }
+        hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
+        if (e != hipSuccess) return e;
+        PcgArgs<T> pa = pcg_args(k0, kss, 0);
+        pa.tiles_x = itx_;
+        pa.ntiles = itiles_;
+        hipLaunchKernelGGL(k_pcg_init<T>, dim3(itiles_, S), dim3(kBlock), 0, st, pa);
+        const double rtol2 = cfg_.rtol * cfg_.rtol;
+        hipLaunchKernelGGL(k_reduce<RED_BB>, dim3(S), dim3(kBlock), 0, st, part, part, itiles_, scal, rtol2, cfg_.maxit, cnt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int it = 0; it < cfg_.maxit; ++it) {
+            vcycle(k0, kss, S, st);
+            hipLaunchKernelGGL(k_reduce<RED_RZ>, dim3(S), dim3(kBlock), 0, st, part, part2, rz_parts_, scal, rtol2, cfg_.maxit, cnt);
+            PcgArgs<T> a = pcg_args(k0, kss, it);
+            hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_, S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
+            hipLaunchKernelGGL(k_reduce<RED_PQ>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
+            hipLaunchKernelGGL(k_pcg_update<T>, dim3(ptiles_, S), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL(k_reduce<RED_RR>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            // lagged convergence poll: read the count of iteration it-1
+            // while iteration it is queued.
+            if ((e = hipMemcpyAsync(&hcnt_[it & 1], cnt, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+            if ((e = hipEventRecord(ev_[it & 1], st)) != hipSuccess) return e;
+            if (it >= 1) {
+                if ((e = hipEventSynchronize(ev_[(it - 1) & 1])) != hipSuccess) return e;
+                if (hcnt_[(it - 1) & 1] == 0) break;
+            }
+        }
+        last_p_ = 0;
+        return hipGetLastError();
+    }
+
+    hipError_t qoi(const void* kv, long long kss, int S, double* q, int* iters, hipStream_t st) override {
+        if (S <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k_qoi<T>, dim3(S), dim3(kBlock), 0, st, ptr<double>(o_X_), lv_[0], cfg_.bc, cfg_.f,
+                           cfg_.qoi, cfg_.qx, cfg_.qy, reinterpret_cast<const T*>(kv), kss, ptr<Scal>(o_scal_),
+                           q ? q : ptr<double>(o_q_), iters ? iters : ptr<int>(o_it_));
+        return hipGetLastError();
+    }
+
+private:
+    template <typename U>
+    U* ptr(size_t off) const { return reinterpret_cast<U*>(reinterpret_cast<char*>(base_) + off); }
+
+    PcgArgs<T> pcg_args(const T* k0, long long kss, int it) {
+        PcgArgs<T> a{};
+        a.L = lv_[0];
+        a.bc = cfg_.bc;
+        a.tiles_x = ptx_;
+        a.ntiles = ptiles_;
+        a.f = cfg_.f;
+        a.h2 = 1.0 / ((double)cfg_.m * cfg_.m);
+        a.k = k0;
+        a.kss = kss;
+        a.X = ptr<double>(o_X_);
+        a.R = ptr<double>(o_R_);
+        a.Pold = ptr<double>((it & 1) ? o_P1_ : o_P0_);
+        a.Pnew = ptr<double>((it & 1) ? o_P0_ : o_P1_);
+        a.Q = ptr<double>(o_Q_);
+        a.Z = ptr<double>(o_Z_);
+        a.part = ptr<double>(o_part_);
+        a.scal = ptr<Scal>(o_scal_);
+        return a;
+    }
+
+    const T* klev(int l, const T* k0) const { return l == 0 ? k0 : ptr<T>(o_k_[l - 1]); }
+    long long kss_lev(int l, long long kss0) const { return l == 0 ? kss0 : lv_[l].ss; }
+
+    void vcycle(const T* k0, long long kss, int S, hipStream_t st) {
+        Scal* scal = ptr<Scal>(o_scal_);
+        for (int l = 0; l < lb_; ++l) {
+            const Lvl& L = lv_[l];
+            const int tx = cdiv(L.m - 1, TX), ty = cdiv(L.yhi - L.ylo + 1, TY);
+            SmoothArgs<T> a{};
+            a.L = L;
+            a.bc = cfg_.bc;
+            a.tiles_x = tx;
+            a.ntiles = tx * ty;
+            a.k = klev(l, k0);
+            a.kss = kss_lev(l, kss);
+            a.rhs = l == 0 ? (const void*)ptr<double>(o_R_) : (const void*)ptr<T>(o_rhs_[l - 1]);
+            a.za = l == 0 ? ptr<T>(o_za0_) : ptr<T>(o_za_[l - 1]);
+            a.scal = scal;
+            if (l == 0)
+                hipLaunchKernelGGL((k_smooth<T, TX, TY, false, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_smooth<T, TX, TY, false, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+            const Lvl& C = lv_[l + 1];
+            const int ctx = cdiv(C.m - 1, CTX), cty = cdiv(C.yhi - C.ylo + 1, CTY);
+            RestrictArgs<T> r{};
+            r.L = L;
+            r.C = C;
+            r.bc = cfg_.bc;
+            r.tiles_x = ctx;
+            r.k = a.k;
+            r.kss = a.kss;
+            r.rhs = a.rhs;
+            r.z = a.za;
+            r.rhs_c = ptr<T>(o_rhs_[l]);
+            r.scal = scal;
+            if (l == 0)
+                hipLaunchKernelGGL((k_restrict<T, CTX, CTY, true>), dim3(ctx * cty, S), dim3(kBlock), 0, st, r);
+            else
+                hipLaunchKernelGGL((k_restrict<T, CTX, CTY, false>), dim3(ctx * cty, S), dim3(kBlock), 0, st, r);
+        }
+        {
+            BottomArgs<T> b{};
+            b.nl = nlev_ - lb_;
+            b.bc = cfg_.bc;
+            for (int l = 0; l < b.nl; ++l) {
+                b.L[l] = lv_[lb_ + l];
+                b.k[l] = klev(lb_ + l, k0);
+                b.kss[l] = kss_lev(lb_ + l, kss);
+            }
+            b.scal = scal;
+            b.dot = ptr<double>(o_part_);
+            b.dot2 = ptr<double>(o_part2_);
+            b.q = ptr<double>(o_Q_);
+            if (lb_ == 0) {
+                b.rhs = ptr<double>(o_R_);
+                b.zout = ptr<double>(o_Z_);
+                hipLaunchKernelGGL((k_bottom<T, MB, true>), dim3(S), dim3(kBlock), 0, st, b);
+            } else {
+                b.rhs = ptr<T>(o_rhs_[lb_ - 1]);
+                b.zout = ptr<T>(o_zb_[lb_ - 1]);
+                hipLaunchKernelGGL((k_bottom<T, MB, false>), dim3(S), dim3(kBlock), 0, st, b);
+            }
+        }
+        for (int l = lb_ - 1; l >= 0; --l) {
+            const Lvl& L = lv_[l];
+            const int tx = cdiv(L.m - 1, TX), ty = cdiv(L.yhi - L.ylo + 1, TY);
+            SmoothArgs<T> a{};
+            a.L = L;
+            a.C = lv_[l + 1];
+            a.bc = cfg_.bc;
+            a.tiles_x = tx;
+            a.ntiles = tx * ty;
+            a.k = klev(l, k0);
+            a.kss = kss_lev(l, kss);
+            a.rhs = l == 0 ? (const void*)ptr<double>(o_R_) : (const void*)ptr<T>(o_rhs_[l - 1]);
+            a.za = l == 0 ? ptr<T>(o_za0_) : ptr<T>(o_za_[l - 1]);
+            a.zc = ptr<T>(o_zb_[l]);
+            a.zout = l == 0 ? (void*)ptr<double>(o_Z_) : (void*)ptr<T>(o_zb_[l - 1]);
+            a.dot = ptr<double>(o_part_);
+            a.dot2 = ptr<double>(o_part2_);
+            a.q = ptr<double>(o_Q_);
+            a.scal = scal;
+            if (l == 0)
+                hipLaunchKernelGGL((k_smooth<T, TX, TY, true, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_smooth<T, TX, TY, true, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+        }
+    }
+
+    SolverCfg cfg_;
+    int cap_;
+    std::vector<Lvl> lv_;
+    int nlev_ = 0, lb_ = 0;
+    int ptx_ = 0, pty_ = 0, ptiles_ = 0, itx_ = 0, ity_ = 0, itiles_ = 0, stx_ = 0, sty_ = 0;
+    int rz_parts_ = 0, max_parts_ = 0;
+    size_t o_X_ = 0, o_R_ = 0, o_P0_ = 0, o_P1_ = 0, o_Q_ = 0, o_Z_ = 0, o_za0_ = 0;
+    std::vector<size_t> o_k_, o_rhs_, o_za_, o_zb_;
+    size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0;
+    size_t bytes_ = 0;
+    void* base_ = nullptr;
+    int* hcnt_ = nullptr;
+    hipEvent_t ev_[2] = {nullptr, nullptr};
+    int last_p_ = 0;
+};
+
+}  // namespace
+
+std::unique_ptr<Solver> make_solver(const SolverCfg& cfg, int capacity, bool is_double, std::string* err) {
+    if (cfg.m < 4 || (cfg.m & (cfg.m - 1)) != 0) {
+        *err = "solver mesh must be a power of two >= 4";
+        return nullptr;
+    }
+    if (is_double) {
+        auto s = std::make_unique<SolverImpl<double>>(cfg, capacity);
+        if (!s->alloc(err)) return nullptr;
+        return s;
+    }
+    auto s = std::make_unique<SolverImpl<float>>(cfg, capacity);
+    if (!s->alloc(err)) return nullptr;
+    return s;
+}
+
+hipError_t launch_finalize(const double* qf, const double* qc, const int* itf, const int* itc, int slot0,
+                           int nslots, long long out0, double* y, double* yf, double* yc, int* iters, int* status,
+                           hipStream_t st) {
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3(cdiv(nslots, kBlock)), dim3(kBlock), 0, st, qf, qc, itf, itc, slot0, nslots,
+                       out0, y, yf, yc, iters, status);
+    return hipGetLastError();
+}
+
+}  // namespace ces

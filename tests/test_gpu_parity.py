@@ -1,0 +1,201 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars (stated per test): normals bit-exact; eigenvalues to 1e-12 of the
+largest; masks equal up to ties within 1e-12; FP64 fields to 1e-11 of
+max|Z|; mixed fields to 1e-5 of max|Z|; FP64 QoI to 1e-9 relative; mixed
+QoI to 1e-6 relative (field rounding to float dominates; CG runs to
+||r|| <= 1e-10 ||r0|| in double on both paths).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import embedding as oem, fem as ofem, normals as onm, sampler as osm
+from paper_2306_13493_amd import workloads as W
+from tests.inputs import lognormal_k
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ces():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_13493_amd as ces
+    ces.load()
+    return ces
+
+
+@pytest.fixture(scope="module")
+def ctx(ces):
+    return ces.Context(0)
+
+
+def mkplan(ctx, ces, w):
+    return ctx.plan(ces.level_desc(**w))
+
+
+def oracle_plan(w):
+    return osm.Plan(W.to_oracle(w))
+
+
+# ------------------------------------------------------------------ normals
+@pytest.mark.parametrize("seed,q,stream,first,count", [
+    (0, 0, 0, 0, 4096),
+    (12345678901, 7, 3, 1000, 5000),
+    (2 ** 63 + 5, 2 ** 40 + 3, 9, 2 ** 31, 3000),
+])
+def test_normals_bit_exact(ces, seed, q, stream, first, count):
+    g = ces.normals(seed, q, stream, first, count).cpu().numpy()
+    e = np.arange(first, first + count, dtype=np.uint64)
+    g0, g1 = onm.normals(seed, q, stream, e)
+    ref = np.stack([g0, g1], axis=1)
+    assert np.array_equal(g.view(np.uint64), ref.view(np.uint64))
+
+
+# ----------------------------------------------------------- eigenvalues
+EIG_CASES = {
+    "c1_clamp": W.C1,
+    "c2_grow": W.C2,
+    "grow_pad_euclid": dict(cov="matern", nu=0.5, lam=0.3, m=32, psd="grow"),
+    "grow_pad_inf": dict(cov="matern", nu=1.5, lam=0.3, m=32, psd="grow", period="inf"),
+    "sepexp": dict(cov="sepexp", lam=0.1, m=32),
+    "c3_l2_smoothed": W.c3_level(2),
+    "c3_l4_finest": W.c3_level(4),
+}
+
+
+def masks_agree(mg, mo, lam, tol=1e-12):
+    if np.array_equal(mg, mo):
+        return True
+    diff = mg != mo
+    lmax = lam.max()
+    # disagreement only among values tied with the kept/dropped boundary
+    boundary = lam[(mo == 0)].max() if (mo == 0).any() else 0.0
+    return bool(np.all(np.abs(lam[diff] - boundary) <= tol * lmax))
+
+
+@pytest.mark.parametrize("name", list(EIG_CASES))
+def test_eigenvalues_and_masks(ctx, ces, name):
+    w = EIG_CASES[name]
+    p = mkplan(ctx, ces, w)
+    o = oracle_plan(w)
+    assert p.info.n == o.n and p.info.J == o.J
+    assert p.info.n_clamped == o.info["n_clamped"]
+    lam = p.eigenvalues()
+    lmax = o.lam.max()
+    assert np.max(np.abs(lam - o.lam)) <= 1e-12 * lmax
+    assert abs(p.info.lam_min - o.info["lam_min"]) <= 1e-12 * lmax
+    mf, mc = p.masks()
+    assert masks_agree(mf, o.keep_f.astype(np.uint8), o.lam)
+    if w.get("level") == "pair":
+        assert masks_agree(mc, o.keep_c.astype(np.uint8), o.lam)
+
+
+# ----------------------------------------------------------------- fields
+FIELD_CASES = {
+    "pair_single": dict(cov="matern", nu=1.0, lam=0.1, m=32, level="single"),
+    "pair_level_smoothed_nf2": dict(cov="matern", nu=0.5, lam=0.03, m=16, level="pair", tau_fine=0, tau_coarse=-1),
+    "pair_level_smoothed_nf1": dict(cov="matern", nu=0.5, lam=0.03, m=32, level="pair", tau_fine=-1, tau_coarse=-1),
+    "hartley_pair_level": dict(cov="matern", nu=1.5, lam=0.2, m=16, level="pair", field="hartley"),
+    "padded_n96": dict(cov="matern", nu=0.5, lam=0.3, m=32, level="pair", stream=3),
+    "c2_size": dict(W.C2),
+}
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 1e-5)])
+@pytest.mark.parametrize("name", list(FIELD_CASES))
+def test_field_parity(ctx, ces, name, prec, tol):
+    w = dict(FIELD_CASES[name], precision=prec)
+    p = mkplan(ctx, ces, w)
+    o = oracle_plan(w)
+    for i in (0, 1, 5):
+        zf, zc = p.field(seed=7, sample=i)
+        rf, rc = o.fields(7, i)
+        scale = np.abs(rf).max()
+        assert np.max(np.abs(zf.cpu().numpy() - rf)) <= tol * scale, (name, i)
+        if rc is not None:
+            assert np.max(np.abs(zc.cpu().numpy() - rc)) <= tol * scale, (name, i)
+
+
+# ------------------------------------------------------------------ solve
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("bc,m", [("dirichlet0", 32), ("flowcell", 32), ("dirichlet0", 64), ("flowcell", 128)])
+def test_solve_parity(ctx, ces, prec, bc, m):
+    w = dict(cov="matern", nu=1.0, lam=0.2, m=m, bc=bc, precision=prec, cg_rtol=1e-12)
+    p = mkplan(ctx, ces, w)
+    k = lognormal_k(m, 3, seed=m + (bc == "flowcell"))
+    u, it = p.solve(torch.from_numpy(k).cuda())
+    u = u.cpu().numpy()
+    it = it.cpu().numpy()
+    assert np.all(it > 0) and np.all(it < 60), it
+    # the mixed path stores k in float: the oracle solves with the same k
+    kref = k if prec == "fp64" else k.astype(np.float32).astype(np.float64)
+    for s in range(k.shape[0]):
+        ref, _, _ = ofem.solve(kref[s], m, ofem.FLOWCELL if bc == "flowcell" else ofem.DIRICHLET0)
+        assert np.max(np.abs(u[s] - ref)) <= 1e-9 * np.abs(ref).max(), (s, it[s])
+
+
+# ---------------------------------------------------------- level samples
+SAMPLE_CASES = {
+    "c1": (dict(W.C1), 64),
+    "c1_mixed": (dict(W.C1, precision="mixed"), 64),
+    "pair_smoothed_nf2": (dict(cov="matern", nu=0.5, lam=0.03, m=16, level="pair", tau_fine=0,
+                               tau_coarse=-1, stream=4), 24),
+    "pair_smoothed_nf1": (dict(cov="matern", nu=0.5, lam=0.03, m=32, level="pair", tau_fine=-1,
+                               tau_coarse=-1, stream=2), 16),
+    "hartley": (dict(cov="matern", nu=1.0, lam=0.1, m=16, field="hartley"), 9),
+    "flowcell_outflux": (dict(cov="matern", nu=1.5, lam=0.05, sigma2=2.0, m=32, bc="flowcell",
+                              qoi="outflux"), 8),
+    "point_qoi_pair": (dict(cov="sepexp", lam=0.3, m=32, level="pair", qoi="point"), 8),
+    "l2_qoi": (dict(cov="matern", nu=1.5, lam=0.03, m=64, qoi="l2"), 6),
+}
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("mixed", 1e-6)])
+@pytest.mark.parametrize("name", list(SAMPLE_CASES))
+def test_level_samples(ctx, ces, name, prec, tol):
+    w, count = SAMPLE_CASES[name]
+    w = dict(w, precision=prec)
+    p = mkplan(ctx, ces, w)
+    out = p.sample(seed=3, first=1, count=count)
+    torch.cuda.synchronize()
+    y = out["y"].cpu().numpy()
+    yf = out["q_fine"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    assert np.all(st == 0) and np.all(it > 0)
+    o = oracle_plan(w)
+    ref = np.array([o.sample(3, 1 + t) for t in range(count)])
+    scale = np.abs(ref[:, 1]).max()
+    assert np.max(np.abs(yf - ref[:, 1])) <= tol * scale
+    assert np.max(np.abs(y - ref[:, 0])) <= tol * scale
+
+
+def test_batch_independence(ctx, ces):
+    w = dict(cov="matern", nu=0.5, lam=0.05, m=32, level="pair", tau_fine=-1, tau_coarse=-1)
+    p = mkplan(ctx, ces, w)
+    a = p.sample(seed=11, first=0, count=20)["y"].cpu().numpy()
+    b = p.sample(seed=11, first=5, count=7)["y"].cpu().numpy()
+    c = p.sample(seed=11, first=19, count=1)["y"].cpu().numpy()
+    assert np.array_equal(a[5:12], b) and a[19] == c[0]
+    d = p.sample(seed=12, first=0, count=20)["y"].cpu().numpy()
+    assert not np.array_equal(a, d)
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-6), ("fp64", 1e-9)])
+def test_c2_full_size_sampled(ctx, ces, prec, tol):
+    w = dict(W.C2, precision=prec)
+    p = mkplan(ctx, ces, w)
+    out = p.sample(seed=0, first=0, count=256)
+    torch.cuda.synchronize()
+    y = out["y"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    assert np.all(out["status"].cpu().numpy() == 0)
+    print("C2 %s iterations: min %d max %d mean %.2f" % (prec, it.min(), it.max(), it.mean()))
+    o = oracle_plan(w)
+    for i in (0, 1, 255):
+        ref = o.sample(0, i)[0]
+        assert abs(y[i] - ref) <= tol * abs(ref), (i, y[i], ref)
