@@ -131,26 +131,6 @@ __device__ void region_conductances(Region<T, RX, RY>& R, int ox, int oy, int m,
     }
 }
 
-// One red-black half-sweep of colour c over [h, RX-h) x [h, RY-h).
-template <typename T, int RX, int RY>
-__device__ void region_half_sweep(Region<T, RX, RY>& R, int ox, int oy, int c, int h) {
-    const int wx = RX - 2 * h, wy = RY - 2 * h;
-    const int half = (wx + 1) / 2;
-    for (int t = threadIdx.x; t < half * wy; t += blockDim.x) {
-        const int yy = t / half;
-        const int y = h + yy;
-        const int par = (c - (ox + h) - (oy + y)) & 1;
-        const int x = h + 2 * (t - yy * half) + par;
-        if (x >= RX - h) continue;
-        const T id = R.aux[y][x];
-        if (id == T(0)) continue;
-        const T s = R.rhs[y][x] + R.ce[y][x] * R.z[y][x + 1] + R.ce[y][x - 1] * R.z[y][x - 1] +
-                    R.cn[y][x] * R.z[y + 1][x] + R.cn[y - 1][x] * R.z[y - 1][x];
-        R.z[y][x] = s * id;
-    }
-    __syncthreads();
-}
-
 // ------------------------------------------------------------ kernels ---
 template <typename T>
 struct SmoothArgs {
@@ -170,10 +150,20 @@ struct SmoothArgs {
     const Scal* scal;
 };
 
-template <typename T, int TX, int TY, bool POST, bool L0>
+// Smoothing step on one tile: the region is 64 columns x 4*SH rows (tile
+// plus a 4-node halo on every side).  Thread (strip, column) owns the SH
+// nodes of its column in its strip and keeps their z, rhs, inverse
+// diagonal and conductances in registers; only left/right neighbours and
+// the first/last node of a strip travel through LDS.  One wave = one strip
+// = 64 consecutive columns, so every LDS row access is conflict-free and
+// every global row access is one coalesced segment.
+template <typename T, int SH, bool POST, bool L0>
 __global__ __launch_bounds__(kBlock) void k_smooth(SmoothArgs<T> a) {
-    constexpr int H = 4, RX = TX + 2 * H, RY = TY + 2 * H;
-    __shared__ Region<T, RX, RY> R;
+    constexpr int H = 4, RX = 64, NS = kBlock / RX, RY = NS * SH;
+    constexpr int TX = RX - 2 * H, TY = RY - 2 * H;
+    __shared__ T sz[RY][RX];
+    __shared__ T sk[RY + 2][RX + 2];
+    __shared__ T szc[POST ? RY / 2 + 3 : 1][POST ? RX / 2 + 3 : 1];
     __shared__ double red[kBlock / 64];
     const int s = blockIdx.y;
     if (!a.scal[s].active) return;
@@ -181,64 +171,101 @@ __global__ __launch_bounds__(kBlock) void k_smooth(SmoothArgs<T> a) {
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = 1 + tx * TX, y0 = a.L.ylo + ty * TY;
     const int ox = x0 - H, oy = y0 - H;
-    const int m = a.L.m, w = a.L.w;
-    region_load_k(R, a.k + (size_t)s * a.kss, ox, oy, m, w);
+    const int m = a.L.m, w = a.L.w, bc = a.bc;
+    const T* kk = a.k + (size_t)s * a.kss;
+    for (int t = threadIdx.x; t < (RX + 2) * (RY + 2); t += blockDim.x) {
+        const int y = t / (RX + 2), x = t - y * (RX + 2);
+        const int gx = ox - 1 + x, gy = oy - 1 + y;
+        sk[y][x] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? kk[(size_t)gy * w + gx] : T(0);
+    }
+    const int cox = ox >> 1, coy = oy >> 1;  // floor for negative origins
+    if constexpr (POST) {
+        const T* zc = a.zc + (size_t)s * a.C.ss;
+        const int cm = a.C.m, cw = a.C.w;
+        for (int t = threadIdx.x; t < (RY / 2 + 3) * (RX / 2 + 3); t += blockDim.x) {
+            const int y = t / (RX / 2 + 3), x = t - y * (RX / 2 + 3);
+            const int I = cox + x, J = coy + y;
+            szc[y][x] = is_unknown(I, J, cm, bc) ? zc[(size_t)J * cw + I] : T(0);
+        }
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % RX;
+    const int ly0 = (threadIdx.x / RX) * SH;
+    const int gx = ox + lx;
+    auto K = [&](int xx, int yy) -> T { return sk[yy - oy + 1][xx - ox + 1]; };
+    T z[SH], rhs[SH], id[SH], cn[SH + 1], ce[SH], cwst[SH];
+    const T* zin = a.za + (size_t)s * a.L.ss;
     const T* rhsT = L0 ? nullptr : reinterpret_cast<const T*>(a.rhs) + (size_t)s * a.L.ss;
     const double* rhsD = L0 ? reinterpret_cast<const double*>(a.rhs) + (size_t)s * a.L.ss : nullptr;
-    const T* zin = a.za + (size_t)s * a.L.ss;
-    const T* zc = POST ? a.zc + (size_t)s * a.C.ss : nullptr;
-    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
-        const int y = t / RX, x = t - y * RX;
-        const int gx = ox + x, gy = oy + y;
-        T r = T(0), z = T(0);
-        if (is_unknown(gx, gy, m, a.bc)) {
+    cn[0] = cond_n<T>(gx, oy + ly0 - 1, m, K);
+#pragma unroll
+    for (int i = 0; i < SH; ++i) {
+        const int gy = oy + ly0 + i;
+        ce[i] = cond_e<T>(gx, gy, m, K);
+        cwst[i] = cond_e<T>(gx - 1, gy, m, K);
+        cn[i + 1] = cond_n<T>(gx, gy, m, K);
+        T r = T(0), zz = T(0), d = T(0);
+        if (is_unknown(gx, gy, m, bc)) {
             const size_t o = (size_t)gy * w + gx;
             r = L0 ? (T)rhsD[o] : rhsT[o];
-            if (POST) {
-                // z + P zc, bilinear prolongation from the coarse nodes
-                const int I = gx >> 1, J = gy >> 1;
-                const int cw = a.C.w, cm = a.C.m;
-                auto zcv = [&](int ci, int cj) -> T {
-                    return is_unknown(ci, cj, cm, a.bc) ? zc[(size_t)cj * cw + ci] : T(0);
-                };
-                T p;
+            d = T(1) / (ce[i] + cwst[i] + cn[i + 1] + cn[i]);
+            if constexpr (POST) {
+                const int I = (gx >> 1) - cox, J = (gy >> 1) - coy;
                 const bool ox1 = gx & 1, oy1 = gy & 1;
-                if (!ox1 && !oy1) p = zcv(I, J);
-                else if (ox1 && !oy1) p = T(0.5) * (zcv(I, J) + zcv(I + 1, J));
-                else if (!ox1 && oy1) p = T(0.5) * (zcv(I, J) + zcv(I, J + 1));
-                else p = T(0.25) * ((zcv(I, J) + zcv(I + 1, J)) + (zcv(I, J + 1) + zcv(I + 1, J + 1)));
-                z = zin[o] + p;
+                T p;
+                if (!ox1 && !oy1) p = szc[J][I];
+                else if (ox1 && !oy1) p = T(0.5) * (szc[J][I] + szc[J][I + 1]);
+                else if (!ox1 && oy1) p = T(0.5) * (szc[J][I] + szc[J + 1][I]);
+                else p = T(0.25) * ((szc[J][I] + szc[J][I + 1]) + (szc[J + 1][I] + szc[J + 1][I + 1]));
+                zz = zin[o] + p;
             }
         }
-        R.rhs[y][x] = r;
-        R.z[y][x] = z;
+        z[i] = zz;
+        rhs[i] = r;
+        id[i] = d;
+        sz[ly0 + i][lx] = zz;
     }
-    __syncthreads();
-    region_conductances(R, ox, oy, m, a.bc, true);
     __syncthreads();
     const int c0 = POST ? 1 : 0;
-    region_half_sweep(R, ox, oy, c0, 1);
-    region_half_sweep(R, ox, oy, 1 - c0, 2);
-    region_half_sweep(R, ox, oy, c0, 3);
-    region_half_sweep(R, ox, oy, 1 - c0, 4);
+#pragma unroll
+    for (int h = 1; h <= H; ++h) {
+        const int c = (h & 1) ? c0 : 1 - c0;
+        const bool colx = lx >= h && lx < RX - h;
+#pragma unroll
+        for (int i = 0; i < SH; ++i) {
+            const int ly = ly0 + i;
+            const bool upd = colx && ly >= h && ly < RY - h && (((gx + oy + ly) & 1) == c) && id[i] != T(0);
+            if (upd) {
+                const T zs = (i > 0) ? z[i - 1] : sz[ly - 1][lx];
+                const T zn = (i < SH - 1) ? z[i + 1] : sz[ly + 1][lx];
+                const T zE = sz[ly][lx + 1], zW = sz[ly][lx - 1];
+                const T v = (rhs[i] + ce[i] * zE + cwst[i] * zW + cn[i + 1] * zn + cn[i] * zs) * id[i];
+                z[i] = v;
+                sz[ly][lx] = v;
+            }
+        }
+        __syncthreads();
+    }
     double acc = 0.0, acc2 = 0.0;
-    for (int t = threadIdx.x; t < TX * TY; t += blockDim.x) {
-        const int yy = t / TX, xx = t - yy * TX;
-        const int gx = x0 + xx, gy = y0 + yy;
-        if (!is_unknown(gx, gy, m, a.bc)) continue;
-        const size_t o = (size_t)gy * w + gx;
-        const T z = R.z[yy + H][xx + H];
-        if (!POST) {
-            a.za[(size_t)s * a.L.ss + o] = z;
-        } else if (L0) {
-            reinterpret_cast<double*>(a.zout)[(size_t)s * a.L.ss + o] = (double)z;
-            acc += rhsD[o] * (double)z;
-            acc2 += a.q[(size_t)s * a.L.ss + o] * (double)z;
-        } else {
-            reinterpret_cast<T*>(a.zout)[(size_t)s * a.L.ss + o] = z;
+    if (lx >= H && lx < H + TX) {
+#pragma unroll
+        for (int i = 0; i < SH; ++i) {
+            const int ly = ly0 + i;
+            const int gy = oy + ly;
+            if (ly < H || ly >= H + TY || !is_unknown(gx, gy, m, bc)) continue;
+            const size_t o = (size_t)gy * w + gx;
+            if (!POST) {
+                a.za[(size_t)s * a.L.ss + o] = z[i];
+            } else if (L0) {
+                reinterpret_cast<double*>(a.zout)[(size_t)s * a.L.ss + o] = (double)z[i];
+                acc += rhsD[o] * (double)z[i];
+                acc2 += a.q[(size_t)s * a.L.ss + o] * (double)z[i];
+            } else {
+                reinterpret_cast<T*>(a.zout)[(size_t)s * a.L.ss + o] = z[i];
+            }
         }
     }
-    if (POST && L0) {
+    if constexpr (POST && L0) {
         acc = block_sum(acc, red);
         acc2 = block_sum(acc2, red);
         if (threadIdx.x == 0) {
@@ -816,8 +843,9 @@ template <typename T>
 class SolverImpl final : public Solver {
 public:
     // tile shapes by precision (LDS <= 64 KiB per workgroup)
-    static constexpr int TX = 64;
-    static constexpr int TY = sizeof(T) == 4 ? 16 : 8;
+    static constexpr int SH = 8;                       // rows per thread
+    static constexpr int TX = 64 - 8;                  // smoothing tile (64 x 4*SH region)
+    static constexpr int TY = (kBlock / 64) * SH - 8;
     static constexpr int CTX = 32;
     static constexpr int CTY = sizeof(T) == 4 ? 8 : 4;
     static constexpr int MB = sizeof(T) == 4 ? 32 : 16;
@@ -998,9 +1026,9 @@ private:
             a.za = l == 0 ? ptr<T>(o_za0_) : ptr<T>(o_za_[l - 1]);
             a.scal = scal;
             if (l == 0)
-                hipLaunchKernelGGL((k_smooth<T, TX, TY, false, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+                hipLaunchKernelGGL((k_smooth<T, SH, false, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
             else
-                hipLaunchKernelGGL((k_smooth<T, TX, TY, false, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+                hipLaunchKernelGGL((k_smooth<T, SH, false, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
             const Lvl& C = lv_[l + 1];
             const int ctx = cdiv(C.m - 1, CTX), cty = cdiv(C.yhi - C.ylo + 1, CTY);
             RestrictArgs<T> r{};
@@ -1062,9 +1090,9 @@ private:
             a.q = ptr<double>(o_Q_);
             a.scal = scal;
             if (l == 0)
-                hipLaunchKernelGGL((k_smooth<T, TX, TY, true, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+                hipLaunchKernelGGL((k_smooth<T, SH, true, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
             else
-                hipLaunchKernelGGL((k_smooth<T, TX, TY, true, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+                hipLaunchKernelGGL((k_smooth<T, SH, true, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
         }
     }
 
