@@ -1,0 +1,217 @@
+"""Benchmark: MLMC level samples/s (field + solve) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = one pass of the whole hot path (normals, field DFTs, multigrid-
+preconditioned CG solve, QoI) over one batch: the 4096 i.i.d. samples of
+the single-level configuration Matern nu=1, lambda=0.1, sigma2=1 on 257^2
+vertices (embedding 512^2), integral QoI, mixed precision (float field and
+multigrid, double CG).  Each step draws new samples (seed 0, consecutive
+sample indices).  Inputs are synthetic and generated on the device; the
+plan set-up (eigenvalue DFT, masks) is timed separately, outside the timed
+region.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLMC level samples/sec (field+solve) at 1 GPU, p50/p99 latency, % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+# library kernel name -> device kernel symbol prefix (for rocprofv3 summaries)
+KERNEL_SYMBOL = {
+    "mg_post_l0": "k_smooth<float, 8, true, true>",
+    "mg_pre_l0": "k_smooth<float, 8, false, true>",
+    "mg_restrict_l0": "k_restrict<float, 32, 8, true>",
+    "pcg_dir": "k_pcg_dir<float>",
+    "pcg_update": "k_pcg_update<float>",
+    "mg_post": "k_smooth<float, 8, true, false>",
+    "mg_pre": "k_smooth<float, 8, false, false>",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _oracle_worker(args):
+    desc, seed, idx = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import sampler
+    p = sampler.Plan(desc)
+    return [p.sample(seed, i)[0] for i in idx]
+
+
+def cpu_baseline(workload, seed, nsamples, nproc):
+    """The FP64 oracle timed on host cores over a bounded sample."""
+    import multiprocessing as mp
+    from paper_2306_13493_amd.workloads import to_oracle
+    desc = to_oracle(workload)
+    chunks = [list(range(r, nsamples, nproc)) for r in range(nproc)]
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(nproc) as pool:
+        parts = pool.map(_oracle_worker, [(desc, seed, c) for c in chunks])
+    dt = time.perf_counter() - t0
+    y = [0.0] * nsamples
+    for c, v in zip(chunks, parts):
+        for i, val in zip(c, v):
+            y[i] = val
+    return y, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--count", type=int, default=4096, help="samples per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-samples", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(samples shard by index across GPUs; see the design notes). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2306_13493_amd as ces
+    from paper_2306_13493_amd import workloads as W
+
+    torch.cuda.init()
+    ces.load()
+    ctx = ces.Context(0)
+    w = dict(W.C2)
+    count = args.count
+    t0 = time.perf_counter()
+    plan = ctx.plan(ces.level_desc(**w))
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    log("plan: n=%d J=%d setup %.1f ms" % (plan.info.n, plan.info.J, setup_ms))
+    seed = 0
+    step_id = 0
+    out = None
+
+    def step():
+        nonlocal step_id, out
+        out = plan.sample(seed, step_id * count, count, out=out)
+        step_id += 1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done (%d steps)" % args.warmup)
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    iters = []
+    ces.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    first_step = step_id
+    for k in range(args.steps):
+        ev[k][0].record()
+        step()
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ces.profile_read()
+    ces.profile_enable(False)
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    it = out["iters"].cpu().numpy()
+    status = out["status"].cpu().numpy()
+    value = args.steps * count / elapsed
+    log("timed: %d steps x %d samples in %.3f s -> %.1f samples/s; CG iterations mean %.2f max %d; failures %d"
+        % (args.steps, count, elapsed, value, it.mean(), it.max(), int((status != 0).sum())))
+
+    # dominant kernel: largest total time inside the timed region
+    name, (launches, ms, nbytes) = max(prof.items(), key=lambda kv: kv[1][1])
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    total_ms = sum(v[1] for v in prof.values())
+    roofline = {"bound": "hbm", "kernel": name, "symbol": KERNEL_SYMBOL.get(name, name),
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(ms * 1e3 / launches, 2), "launches": launches,
+                "algorithmic_bytes_per_launch": round(nbytes / launches),
+                "share_of_kernel_time": round(ms / total_ms, 4)}
+    all_bytes = sum(v[2] for v in prof.values())
+    solver_kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
+                          "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+                      for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    log("dominant kernel %s: %.1f GB/s (%.1f%% of 8 TB/s); whole path %.1f GB/s"
+        % (name, achieved, 100 * achieved / HBM_PEAK_GBS, all_bytes / (total_ms * 1e-3) / 1e9))
+
+    # parity of the timed path and the plain FP64 GPU path against the oracle
+    extra = {}
+    y_last = out["y"].cpu().numpy()
+    last_first = (step_id - 1) * count
+    cpu = None
+    if not args.no_cpu_baseline:
+        nproc = max(1, min(os.cpu_count() or 1, 16))
+        ns = args.cpu_samples or max(8, nproc)
+        log("cpu baseline: oracle on %d samples with %d processes ..." % (ns, nproc))
+        y_ref, dt = cpu_baseline(w, seed, ns, nproc)
+        y_ref = np.array(y_ref)
+        # same samples on the GPU (indices 0 .. ns-1)
+        g = plan.sample(seed, 0, ns)["y"].cpu().numpy()
+        rel = float(np.max(np.abs(g - y_ref) / np.abs(y_ref)))
+        cpu = {"value": round(ns / dt, 3), "unit": "samples/s", "cores": nproc, "kind": "oracle",
+               "sample": "samples 0..%d of the same workload (seed 0), FP64 NumPy/SciPy (SuperLU), "
+                         "%d processes x 1 thread, wall %.1f s" % (ns - 1, nproc, dt)}
+        extra["parity_vs_oracle_max_rel"] = rel
+        log("cpu baseline %.3f samples/s; GPU vs oracle max rel diff %.2e" % (ns / dt, rel))
+    if not args.no_fp64:
+        p64 = ctx.plan(ces.level_desc(**dict(w, precision="fp64")))
+        o64 = p64.sample(seed, 0, count)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        nrep = max(1, args.steps // 3)
+        for r in range(nrep):
+            o64 = p64.sample(seed, r * count, count, out=o64)
+        torch.cuda.synchronize()
+        v64 = nrep * count / (time.perf_counter() - t1)
+        om = plan.sample(seed, (nrep - 1) * count, count)
+        diff = float(torch.max(torch.abs(om["y"] - o64["y"]) / torch.abs(o64["y"])).item())
+        extra["fp64_plain_path"] = {"value": round(v64, 1), "unit": "samples/s",
+                                    "mixed_vs_fp64_max_rel_diff_Y": diff}
+        log("plain FP64 path %.1f samples/s; mixed vs FP64 max rel diff %.2e" % (v64, diff))
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(float(elapsed * 1e3 / args.steps), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "Matern nu=1 lambda=0.1 sigma2=1, 257x257 vertices, embedding 512x512 "
+                               "(grown to nonnegative), %d i.i.d. samples per step, f=1, u=0 on the boundary, "
+                               "QoI integral of u, float field+multigrid, double CG to 1e-10" % count,
+                   "samples_per_step": count, "precision": "mixed"},
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                       "p99": round(float(np.percentile(step_ms, 99)), 3),
+                       "per": "step of %d samples" % count},
+        "setup_ms": round(setup_ms, 2),
+        "cg_iterations_mean": round(float(it.mean()), 3),
+        "roofline": roofline,
+        "kernels": solver_kernels,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

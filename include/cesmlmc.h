@@ -179,6 +179,27 @@ int ces_field(ces_plan plan, uint64_t seed, uint64_t sample, double* z_fine_dev,
 int ces_solve(ces_plan plan, int32_t grid, int64_t count, const double* k_dev, double* u_dev,
               int32_t* iters_dev, void* hip_stream);
 
+/* ---- launch profiler (bench and roofline reporting) ------------------ */
+
+/* Per-kernel aggregate since the last read: HIP-event time summed over
+ * launches, and the algorithmic bytes those launches move (inputs read
+ * once, outputs written once; samples already converged are not counted). */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+    double bytes;
+} ces_profile_entry;
+
+/* Process-wide.  on != 0 starts recording HIP events around every library
+ * kernel launch (clearing earlier records); on == 0 stops. */
+int ces_profile_enable(int32_t on);
+
+/* Synchronises with the recorded launches, writes up to max_entries
+ * entries (largest total time first) to host memory and the number of
+ * kernels to *n_entries, then clears the records. */
+int ces_profile_read(ces_profile_entry* out, int32_t max_entries, int32_t* n_entries);
+
 const char* ces_last_error(void);
 
 #ifdef __cplusplus

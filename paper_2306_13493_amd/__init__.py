@@ -202,4 +202,19 @@ def normals(seed, q, stream_tag, first_e, count, device=0, stream=None):
     return out
 
 
-__all__ = ["Context", "Plan", "level_desc", "normals", "CesError", "LevelDesc", "PlanInfo", "load"]
+def profile_enable(on=True):
+    """Start (clearing earlier records) or stop the library's launch profiler."""
+    check(load().ces_profile_enable(1 if on else 0))
+
+
+def profile_read(max_entries=64):
+    """Per-kernel {name: (launches, total_ms, algorithmic_bytes)}; clears."""
+    lib = load()
+    buf = (_lib.ProfileEntry * max_entries)()
+    n = ctypes.c_int32()
+    check(lib.ces_profile_read(buf, max_entries, ctypes.byref(n)))
+    return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms, buf[i].bytes)
+            for i in range(min(n.value, max_entries))}
+
+
+__all__ = ["Context", "Plan", "level_desc", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc", "PlanInfo", "load"]

@@ -42,6 +42,10 @@ class PlanInfo(ctypes.Structure):
         ("bytes_per_sample", c_size_t)]
 
 
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", c_int64), ("total_ms", c_double), ("bytes", c_double)]
+
+
 # name -> (restype, argtypes); every function declared in include/cesmlmc.h
 SIGNATURES = {
     "ces_level_desc_default": (None, [ctypes.POINTER(LevelDesc)]),
@@ -57,6 +61,8 @@ SIGNATURES = {
     "ces_plan_mask": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ces_field": (c_int32, [c_void_p, c_uint64, c_uint64, c_dptr, c_dptr, c_void_p]),
     "ces_solve": (c_int32, [c_void_p, c_int32, c_int64, c_dptr, c_dptr, c_dptr, c_void_p]),
+    "ces_profile_enable": (c_int32, [c_int32]),
+    "ces_profile_read": (c_int32, [ctypes.POINTER(ProfileEntry), c_int32, ctypes.POINTER(c_int32)]),
     "ces_last_error": (ctypes.c_char_p, []),
 }
 

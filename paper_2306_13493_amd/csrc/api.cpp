@@ -476,6 +476,27 @@ void ces_level_desc_default(ces_level_desc* d) {
 
 const char* ces_last_error(void) { return g_err.c_str(); }
 
+int ces_profile_enable(int32_t on) {
+    Profiler::get().enable(on != 0);
+    return CES_OK;
+}
+
+int ces_profile_read(ces_profile_entry* out, int32_t max_entries, int32_t* n_entries) {
+    if (max_entries < 0 || (max_entries > 0 && !out)) return fail(CES_ERR_ARG, "profile output buffer");
+    std::vector<Profiler::Entry> v;
+    if (Profiler::get().read(v) != 0) return fail(CES_ERR_DEVICE, "profile events could not be read");
+    const int n = std::min<int>((int)v.size(), max_entries);
+    for (int i = 0; i < n; ++i) {
+        std::memset(&out[i], 0, sizeof(out[i]));
+        std::strncpy(out[i].name, v[i].name.c_str(), sizeof(out[i].name) - 1);
+        out[i].launches = v[i].launches;
+        out[i].total_ms = v[i].ms;
+        out[i].bytes = v[i].bytes;
+    }
+    if (n_entries) *n_entries = (int32_t)v.size();
+    return CES_OK;
+}
+
 int ces_context_create(int device, size_t mem_budget_bytes, ces_context* out) {
     if (!out) return fail(CES_ERR_ARG, "out is NULL");
     *out = nullptr;

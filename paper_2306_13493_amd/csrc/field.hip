@@ -204,9 +204,20 @@ hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2
     auto kr = k_field_rows<T, E, MODE, NF>;
     hipError_t e = allow_lds(kr, lds1);
     if (e != hipSuccess) return e;
+    // algorithmic bytes: amplitudes once, the pruned intermediate written
+    // then read, k written at the fine (and coarse) nodes
+    const double sT = sizeof(T);
+    const double inter = (double)b.units * NF * (b.m + 1) * b.n * 2.0 * sT;
+    const double slots = (double)b.units * (MODE == MODE_PAIR ? 2 : 1);
+    const double kout = slots * sT * ((double)(b.m + 1) * (b.m + 1) +
+                                      (b.coarse ? (double)(b.m / 2 + 1) * (b.m / 2 + 1) : 0.0));
+    Profiler& P = Profiler::get();
+    int idx = P.begin(st);
     hipLaunchKernelGGL(kr, dim3(b.n / L1, b.units), dim3(kBlock), lds1, st, b, L1);
+    P.end(idx, "field_rows", (double)NF * b.n * b.n * sT + inter, 1, st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     dim3 g2(cdiv(b.m + 1, L2), b.units, NF);
+    idx = P.begin(st);
     if (b.zf) {
         auto kc = k_field_cols<T, E, MODE, NF, true>;
         if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
@@ -216,6 +227,7 @@ hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2
         if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
         hipLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, b, L2);
     }
+    P.end(idx, "field_cols", inter + kout, 1, st);
     return hipGetLastError();
 }
 

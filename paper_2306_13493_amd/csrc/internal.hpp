@@ -3,6 +3,7 @@
 
 #include <memory>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 #include "fft_lds.hpp"
@@ -92,5 +93,37 @@ std::unique_ptr<Solver> make_solver(const SolverCfg& cfg, int capacity, bool is_
 hipError_t launch_finalize(const double* qf, const double* qc, const int* itf, const int* itc,
                            int slot0, int nslots, long long out0, double* y, double* yf, double* yc,
                            int* iters, int* status, hipStream_t st);
+
+// ------------------------------------------------------------- profiler
+// Process-wide; records HIP events around launches while enabled.
+class Profiler {
+public:
+    struct Entry {
+        std::string name;
+        long long launches = 0;
+        double ms = 0.0;
+        double bytes = 0.0;   // algorithmic bytes summed over launches
+    };
+    static Profiler& get();
+    bool on() const { return on_; }
+    void enable(bool on);
+    int begin(hipStream_t st);   // -1 when off
+    void end(int idx, const char* name, double bytes_per_sample, int samples, hipStream_t st);
+    void set_samples(int idx, int samples);
+    int read(std::vector<Entry>& out);   // synchronises; clears the records
+
+private:
+    struct Rec {
+        const char* name = nullptr;
+        hipEvent_t a = nullptr, b = nullptr;
+        double bps = 0.0;
+        int samples = 0;
+    };
+    bool on_ = false;
+    std::vector<Rec> recs_;
+    std::vector<hipEvent_t> pool_;
+    size_t used_ = 0;
+    hipEvent_t event();
+};
 
 }  // namespace ces

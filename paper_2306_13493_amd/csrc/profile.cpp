@@ -1,0 +1,76 @@
+// Launch profiler: HIP events around kernel launches, aggregated by kernel
+// name with the algorithmic bytes each launch moves.  Off unless enabled.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace ces {
+
+Profiler& Profiler::get() {
+    static Profiler p;
+    return p;
+}
+
+hipEvent_t Profiler::event() {
+    if (used_ < pool_.size()) return pool_[used_++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pool_.push_back(e);
+    ++used_;
+    return e;
+}
+
+int Profiler::begin(hipStream_t st) {
+    if (!on_) return -1;
+    Rec r;
+    r.a = event();
+    r.b = event();
+    if (!r.a || !r.b) return -1;
+    if (hipEventRecord(r.a, st) != hipSuccess) return -1;
+    recs_.push_back(r);
+    return (int)recs_.size() - 1;
+}
+
+void Profiler::end(int idx, const char* name, double bytes_per_sample, int samples, hipStream_t st) {
+    if (idx < 0 || idx >= (int)recs_.size()) return;
+    Rec& r = recs_[idx];
+    r.name = name;
+    r.bps = bytes_per_sample;
+    r.samples = samples;
+    (void)hipEventRecord(r.b, st);
+}
+
+void Profiler::set_samples(int idx, int samples) {
+    if (idx >= 0 && idx < (int)recs_.size()) recs_[idx].samples = samples;
+}
+
+void Profiler::enable(bool on) {
+    on_ = on;
+    recs_.clear();
+    used_ = 0;
+}
+
+int Profiler::read(std::vector<Entry>& out) {
+    out.clear();
+    std::map<std::string, Entry> agg;
+    for (const Rec& r : recs_) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return -1;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return -1;
+        Entry& e = agg[r.name ? r.name : "?"];
+        e.name = r.name ? r.name : "?";
+        e.launches += 1;
+        e.ms += ms;
+        e.bytes += r.bps * (double)r.samples;
+    }
+    for (auto& kv : agg) out.push_back(kv.second);
+    std::sort(out.begin(), out.end(), [](const Entry& a, const Entry& b) { return a.ms > b.ms; });
+    recs_.clear();
+    used_ = 0;
+    return 0;
+}
+
+}  // namespace ces

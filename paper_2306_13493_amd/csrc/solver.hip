@@ -818,6 +818,11 @@ __global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ X, Lv
     }
 }
 
+// copy of the active-sample counter (launch profiler only)
+__global__ void k_snapshot(const int* cnt, int* dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *cnt;
+}
+
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* qf, const double* qc, const int* itf,
                                                      const int* itc, int slot0, int nslots, long long out0,
                                                      double* y, double* yf, double* yc, int* iters, int* status) {
@@ -898,6 +903,7 @@ public:
         o_q_ = take((size_t)cap * 8);
         o_it_ = take((size_t)cap * 4);
         o_cnt_ = take(64);
+        o_hist_ = take((size_t)(cfg.maxit + 2) * sizeof(int));
         bytes_ = off;
     }
     ~SolverImpl() override {
@@ -934,32 +940,48 @@ public:
         const T* k0 = reinterpret_cast<const T*>(kv);
         Scal* scal = ptr<Scal>(o_scal_);
         int* cnt = ptr<int>(o_cnt_);
+        int* hist = ptr<int>(o_hist_);
         double* part = ptr<double>(o_part_);
         double* part2 = ptr<double>(o_part2_);
+        const bool prof = Profiler::get().on();
+        recs_.clear();
+        const double sT = sizeof(T);
         // coefficient hierarchy
         for (int l = 0; l + 1 < nlev_; ++l) {
             const T* kf = l == 0 ? k0 : ptr<T>(o_k_[l - 1]);
             const long long fss = l == 0 ? kss : lv_[l].ss;
-            hipLaunchKernelGGL(k_coarsen<T>, dim3(cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S),
-                               dim3(kBlock), 0, st, kf, fss, lv_[l], ptr<T>(o_k_[l]), lv_[l + 1], scal);
+            launch("coarsen", (nv(l) + nv(l + 1)) * sT, S, -1, st, [&] {
+                hipLaunchKernelGGL(k_coarsen<T>, dim3(cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S),
+                                   dim3(kBlock), 0, st, kf, fss, lv_[l], ptr<T>(o_k_[l]), lv_[l + 1], scal);
+            });
         }
         hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
         if (e != hipSuccess) return e;
         PcgArgs<T> pa = pcg_args(k0, kss, 0);
         pa.tiles_x = itx_;
         pa.ntiles = itiles_;
-        hipLaunchKernelGGL(k_pcg_init<T>, dim3(itiles_, S), dim3(kBlock), 0, st, pa);
+        launch("pcg_init", nv(0) * (sT + 48.0), S, -1, st, [&] {
+            hipLaunchKernelGGL(k_pcg_init<T>, dim3(itiles_, S), dim3(kBlock), 0, st, pa);
+        });
         const double rtol2 = cfg_.rtol * cfg_.rtol;
         hipLaunchKernelGGL(k_reduce<RED_BB>, dim3(S), dim3(kBlock), 0, st, part, part, itiles_, scal, rtol2, cfg_.maxit, cnt);
+        if (prof) hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, hist);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        int iters_run = 0;
         for (int it = 0; it < cfg_.maxit; ++it) {
-            vcycle(k0, kss, S, st);
+            iters_run = it + 1;
+            vcycle(k0, kss, S, it, st);
             hipLaunchKernelGGL(k_reduce<RED_RZ>, dim3(S), dim3(kBlock), 0, st, part, part2, rz_parts_, scal, rtol2, cfg_.maxit, cnt);
             PcgArgs<T> a = pcg_args(k0, kss, it);
-            hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_, S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
+            launch("pcg_dir", nu(0) * 32.0 + nv(0) * sT, S, it, st, [&] {
+                hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_, S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
+            });
             hipLaunchKernelGGL(k_reduce<RED_PQ>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
-            hipLaunchKernelGGL(k_pcg_update<T>, dim3(ptiles_, S), dim3(kBlock), 0, st, a);
+            launch("pcg_update", nu(0) * 48.0, S, it, st, [&] {
+                hipLaunchKernelGGL(k_pcg_update<T>, dim3(ptiles_, S), dim3(kBlock), 0, st, a);
+            });
             hipLaunchKernelGGL(k_reduce<RED_RR>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
+            if (prof) hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, hist + it + 1);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             // lagged convergence poll: read the count of iteration it-1
             // while iteration it is queued.
@@ -970,21 +992,46 @@ public:
                 if (hcnt_[(it - 1) & 1] == 0) break;
             }
         }
-        last_p_ = 0;
+        if (prof) {
+            // samples active in iteration it = counter after iteration it-1
+            std::vector<int> h(iters_run + 1);
+            if ((e = hipMemcpyAsync(h.data(), hist, h.size() * sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+            for (auto& r : recs_)
+                if (r.second >= 0) Profiler::get().set_samples(r.first, h[r.second]);
+        }
         return hipGetLastError();
     }
 
     hipError_t qoi(const void* kv, long long kss, int S, double* q, int* iters, hipStream_t st) override {
         if (S <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k_qoi<T>, dim3(S), dim3(kBlock), 0, st, ptr<double>(o_X_), lv_[0], cfg_.bc, cfg_.f,
-                           cfg_.qoi, cfg_.qx, cfg_.qy, reinterpret_cast<const T*>(kv), kss, ptr<Scal>(o_scal_),
-                           q ? q : ptr<double>(o_q_), iters ? iters : ptr<int>(o_it_));
+        launch("qoi", nv(0) * 8.0, S, -1, st, [&] {
+            hipLaunchKernelGGL(k_qoi<T>, dim3(S), dim3(kBlock), 0, st, ptr<double>(o_X_), lv_[0], cfg_.bc, cfg_.f,
+                               cfg_.qoi, cfg_.qx, cfg_.qy, reinterpret_cast<const T*>(kv), kss, ptr<Scal>(o_scal_),
+                               q ? q : ptr<double>(o_q_), iters ? iters : ptr<int>(o_it_));
+        });
         return hipGetLastError();
     }
 
 private:
     template <typename U>
     U* ptr(size_t off) const { return reinterpret_cast<U*>(reinterpret_cast<char*>(base_) + off); }
+
+    double nv(int l) const { return (double)lv_[l].w * lv_[l].w; }
+    double nu(int l) const { return (double)(lv_[l].m - 1) * (lv_[l].yhi - lv_[l].ylo + 1); }
+
+    // launch with an optional profiler record; it >= 0 ties the record's
+    // sample count to the samples active in CG iteration it
+    template <typename F>
+    void launch(const char* name, double bytes_per_sample, int S, int it, hipStream_t st, F&& f) {
+        Profiler& P = Profiler::get();
+        const int idx = P.begin(st);
+        f();
+        if (idx >= 0) {
+            P.end(idx, name, bytes_per_sample, S, st);
+            if (it >= 0) recs_.emplace_back(idx, it);
+        }
+    }
 
     PcgArgs<T> pcg_args(const T* k0, long long kss, int it) {
         PcgArgs<T> a{};
@@ -1010,7 +1057,8 @@ private:
     const T* klev(int l, const T* k0) const { return l == 0 ? k0 : ptr<T>(o_k_[l - 1]); }
     long long kss_lev(int l, long long kss0) const { return l == 0 ? kss0 : lv_[l].ss; }
 
-    void vcycle(const T* k0, long long kss, int S, hipStream_t st) {
+    void vcycle(const T* k0, long long kss, int S, int it, hipStream_t st) {
+        const double sT = sizeof(T);
         Scal* scal = ptr<Scal>(o_scal_);
         for (int l = 0; l < lb_; ++l) {
             const Lvl& L = lv_[l];
@@ -1025,10 +1073,13 @@ private:
             a.rhs = l == 0 ? (const void*)ptr<double>(o_R_) : (const void*)ptr<T>(o_rhs_[l - 1]);
             a.za = l == 0 ? ptr<T>(o_za0_) : ptr<T>(o_za_[l - 1]);
             a.scal = scal;
-            if (l == 0)
-                hipLaunchKernelGGL((k_smooth<T, SH, false, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
-            else
-                hipLaunchKernelGGL((k_smooth<T, SH, false, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+            const double rb = l == 0 ? 8.0 : sT;
+            launch(l == 0 ? "mg_pre_l0" : "mg_pre", nv(l) * sT + nu(l) * (rb + sT), S, it, st, [&] {
+                if (l == 0)
+                    hipLaunchKernelGGL((k_smooth<T, SH, false, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_smooth<T, SH, false, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+            });
             const Lvl& C = lv_[l + 1];
             const int ctx = cdiv(C.m - 1, CTX), cty = cdiv(C.yhi - C.ylo + 1, CTY);
             RestrictArgs<T> r{};
@@ -1042,10 +1093,12 @@ private:
             r.z = a.za;
             r.rhs_c = ptr<T>(o_rhs_[l]);
             r.scal = scal;
-            if (l == 0)
-                hipLaunchKernelGGL((k_restrict<T, CTX, CTY, true>), dim3(ctx * cty, S), dim3(kBlock), 0, st, r);
-            else
-                hipLaunchKernelGGL((k_restrict<T, CTX, CTY, false>), dim3(ctx * cty, S), dim3(kBlock), 0, st, r);
+            launch(l == 0 ? "mg_restrict_l0" : "mg_restrict", nv(l) * sT + nu(l) * (rb + sT) + nu(l + 1) * sT, S, it, st, [&] {
+                if (l == 0)
+                    hipLaunchKernelGGL((k_restrict<T, CTX, CTY, true>), dim3(ctx * cty, S), dim3(kBlock), 0, st, r);
+                else
+                    hipLaunchKernelGGL((k_restrict<T, CTX, CTY, false>), dim3(ctx * cty, S), dim3(kBlock), 0, st, r);
+            });
         }
         {
             BottomArgs<T> b{};
@@ -1060,15 +1113,20 @@ private:
             b.dot = ptr<double>(o_part_);
             b.dot2 = ptr<double>(o_part2_);
             b.q = ptr<double>(o_Q_);
-            if (lb_ == 0) {
-                b.rhs = ptr<double>(o_R_);
-                b.zout = ptr<double>(o_Z_);
-                hipLaunchKernelGGL((k_bottom<T, MB, true>), dim3(S), dim3(kBlock), 0, st, b);
-            } else {
-                b.rhs = ptr<T>(o_rhs_[lb_ - 1]);
-                b.zout = ptr<T>(o_zb_[lb_ - 1]);
-                hipLaunchKernelGGL((k_bottom<T, MB, false>), dim3(S), dim3(kBlock), 0, st, b);
-            }
+            double kb = 0.0;
+            for (int l = lb_; l < nlev_; ++l) kb += nv(l) * sT;
+            const double io = lb_ == 0 ? nu(0) * 32.0 : nu(lb_) * 2.0 * sT;
+            launch("mg_bottom", kb + io, S, it, st, [&] {
+                if (lb_ == 0) {
+                    b.rhs = ptr<double>(o_R_);
+                    b.zout = ptr<double>(o_Z_);
+                    hipLaunchKernelGGL((k_bottom<T, MB, true>), dim3(S), dim3(kBlock), 0, st, b);
+                } else {
+                    b.rhs = ptr<T>(o_rhs_[lb_ - 1]);
+                    b.zout = ptr<T>(o_zb_[lb_ - 1]);
+                    hipLaunchKernelGGL((k_bottom<T, MB, false>), dim3(S), dim3(kBlock), 0, st, b);
+                }
+            });
         }
         for (int l = lb_ - 1; l >= 0; --l) {
             const Lvl& L = lv_[l];
@@ -1089,10 +1147,15 @@ private:
             a.dot2 = ptr<double>(o_part2_);
             a.q = ptr<double>(o_Q_);
             a.scal = scal;
-            if (l == 0)
-                hipLaunchKernelGGL((k_smooth<T, SH, true, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
-            else
-                hipLaunchKernelGGL((k_smooth<T, SH, true, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+            // k, z_pre, rhs, coarse correction in; z out (level 0: r, q in and z out in double)
+            const double post = l == 0 ? nv(0) * sT + nu(0) * (sT + 8.0 + 8.0 + 8.0) + nu(1) * sT
+                                       : nv(l) * sT + nu(l) * 3.0 * sT + nu(l + 1) * sT;
+            launch(l == 0 ? "mg_post_l0" : "mg_post", post, S, it, st, [&] {
+                if (l == 0)
+                    hipLaunchKernelGGL((k_smooth<T, SH, true, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_smooth<T, SH, true, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+            });
         }
     }
 
@@ -1104,12 +1167,12 @@ private:
     int rz_parts_ = 0, max_parts_ = 0;
     size_t o_X_ = 0, o_R_ = 0, o_P0_ = 0, o_P1_ = 0, o_Q_ = 0, o_Z_ = 0, o_za0_ = 0;
     std::vector<size_t> o_k_, o_rhs_, o_za_, o_zb_;
-    size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0;
+    size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0, o_hist_ = 0;
+    std::vector<std::pair<int, int>> recs_;
     size_t bytes_ = 0;
     void* base_ = nullptr;
     int* hcnt_ = nullptr;
     hipEvent_t ev_[2] = {nullptr, nullptr};
-    int last_p_ = 0;
 };
 
 }  // namespace
