@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy first (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -89,6 +91,14 @@ def main():
 
     torch.cuda.init()
     ces.load()
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x %d bytes" % (a.numel() * 4))
+        del a, b
     ctx = ces.Context(0)
     w = dict(W.C2)
     count = args.count

@@ -58,6 +58,17 @@ __device__ __forceinline__ T block_max(T v, T* red) {
     return s;
 }
 
+// Work-item index of workgroup b in a 1-D grid of nb workgroups such that
+// each of the 8 XCDs (which receive workgroups round-robin, each with its
+// own L2) processes one contiguous range of work items: neighbouring tiles
+// of a sample then share an L2 and their halo rows are fetched once.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    constexpr int NX = 8;
+    const int per = nb / NX, rem = nb - per * NX;
+    const int x = b % NX, j = b / NX;
+    return x * per + (x < rem ? x : rem) + j;
+}
+
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace ces

@@ -78,266 +78,266 @@ __device__ __forceinline__ int tri_count(int i, int j, int m) {
     return c;
 }
 
-// ------------------------------------------------------------ LDS region
-// Nodes [ox, ox+RX) x [oy, oy+RY) of one sample's level, with k on a
-// one-node ring around it.
-template <typename T, int RX, int RY>
-struct Region {
-    T z[RY][RX];
-    T rhs[RY][RX];
-    T ce[RY][RX];
-    T cn[RY][RX];
-    T aux[RY][RX];  // inverse diagonal (smoothing) or residual (restriction)
-    T k[RY + 2][RX + 2];
-};
-
-template <typename T, int RX, int RY>
-struct RegionK {
-    const Region<T, RX, RY>& R;
-    int ox, oy;
-    __device__ T operator()(int gx, int gy) const { return R.k[gy - oy + 1][gx - ox + 1]; }
-};
-
-template <typename T, int RX, int RY>
-__device__ void region_load_k(Region<T, RX, RY>& R, const T* __restrict__ k, int ox, int oy, int m, int w) {
-    for (int t = threadIdx.x; t < (RX + 2) * (RY + 2); t += blockDim.x) {
-        const int y = t / (RX + 2), x = t - y * (RX + 2);
-        const int gx = ox - 1 + x, gy = oy - 1 + y;
-        R.k[y][x] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? k[(size_t)gy * w + gx] : T(0);
-    }
-}
-
-// conductances of every node of the region; aux = 1/diag at unknown nodes
-// that have all four neighbours inside the region (else 0).
-template <typename T, int RX, int RY>
-__device__ void region_conductances(Region<T, RX, RY>& R, int ox, int oy, int m, int bc, bool inv_diag) {
-    RegionK<T, RX, RY> K{R, ox, oy};
-    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
-        const int y = t / RX, x = t - y * RX;
-        R.ce[y][x] = cond_e<T>(ox + x, oy + y, m, K);
-        R.cn[y][x] = cond_n<T>(ox + x, oy + y, m, K);
-    }
-    __syncthreads();
-    if (inv_diag) {
-        for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
-            const int y = t / RX, x = t - y * RX;
-            T v = T(0);
-            if (x >= 1 && y >= 1 && x < RX - 1 && y < RY - 1 && is_unknown(ox + x, oy + y, m, bc)) {
-                const T d = R.ce[y][x] + R.ce[y][x - 1] + R.cn[y][x] + R.cn[y - 1][x];
-                v = T(1) / d;
-            }
-            R.aux[y][x] = v;
-        }
-    }
-}
-
-// ------------------------------------------------------------ kernels ---
+// ------------------------------------------------------- multigrid tiles
+// One tile of one sample's level.  The region is 64 columns x 8*SH rows:
+// the tile plus an H-node halo on every side.  A workgroup is 8 half-waves
+// of 32 lanes; half-wave hw owns region rows [hw*SH, hw*SH + SH) and lane k
+// owns the two columns 2k, 2k+1 of them, keeping z, rhs, inverse diagonal
+// and conductances of its 2*SH nodes in registers.  In a red-black
+// half-sweep exactly one of a lane's two nodes per row has the active
+// colour, and which one is the same for every lane of the workgroup, so the
+// update runs without masked-off lanes.  Neighbours come from registers
+// except the column across the lane boundary and the rows across the strip
+// boundary, which go through LDS.
+//
+// Conductances from per-triangle sums: for the square (i, j) (existing iff
+// 0 <= i, j <= m-1) let S1 = k_ij + k_i+1,j + k_i+1,j+1 (triangle below the
+// diagonal) and S2 = k_ij + k_i+1,j+1 + k_i,j+1 (above); then
+// c_E(i,j) = (S1(i,j) + S2(i,j-1))/6 and c_N(i,j) = (S2(i,j) + S1(i-1,j))/6,
+// with S = 0 for squares outside the mesh -- which is exactly the boundary
+// rule (only existing triangles contribute).
+//
+// PRE (H = 6): two sweeps (red, black, red, black) from z = 0, z written on
+// the tile, then the residual r - A z on the tile plus one ring and its
+// restriction P^T to the coarse nodes whose fine centre lies in the tile.
+// POST (H = 4): z_pre + P z_coarse, two sweeps (black, red, black, red),
+// z written on the tile; on level 0 also the partial sums r.z and z.q_old.
 template <typename T>
-struct SmoothArgs {
-    Lvl L;
+struct MgArgs {
+    Lvl L, C;            // this level, the next coarser level
     int bc, tiles_x, ntiles;
     const T* k;
     long long kss;
-    const void* rhs;    // double (level 0) or T
-    T* za;              // pre-smoothed z of this level (PRE output / POST input)
-    // POST only
-    const T* zc;        // coarse correction
-    Lvl C;
-    void* zout;         // double Z (level 0) or T zb
-    double* dot;        // level-0 POST: partial r.z per tile
-    double* dot2;       // level-0 POST: partial z.q_old per tile
-    const double* q;    // level-0 POST: q_old = A p_old
+    const void* rhs;     // level rhs: double (level 0) or T
+    T* za;               // pre-smoothed z (PRE output, POST input)
+    T* rhs_c;            // PRE: coarse rhs output
+    const T* zc;         // POST: coarse correction
+    T* zout;             // POST: smoothed z
+    double* dot;         // POST level 0: partial r.z per tile
+    double* dot2;        // POST level 0: partial z.q_old per tile
+    const double* q;     // POST level 0: q_old
     const Scal* scal;
 };
 
-// Smoothing step on one tile: the region is 64 columns x 4*SH rows (tile
-// plus a 4-node halo on every side).  Thread (strip, column) owns the SH
-// nodes of its column in its strip and keeps their z, rhs, inverse
-// diagonal and conductances in registers; only left/right neighbours and
-// the first/last node of a strip travel through LDS.  One wave = one strip
-// = 64 consecutive columns, so every LDS row access is conflict-free and
-// every global row access is one coalesced segment.
+template <typename T>
+__device__ __forceinline__ T fast_rcp(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_amdgcn_rcpf(v);
+    } else {
+        return T(1) / v;
+    }
+}
+
+template <typename T, int SH, int Q0>
+__device__ __forceinline__ void mg_half_sweep(T (&z)[SH][2], const T (&rhs)[SH][2], const T (&id)[SH][2],
+                                              const T (&ce)[SH][2], const T (&cw0)[SH], const T (&cn)[SH + 1][2],
+                                              T* sz, int lx0, int ly0, int RX, int RY) {
+#pragma unroll
+    for (int r = 0; r < SH; ++r) {
+        const int q = Q0 ^ (r & 1);
+        const int ly = ly0 + r;
+        T zE, zW, zN, zS;
+        if (q == 0) {
+            zE = z[r][1];
+            zW = sz[ly * RX + (lx0 > 0 ? lx0 - 1 : 0)];
+        } else {
+            zW = z[r][0];
+            zE = sz[ly * RX + (lx0 + 2 < RX ? lx0 + 2 : RX - 1)];
+        }
+        zN = (r < SH - 1) ? z[r + 1][q] : sz[(ly + 1 < RY ? ly + 1 : RY - 1) * RX + lx0 + q];
+        zS = (r > 0) ? z[r - 1][q] : sz[(ly > 0 ? ly - 1 : 0) * RX + lx0 + q];
+        const T cW = q == 0 ? cw0[r] : ce[r][0];
+        const T v = (rhs[r][q] + ce[r][q] * zE + cW * zW + cn[r + 1][q] * zN + cn[r][q] * zS) * id[r][q];
+        z[r][q] = v;
+        sz[ly * RX + lx0 + q] = v;
+    }
+    __syncthreads();
+}
+
 template <typename T, int SH, bool POST, bool L0>
-__global__ __launch_bounds__(kBlock) void k_smooth(SmoothArgs<T> a) {
-    constexpr int H = 4, RX = 64, NS = kBlock / RX, RY = NS * SH;
+__global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
+    constexpr int RX = 64, NH = kBlock / 32, RY = NH * SH;
+    constexpr int H = POST ? 4 : 6;
     constexpr int TX = RX - 2 * H, TY = RY - 2 * H;
-    __shared__ T sz[RY][RX];
-    __shared__ T sk[RY + 2][RX + 2];
-    __shared__ T szc[POST ? RY / 2 + 3 : 1][POST ? RX / 2 + 3 : 1];
+    constexpr int KX = RX + 2, KY = RY + 2;
+    __shared__ T sz[RY * RX];
+    __shared__ T sk[KY * KX];    // k (ring of one node); PRE reuses it for the residual
+    __shared__ T szc[POST ? (RY / 2 + 3) * (RX / 2 + 3) : 1];
     __shared__ double red[kBlock / 64];
-    const int s = blockIdx.y;
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = wi / a.ntiles;
+    const int tile = wi - s * a.ntiles;
     if (!a.scal[s].active) return;
-    const int tile = blockIdx.x;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = 1 + tx * TX, y0 = a.L.ylo + ty * TY;
     const int ox = x0 - H, oy = y0 - H;
     const int m = a.L.m, w = a.L.w, bc = a.bc;
     const T* kk = a.k + (size_t)s * a.kss;
-    for (int t = threadIdx.x; t < (RX + 2) * (RY + 2); t += blockDim.x) {
-        const int y = t / (RX + 2), x = t - y * (RX + 2);
+    for (int t = threadIdx.x; t < KX * KY; t += blockDim.x) {
+        const int y = t / KX, x = t - y * KX;
         const int gx = ox - 1 + x, gy = oy - 1 + y;
-        sk[y][x] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? kk[(size_t)gy * w + gx] : T(0);
+        sk[t] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? kk[(size_t)gy * w + gx] : T(0);
     }
-    const int cox = ox >> 1, coy = oy >> 1;  // floor for negative origins
+    constexpr int CX = RX / 2 + 3;
+    const int cox = ox >> 1, coy = oy >> 1;  // floor, also for negative origins
     if constexpr (POST) {
         const T* zc = a.zc + (size_t)s * a.C.ss;
         const int cm = a.C.m, cw = a.C.w;
-        for (int t = threadIdx.x; t < (RY / 2 + 3) * (RX / 2 + 3); t += blockDim.x) {
-            const int y = t / (RX / 2 + 3), x = t - y * (RX / 2 + 3);
+        for (int t = threadIdx.x; t < (RY / 2 + 3) * CX; t += blockDim.x) {
+            const int y = t / CX, x = t - y * CX;
             const int I = cox + x, J = coy + y;
-            szc[y][x] = is_unknown(I, J, cm, bc) ? zc[(size_t)J * cw + I] : T(0);
+            szc[t] = is_unknown(I, J, cm, bc) ? zc[(size_t)J * cw + I] : T(0);
         }
     }
     __syncthreads();
-    const int lx = threadIdx.x % RX;
-    const int ly0 = (threadIdx.x / RX) * SH;
-    const int gx = ox + lx;
-    auto K = [&](int xx, int yy) -> T { return sk[yy - oy + 1][xx - ox + 1]; };
-    T z[SH], rhs[SH], id[SH], cn[SH + 1], ce[SH], cwst[SH];
+    const int lane = threadIdx.x & 31, hw = threadIdx.x >> 5;
+    const int lx0 = 2 * lane, ly0 = hw * SH;
+    const int gx0 = ox + lx0;
+    // triangle sums of the squares with lower-left corner (lx, ly) (region coords)
+    auto Kl = [&](int lx, int ly) -> T { return sk[(ly + 1) * KX + lx + 1]; };
+    auto sq = [&](int lx, int ly) -> bool {
+        const int gx = ox + lx, gy = oy + ly;
+        return gx >= 0 && gx < m && gy >= 0 && gy < m;
+    };
+    T ce[SH][2], cw0[SH], cn[SH + 1][2];
+    {
+        T p2m = T(0), p2a = T(0), p2b = T(0);
+        const T sixth = T(1.0 / 6.0);
+#pragma unroll
+        for (int r = -1; r < SH; ++r) {
+            const int ly = ly0 + r;
+            const T k_m = Kl(lx0 - 1, ly), k_a = Kl(lx0, ly), k_b = Kl(lx0 + 1, ly), k_c = Kl(lx0 + 2, ly);
+            const T u_m = Kl(lx0 - 1, ly + 1), u_a = Kl(lx0, ly + 1), u_b = Kl(lx0 + 1, ly + 1),
+                    u_c = Kl(lx0 + 2, ly + 1);
+            const T s1m = sq(lx0 - 1, ly) ? k_m + k_a + u_a : T(0);
+            const T s2m = sq(lx0 - 1, ly) ? k_m + u_a + u_m : T(0);
+            const T s1a = sq(lx0, ly) ? k_a + k_b + u_b : T(0);
+            const T s2a = sq(lx0, ly) ? k_a + u_b + u_a : T(0);
+            const T s1b = sq(lx0 + 1, ly) ? k_b + k_c + u_c : T(0);
+            const T s2b = sq(lx0 + 1, ly) ? k_b + u_c + u_b : T(0);
+            if (r >= 0) {
+                ce[r][0] = (s1a + p2a) * sixth;
+                ce[r][1] = (s1b + p2b) * sixth;
+                cw0[r] = (s1m + p2m) * sixth;
+            }
+            cn[r + 1][0] = (s2a + s1m) * sixth;
+            cn[r + 1][1] = (s2b + s1a) * sixth;
+            p2m = s2m;
+            p2a = s2a;
+            p2b = s2b;
+        }
+    }
+    T z[SH][2], rhs[SH][2], id[SH][2];
     const T* zin = a.za + (size_t)s * a.L.ss;
     const T* rhsT = L0 ? nullptr : reinterpret_cast<const T*>(a.rhs) + (size_t)s * a.L.ss;
     const double* rhsD = L0 ? reinterpret_cast<const double*>(a.rhs) + (size_t)s * a.L.ss : nullptr;
-    cn[0] = cond_n<T>(gx, oy + ly0 - 1, m, K);
 #pragma unroll
-    for (int i = 0; i < SH; ++i) {
-        const int gy = oy + ly0 + i;
-        ce[i] = cond_e<T>(gx, gy, m, K);
-        cwst[i] = cond_e<T>(gx - 1, gy, m, K);
-        cn[i + 1] = cond_n<T>(gx, gy, m, K);
-        T r = T(0), zz = T(0), d = T(0);
-        if (is_unknown(gx, gy, m, bc)) {
-            const size_t o = (size_t)gy * w + gx;
-            r = L0 ? (T)rhsD[o] : rhsT[o];
-            d = T(1) / (ce[i] + cwst[i] + cn[i + 1] + cn[i]);
-            if constexpr (POST) {
-                const int I = (gx >> 1) - cox, J = (gy >> 1) - coy;
-                const bool ox1 = gx & 1, oy1 = gy & 1;
-                T p;
-                if (!ox1 && !oy1) p = szc[J][I];
-                else if (ox1 && !oy1) p = T(0.5) * (szc[J][I] + szc[J][I + 1]);
-                else if (!ox1 && oy1) p = T(0.5) * (szc[J][I] + szc[J + 1][I]);
-                else p = T(0.25) * ((szc[J][I] + szc[J][I + 1]) + (szc[J + 1][I] + szc[J + 1][I + 1]));
-                zz = zin[o] + p;
+    for (int r = 0; r < SH; ++r) {
+        const int gy = oy + ly0 + r;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int gx = gx0 + q;
+            T rr = T(0), zz = T(0), d = T(0);
+            if (is_unknown(gx, gy, m, bc)) {
+                const size_t o = (size_t)gy * w + gx;
+                rr = L0 ? (T)rhsD[o] : rhsT[o];
+                const T cW = q == 0 ? cw0[r] : ce[r][0];
+                d = fast_rcp(ce[r][q] + cW + cn[r + 1][q] + cn[r][q]);
+                if constexpr (POST) {
+                    const int I = (gx >> 1) - cox, J = (gy >> 1) - coy;
+                    const bool ox1 = gx & 1, oy1 = gy & 1;
+                    const T* c0 = szc + J * CX + I;
+                    T p;
+                    if (!ox1 && !oy1) p = c0[0];
+                    else if (ox1 && !oy1) p = T(0.5) * (c0[0] + c0[1]);
+                    else if (!ox1 && oy1) p = T(0.5) * (c0[0] + c0[CX]);
+                    else p = T(0.25) * ((c0[0] + c0[1]) + (c0[CX] + c0[CX + 1]));
+                    zz = zin[o] + p;
+                }
             }
+            z[r][q] = zz;
+            rhs[r][q] = rr;
+            id[r][q] = d;
+            sz[(ly0 + r) * RX + lx0 + q] = zz;
         }
-        z[i] = zz;
-        rhs[i] = r;
-        id[i] = d;
-        sz[ly0 + i][lx] = zz;
     }
     __syncthreads();
+    // the active column of row 0 for colour c is (c - ox - oy) & 1 (ly0 is even)
+    const int par = (ox + oy) & 1;
     const int c0 = POST ? 1 : 0;
 #pragma unroll
-    for (int h = 1; h <= H; ++h) {
-        const int c = (h & 1) ? c0 : 1 - c0;
-        const bool colx = lx >= h && lx < RX - h;
+    for (int h = 0; h < 4; ++h) {
+        const int c = (h & 1) ? 1 - c0 : c0;
+        if (((c - par) & 1) == 0)
+            mg_half_sweep<T, SH, 0>(z, rhs, id, ce, cw0, cn, sz, lx0, ly0, RX, RY);
+        else
+            mg_half_sweep<T, SH, 1>(z, rhs, id, ce, cw0, cn, sz, lx0, ly0, RX, RY);
+    }
+    // outputs on the tile (margin >= H)
+    double acc = 0.0, acc2 = 0.0;
 #pragma unroll
-        for (int i = 0; i < SH; ++i) {
-            const int ly = ly0 + i;
-            const bool upd = colx && ly >= h && ly < RY - h && (((gx + oy + ly) & 1) == c) && id[i] != T(0);
-            if (upd) {
-                const T zs = (i > 0) ? z[i - 1] : sz[ly - 1][lx];
-                const T zn = (i < SH - 1) ? z[i + 1] : sz[ly + 1][lx];
-                const T zE = sz[ly][lx + 1], zW = sz[ly][lx - 1];
-                const T v = (rhs[i] + ce[i] * zE + cwst[i] * zW + cn[i + 1] * zn + cn[i] * zs) * id[i];
-                z[i] = v;
-                sz[ly][lx] = v;
+    for (int r = 0; r < SH; ++r) {
+        const int ly = ly0 + r, gy = oy + ly;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int lx = lx0 + q, gx = gx0 + q;
+            if (lx < H || lx >= H + TX || ly < H || ly >= H + TY || !is_unknown(gx, gy, m, bc)) continue;
+            const size_t o = (size_t)s * a.L.ss + (size_t)gy * w + gx;
+            if (!POST) {
+                a.za[o] = z[r][q];
+            } else {
+                a.zout[o] = z[r][q];
+                if (L0) {
+                    acc += rhsD[(size_t)gy * w + gx] * (double)z[r][q];
+                    acc2 += a.q[o] * (double)z[r][q];
+                }
+            }
+        }
+    }
+    if constexpr (POST) {
+        if constexpr (L0) {
+            acc = block_sum(acc, red);
+            acc2 = block_sum(acc2, red);
+            if (threadIdx.x == 0) {
+                a.dot[(size_t)s * a.ntiles + tile] = acc;
+                a.dot2[(size_t)s * a.ntiles + tile] = acc2;
+            }
+        }
+        return;
+    } else {
+        // residual r - A z (difference form) into sk, on every region node
+        T* sres = sk;
+#pragma unroll
+        for (int r = 0; r < SH; ++r) {
+            const int ly = ly0 + r;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const T zp = z[r][q];
+                const T zE = q == 0 ? z[r][1] : sz[ly * RX + (lx0 + 2 < RX ? lx0 + 2 : RX - 1)];
+                const T zW = q == 1 ? z[r][0] : sz[ly * RX + (lx0 > 0 ? lx0 - 1 : 0)];
+                const T zN = (r < SH - 1) ? z[r + 1][q] : sz[(ly + 1 < RY ? ly + 1 : RY - 1) * RX + lx0 + q];
+                const T zS = (r > 0) ? z[r - 1][q] : sz[(ly > 0 ? ly - 1 : 0) * RX + lx0 + q];
+                const T cW = q == 0 ? cw0[r] : ce[r][0];
+                const T az = (ce[r][q] * (zp - zE) + cW * (zp - zW)) + (cn[r + 1][q] * (zp - zN) + cn[r][q] * (zp - zS));
+                sres[ly * RX + lx0 + q] = id[r][q] != T(0) ? rhs[r][q] - az : T(0);
             }
         }
         __syncthreads();
-    }
-    double acc = 0.0, acc2 = 0.0;
-    if (lx >= H && lx < H + TX) {
-#pragma unroll
-        for (int i = 0; i < SH; ++i) {
-            const int ly = ly0 + i;
-            const int gy = oy + ly;
-            if (ly < H || ly >= H + TY || !is_unknown(gx, gy, m, bc)) continue;
-            const size_t o = (size_t)gy * w + gx;
-            if (!POST) {
-                a.za[(size_t)s * a.L.ss + o] = z[i];
-            } else if (L0) {
-                reinterpret_cast<double*>(a.zout)[(size_t)s * a.L.ss + o] = (double)z[i];
-                acc += rhsD[o] * (double)z[i];
-                acc2 += a.q[(size_t)s * a.L.ss + o] * (double)z[i];
-            } else {
-                reinterpret_cast<T*>(a.zout)[(size_t)s * a.L.ss + o] = z[i];
-            }
+        // coarse nodes whose fine centre (2I, 2J) lies in the tile
+        const int I0 = (x0 + 1) >> 1, J0 = (y0 + 1) >> 1;
+        const int nI = ((x0 + TX + 1) >> 1) - I0, nJ = ((y0 + TY + 1) >> 1) - J0;
+        const int cm = a.C.m, cwid = a.C.w;
+        T* rc = a.rhs_c + (size_t)s * a.C.ss;
+        for (int t = threadIdx.x; t < nI * nJ; t += blockDim.x) {
+            const int jj = t / nI, ii = t - jj * nI;
+            const int I = I0 + ii, J = J0 + jj;
+            if (!is_unknown(I, J, cm, bc)) continue;
+            const int lx = 2 * I - ox, ly = 2 * J - oy;
+            const T* c0 = sres + ly * RX + lx;
+            const T v = c0[0] + T(0.5) * ((c0[-1] + c0[1]) + (c0[-RX] + c0[RX])) +
+                        T(0.25) * ((c0[-RX - 1] + c0[-RX + 1]) + (c0[RX - 1] + c0[RX + 1]));
+            rc[(size_t)J * cwid + I] = v;
         }
-    }
-    if constexpr (POST && L0) {
-        acc = block_sum(acc, red);
-        acc2 = block_sum(acc2, red);
-        if (threadIdx.x == 0) {
-            a.dot[(size_t)s * a.ntiles + tile] = acc;
-            a.dot2[(size_t)s * a.ntiles + tile] = acc2;
-        }
-    }
-}
-
-template <typename T>
-struct RestrictArgs {
-    Lvl L, C;
-    int bc, tiles_x;
-    const T* k;
-    long long kss;
-    const void* rhs;   // level rhs: double (level 0) or T
-    const T* z;        // pre-smoothed z of the level
-    T* rhs_c;          // coarse rhs (output)
-    const Scal* scal;
-};
-
-// rhs_c = P^T (rhs - A z) on a CTX x CTY tile of coarse nodes.
-template <typename T, int CTX, int CTY, bool L0>
-__global__ __launch_bounds__(kBlock) void k_restrict(RestrictArgs<T> a) {
-    constexpr int RX = 2 * CTX + 3, RY = 2 * CTY + 3;
-    __shared__ Region<T, RX, RY> R;
-    const int s = blockIdx.y;
-    if (!a.scal[s].active) return;
-    const int tile = blockIdx.x;
-    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
-    const int cx0 = 1 + tx * CTX, cy0 = a.C.ylo + ty * CTY;
-    const int ox = 2 * cx0 - 2, oy = 2 * cy0 - 2;
-    const int m = a.L.m, w = a.L.w;
-    region_load_k(R, a.k + (size_t)s * a.kss, ox, oy, m, w);
-    const T* zin = a.z + (size_t)s * a.L.ss;
-    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
-        const int y = t / RX, x = t - y * RX;
-        const int gx = ox + x, gy = oy + y;
-        T r = T(0), z = T(0);
-        if (is_unknown(gx, gy, m, a.bc)) {
-            const size_t o = (size_t)gy * w + gx;
-            r = L0 ? (T)(reinterpret_cast<const double*>(a.rhs)[(size_t)s * a.L.ss + o])
-                   : reinterpret_cast<const T*>(a.rhs)[(size_t)s * a.L.ss + o];
-            z = zin[o];
-        }
-        R.rhs[y][x] = r;
-        R.z[y][x] = z;
-    }
-    __syncthreads();
-    region_conductances(R, ox, oy, m, a.bc, false);
-    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
-        const int y = t / RX, x = t - y * RX;
-        T res = T(0);
-        if (x >= 1 && y >= 1 && x < RX - 1 && y < RY - 1 && is_unknown(ox + x, oy + y, m, a.bc)) {
-            const T zp = R.z[y][x];
-            const T az = (R.ce[y][x] * (zp - R.z[y][x + 1]) + R.ce[y][x - 1] * (zp - R.z[y][x - 1])) +
-                         (R.cn[y][x] * (zp - R.z[y + 1][x]) + R.cn[y - 1][x] * (zp - R.z[y - 1][x]));
-            res = R.rhs[y][x] - az;
-        }
-        R.aux[y][x] = res;
-    }
-    __syncthreads();
-    const int cm = a.C.m, cw = a.C.w;
-    for (int t = threadIdx.x; t < CTX * CTY; t += blockDim.x) {
-        const int b = t / CTX, aa = t - b * CTX;
-        const int I = cx0 + aa, J = cy0 + b;
-        if (!is_unknown(I, J, cm, a.bc)) continue;
-        const int x = 2 * aa + 2, y = 2 * b + 2;
-        const T v = R.aux[y][x] +
-                    T(0.5) * ((R.aux[y][x - 1] + R.aux[y][x + 1]) + (R.aux[y - 1][x] + R.aux[y + 1][x])) +
-                    T(0.25) * ((R.aux[y - 1][x - 1] + R.aux[y - 1][x + 1]) + (R.aux[y + 1][x - 1] + R.aux[y + 1][x + 1]));
-        a.rhs_c[(size_t)s * a.C.ss + (size_t)J * cw + I] = v;
     }
 }
 
@@ -350,7 +350,7 @@ struct BottomArgs {
     const T* k[8];     // k of each level
     long long kss[8];
     const void* rhs;   // level-0-of-bottom rhs: double (global level 0) or T
-    void* zout;        // double Z (global level 0) or T zb
+    void* zout;        // z of the bottom's finest level
     double* dot;       // global level 0: partial r.z (1 per sample)
     double* dot2;      // global level 0: partial z.q_old
     const double* q;   // global level 0: q_old
@@ -534,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
         if (L0) {
             const size_t o = (size_t)s * a.L[0].ss + t;
             const double r = reinterpret_cast<const double*>(a.rhs)[o];
-            reinterpret_cast<double*>(a.zout)[o] = (double)z[t];
+            reinterpret_cast<T*>(a.zout)[o] = z[t];
             acc += r * (double)z[t];
             acc2 += a.q[o] * (double)z[t];
         } else {
@@ -583,7 +583,8 @@ struct PcgArgs {
     double f, h2;
     const T* k;
     long long kss;
-    double *X, *R, *Pold, *Pnew, *Q, *Z;
+    double *X, *R, *Pold, *Pnew, *Q;
+    T* Z;   // preconditioned residual (precision of the multigrid)
     double* part;
     Scal* scal;
 };
@@ -608,7 +609,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs<T> a) {
     __shared__ KTile<T> K;
     __shared__ double red[kBlock / 64];
-    const int s = blockIdx.y, tile = blockIdx.x;
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = wi / a.ntiles, tile = wi - s * a.ntiles;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = tx * PTX, y0 = ty * PTY;
     const int m = a.L.m, w = a.L.w;
@@ -639,7 +641,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs<T> a) {
         a.Pold[o] = 0.0;
         a.Pnew[o] = 0.0;
         a.Q[o] = 0.0;
-        a.Z[o] = 0.0;
+        a.Z[o] = T(0);
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
@@ -651,7 +653,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
     __shared__ KTile<T> K;
     __shared__ double P[PTY + 2][PTX + 2];
     __shared__ double red[kBlock / 64];
-    const int s = blockIdx.y, tile = blockIdx.x;
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = wi / a.ntiles, tile = wi - s * a.ntiles;
     const Scal sc = a.scal[s];
     if (!sc.active) return;
     // flexible (Polak-Ribiere) beta = z_new.(r_new - r_old) / z_old.r_old
@@ -668,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
         double v = 0.0;
         if (is_unknown(gx, gy, m, a.bc)) {
             const size_t o = base + (size_t)gy * w + gx;
-            v = a.Z[o] + beta * a.Pold[o];
+            v = (double)a.Z[o] + beta * a.Pold[o];
         }
         P[y][x] = v;
     }
@@ -697,7 +700,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(PcgArgs<T> a) {
     __shared__ double red[kBlock / 64];
-    const int s = blockIdx.y, tile = blockIdx.x;
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = wi / a.ntiles, tile = wi - s * a.ntiles;
     const Scal sc = a.scal[s];
     if (!sc.active) return;
     const double alpha = sc.rz / sc.pq;
@@ -848,11 +852,11 @@ template <typename T>
 class SolverImpl final : public Solver {
 public:
     // tile shapes by precision (LDS <= 64 KiB per workgroup)
-    static constexpr int SH = 8;                       // rows per thread
-    static constexpr int TX = 64 - 8;                  // smoothing tile (64 x 4*SH region)
-    static constexpr int TY = (kBlock / 64) * SH - 8;
-    static constexpr int CTX = 32;
-    static constexpr int CTY = sizeof(T) == 4 ? 8 : 4;
+    // multigrid tile: 64 columns x 8*SH rows region (SH rows per half-wave)
+    static constexpr int SH = sizeof(T) == 4 ? 8 : 4;
+    static constexpr int RYT = (kBlock / 32) * SH;
+    static constexpr int PRE_TX = 64 - 12, PRE_TY = RYT - 12;   // halo 6
+    static constexpr int POST_TX = 64 - 8, POST_TY = RYT - 8;   // halo 4
     static constexpr int MB = sizeof(T) == 4 ? 32 : 16;
 
     SolverImpl(const SolverCfg& cfg, int cap) : cfg_(cfg), cap_(cap) {
@@ -875,8 +879,8 @@ public:
         itx_ = cdiv(L0.m + 1, PTX);
         ity_ = cdiv(L0.m + 1, PTY);
         itiles_ = itx_ * ity_;
-        stx_ = cdiv(L0.m - 1, TX);
-        sty_ = cdiv(L0.yhi - L0.ylo + 1, TY);
+        stx_ = cdiv(L0.m - 1, POST_TX);
+        sty_ = cdiv(L0.yhi - L0.ylo + 1, POST_TY);
         rz_parts_ = lb_ == 0 ? 1 : stx_ * sty_;
         max_parts_ = std::max(std::max(ptiles_, itiles_), rz_parts_);
         // memory plan
@@ -888,7 +892,7 @@ public:
         };
         const size_t n0 = (size_t)cap * L0.ss;
         o_X_ = take(n0 * 8); o_R_ = take(n0 * 8); o_P0_ = take(n0 * 8); o_P1_ = take(n0 * 8);
-        o_Q_ = take(n0 * 8); o_Z_ = take(n0 * 8);
+        o_Q_ = take(n0 * 8); o_Z_ = take(n0 * sizeof(T));
         o_za0_ = take(n0 * sizeof(T));
         for (int l = 1; l < nlev_; ++l) {
             const size_t nl = (size_t)cap * lv_[l].ss * sizeof(T);
@@ -960,8 +964,8 @@ public:
         PcgArgs<T> pa = pcg_args(k0, kss, 0);
         pa.tiles_x = itx_;
         pa.ntiles = itiles_;
-        launch("pcg_init", nv(0) * (sT + 48.0), S, -1, st, [&] {
-            hipLaunchKernelGGL(k_pcg_init<T>, dim3(itiles_, S), dim3(kBlock), 0, st, pa);
+        launch("pcg_init", nv(0) * (2.0 * sT + 40.0), S, -1, st, [&] {
+            hipLaunchKernelGGL(k_pcg_init<T>, dim3(itiles_ * S), dim3(kBlock), 0, st, pa);
         });
         const double rtol2 = cfg_.rtol * cfg_.rtol;
         hipLaunchKernelGGL(k_reduce<RED_BB>, dim3(S), dim3(kBlock), 0, st, part, part, itiles_, scal, rtol2, cfg_.maxit, cnt);
@@ -973,12 +977,12 @@ public:
             vcycle(k0, kss, S, it, st);
             hipLaunchKernelGGL(k_reduce<RED_RZ>, dim3(S), dim3(kBlock), 0, st, part, part2, rz_parts_, scal, rtol2, cfg_.maxit, cnt);
             PcgArgs<T> a = pcg_args(k0, kss, it);
-            launch("pcg_dir", nu(0) * 32.0 + nv(0) * sT, S, it, st, [&] {
-                hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_, S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
+            launch("pcg_dir", nu(0) * (24.0 + sT) + nv(0) * sT, S, it, st, [&] {
+                hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
             });
             hipLaunchKernelGGL(k_reduce<RED_PQ>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
             launch("pcg_update", nu(0) * 48.0, S, it, st, [&] {
-                hipLaunchKernelGGL(k_pcg_update<T>, dim3(ptiles_, S), dim3(kBlock), 0, st, a);
+                hipLaunchKernelGGL(k_pcg_update<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a);
             });
             hipLaunchKernelGGL(k_reduce<RED_RR>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
             if (prof) hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, hist + it + 1);
@@ -1048,7 +1052,7 @@ private:
         a.Pold = ptr<double>((it & 1) ? o_P1_ : o_P0_);
         a.Pnew = ptr<double>((it & 1) ? o_P0_ : o_P1_);
         a.Q = ptr<double>(o_Q_);
-        a.Z = ptr<double>(o_Z_);
+        a.Z = ptr<T>(o_Z_);
         a.part = ptr<double>(o_part_);
         a.scal = ptr<Scal>(o_scal_);
         return a;
@@ -1057,47 +1061,35 @@ private:
     const T* klev(int l, const T* k0) const { return l == 0 ? k0 : ptr<T>(o_k_[l - 1]); }
     long long kss_lev(int l, long long kss0) const { return l == 0 ? kss0 : lv_[l].ss; }
 
+    MgArgs<T> mg_args(int l, const T* k0, long long kss, int tiles_x, int ntiles) {
+        MgArgs<T> a{};
+        a.L = lv_[l];
+        a.C = lv_[l + 1];
+        a.bc = cfg_.bc;
+        a.tiles_x = tiles_x;
+        a.ntiles = ntiles;
+        a.k = klev(l, k0);
+        a.kss = kss_lev(l, kss);
+        a.rhs = l == 0 ? (const void*)ptr<double>(o_R_) : (const void*)ptr<T>(o_rhs_[l - 1]);
+        a.za = l == 0 ? ptr<T>(o_za0_) : ptr<T>(o_za_[l - 1]);
+        a.scal = ptr<Scal>(o_scal_);
+        return a;
+    }
+
     void vcycle(const T* k0, long long kss, int S, int it, hipStream_t st) {
         const double sT = sizeof(T);
-        Scal* scal = ptr<Scal>(o_scal_);
         for (int l = 0; l < lb_; ++l) {
             const Lvl& L = lv_[l];
-            const int tx = cdiv(L.m - 1, TX), ty = cdiv(L.yhi - L.ylo + 1, TY);
-            SmoothArgs<T> a{};
-            a.L = L;
-            a.bc = cfg_.bc;
-            a.tiles_x = tx;
-            a.ntiles = tx * ty;
-            a.k = klev(l, k0);
-            a.kss = kss_lev(l, kss);
-            a.rhs = l == 0 ? (const void*)ptr<double>(o_R_) : (const void*)ptr<T>(o_rhs_[l - 1]);
-            a.za = l == 0 ? ptr<T>(o_za0_) : ptr<T>(o_za_[l - 1]);
-            a.scal = scal;
+            const int tx = cdiv(L.m - 1, PRE_TX), ty = cdiv(L.yhi - L.ylo + 1, PRE_TY);
+            MgArgs<T> a = mg_args(l, k0, kss, tx, tx * ty);
+            a.rhs_c = ptr<T>(o_rhs_[l]);
+            // k, rhs in; z_pre and the coarse rhs out
             const double rb = l == 0 ? 8.0 : sT;
-            launch(l == 0 ? "mg_pre_l0" : "mg_pre", nv(l) * sT + nu(l) * (rb + sT), S, it, st, [&] {
+            launch(l == 0 ? "mg_pre_l0" : "mg_pre", nv(l) * sT + nu(l) * (rb + sT) + nu(l + 1) * sT, S, it, st, [&] {
                 if (l == 0)
-                    hipLaunchKernelGGL((k_smooth<T, SH, false, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+                    hipLaunchKernelGGL((k_mg<T, SH, false, true>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
                 else
-                    hipLaunchKernelGGL((k_smooth<T, SH, false, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
-            });
-            const Lvl& C = lv_[l + 1];
-            const int ctx = cdiv(C.m - 1, CTX), cty = cdiv(C.yhi - C.ylo + 1, CTY);
-            RestrictArgs<T> r{};
-            r.L = L;
-            r.C = C;
-            r.bc = cfg_.bc;
-            r.tiles_x = ctx;
-            r.k = a.k;
-            r.kss = a.kss;
-            r.rhs = a.rhs;
-            r.z = a.za;
-            r.rhs_c = ptr<T>(o_rhs_[l]);
-            r.scal = scal;
-            launch(l == 0 ? "mg_restrict_l0" : "mg_restrict", nv(l) * sT + nu(l) * (rb + sT) + nu(l + 1) * sT, S, it, st, [&] {
-                if (l == 0)
-                    hipLaunchKernelGGL((k_restrict<T, CTX, CTY, true>), dim3(ctx * cty, S), dim3(kBlock), 0, st, r);
-                else
-                    hipLaunchKernelGGL((k_restrict<T, CTX, CTY, false>), dim3(ctx * cty, S), dim3(kBlock), 0, st, r);
+                    hipLaunchKernelGGL((k_mg<T, SH, false, false>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
             });
         }
         {
@@ -1109,17 +1101,17 @@ private:
                 b.k[l] = klev(lb_ + l, k0);
                 b.kss[l] = kss_lev(lb_ + l, kss);
             }
-            b.scal = scal;
+            b.scal = ptr<Scal>(o_scal_);
             b.dot = ptr<double>(o_part_);
             b.dot2 = ptr<double>(o_part2_);
             b.q = ptr<double>(o_Q_);
             double kb = 0.0;
             for (int l = lb_; l < nlev_; ++l) kb += nv(l) * sT;
-            const double io = lb_ == 0 ? nu(0) * 32.0 : nu(lb_) * 2.0 * sT;
+            const double io = lb_ == 0 ? nu(0) * (24.0 + sT) : nu(lb_) * 2.0 * sT;
             launch("mg_bottom", kb + io, S, it, st, [&] {
                 if (lb_ == 0) {
                     b.rhs = ptr<double>(o_R_);
-                    b.zout = ptr<double>(o_Z_);
+                    b.zout = ptr<T>(o_Z_);
                     hipLaunchKernelGGL((k_bottom<T, MB, true>), dim3(S), dim3(kBlock), 0, st, b);
                 } else {
                     b.rhs = ptr<T>(o_rhs_[lb_ - 1]);
@@ -1130,31 +1122,21 @@ private:
         }
         for (int l = lb_ - 1; l >= 0; --l) {
             const Lvl& L = lv_[l];
-            const int tx = cdiv(L.m - 1, TX), ty = cdiv(L.yhi - L.ylo + 1, TY);
-            SmoothArgs<T> a{};
-            a.L = L;
-            a.C = lv_[l + 1];
-            a.bc = cfg_.bc;
-            a.tiles_x = tx;
-            a.ntiles = tx * ty;
-            a.k = klev(l, k0);
-            a.kss = kss_lev(l, kss);
-            a.rhs = l == 0 ? (const void*)ptr<double>(o_R_) : (const void*)ptr<T>(o_rhs_[l - 1]);
-            a.za = l == 0 ? ptr<T>(o_za0_) : ptr<T>(o_za_[l - 1]);
+            const int tx = cdiv(L.m - 1, POST_TX), ty = cdiv(L.yhi - L.ylo + 1, POST_TY);
+            MgArgs<T> a = mg_args(l, k0, kss, tx, tx * ty);
             a.zc = ptr<T>(o_zb_[l]);
-            a.zout = l == 0 ? (void*)ptr<double>(o_Z_) : (void*)ptr<T>(o_zb_[l - 1]);
+            a.zout = l == 0 ? ptr<T>(o_Z_) : ptr<T>(o_zb_[l - 1]);
             a.dot = ptr<double>(o_part_);
             a.dot2 = ptr<double>(o_part2_);
             a.q = ptr<double>(o_Q_);
-            a.scal = scal;
-            // k, z_pre, rhs, coarse correction in; z out (level 0: r, q in and z out in double)
-            const double post = l == 0 ? nv(0) * sT + nu(0) * (sT + 8.0 + 8.0 + 8.0) + nu(1) * sT
+            // k, z_pre, rhs, coarse correction in; z out (level 0: r, q_old in for the dots)
+            const double post = l == 0 ? nv(0) * sT + nu(0) * (sT + 8.0 + 8.0 + sT) + nu(1) * sT
                                        : nv(l) * sT + nu(l) * 3.0 * sT + nu(l + 1) * sT;
             launch(l == 0 ? "mg_post_l0" : "mg_post", post, S, it, st, [&] {
                 if (l == 0)
-                    hipLaunchKernelGGL((k_smooth<T, SH, true, true>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+                    hipLaunchKernelGGL((k_mg<T, SH, true, true>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
                 else
-                    hipLaunchKernelGGL((k_smooth<T, SH, true, false>), dim3(tx * ty, S), dim3(kBlock), 0, st, a);
+                    hipLaunchKernelGGL((k_mg<T, SH, true, false>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
             });
         }
     }
