@@ -106,8 +106,10 @@ template <typename T>
 struct MgArgs {
     Lvl L, C;            // this level, the next coarser level
     int bc, tiles_x, ntiles;
-    const T* k;
+    const T* k;          // level 0: nodal k
     long long kss;
+    const T* ce;         // coarser levels: stored edge conductances (stride L.ss)
+    const T* cn;
     const void* rhs;     // level rhs: double (level 0) or T
     T* za;               // pre-smoothed z (PRE output, POST input)
     T* rhs_c;            // PRE: coarse rhs output
@@ -172,11 +174,13 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
     const int x0 = 1 + tx * TX, y0 = a.L.ylo + ty * TY;
     const int ox = x0 - H, oy = y0 - H;
     const int m = a.L.m, w = a.L.w, bc = a.bc;
-    const T* kk = a.k + (size_t)s * a.kss;
-    for (int t = threadIdx.x; t < KX * KY; t += blockDim.x) {
-        const int y = t / KX, x = t - y * KX;
-        const int gx = ox - 1 + x, gy = oy - 1 + y;
-        sk[t] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? kk[(size_t)gy * w + gx] : T(0);
+    if constexpr (L0) {
+        const T* kk = a.k + (size_t)s * a.kss;
+        for (int t = threadIdx.x; t < KX * KY; t += blockDim.x) {
+            const int y = t / KX, x = t - y * KX;
+            const int gx = ox - 1 + x, gy = oy - 1 + y;
+            sk[t] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? kk[(size_t)gy * w + gx] : T(0);
+        }
     }
     constexpr int CX = RX / 2 + 3;
     const int cox = ox >> 1, coy = oy >> 1;  // floor, also for negative origins
@@ -200,7 +204,26 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
         return gx >= 0 && gx < m && gy >= 0 && gy < m;
     };
     T ce[SH][2], cw0[SH], cn[SH + 1][2];
-    {
+    if constexpr (!L0) {
+        // coarser levels: stored conductances (zero outside the mesh)
+        const T* CEg = a.ce + (size_t)s * a.L.ss;
+        const T* CNg = a.cn + (size_t)s * a.L.ss;
+        auto ld = [&](const T* g, int gx, int gy) -> T {
+            return (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? g[(size_t)gy * w + gx] : T(0);
+        };
+#pragma unroll
+        for (int q = 0; q < 2; ++q) cn[0][q] = ld(CNg, gx0 + q, oy + ly0 - 1);
+#pragma unroll
+        for (int r = 0; r < SH; ++r) {
+            const int gy = oy + ly0 + r;
+            cw0[r] = ld(CEg, gx0 - 1, gy);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                ce[r][q] = ld(CEg, gx0 + q, gy);
+                cn[r + 1][q] = ld(CNg, gx0 + q, gy);
+            }
+        }
+    } else {
         T p2m = T(0), p2a = T(0), p2b = T(0);
         const T sixth = T(1.0 / 6.0);
 #pragma unroll
@@ -347,8 +370,10 @@ struct BottomArgs {
     int nl;            // levels handled here: m0, m0/2, ..., 2
     int bc;
     Lvl L[8];
-    const T* k[8];     // k of each level
-    long long kss[8];
+    const T* k0;       // k of the global level 0 (when it is the bottom's first level)
+    long long kss0;
+    const T* ce[8];    // stored edge conductances of coarse levels (stride L[l].ss)
+    const T* cn[8];
     const void* rhs;   // level-0-of-bottom rhs: double (global level 0) or T
     void* zout;        // z of the bottom's finest level
     double* dot;       // global level 0: partial r.z (1 per sample)
@@ -406,15 +431,25 @@ __global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
     // conductances and inverse diagonals of every level
     for (int l = 0; l < a.nl; ++l) {
         const int m = a.L[l].m, w = a.L[l].w;
-        const T* kg = a.k[l] + (size_t)s * a.kss[l];
-        for (int t = threadIdx.x; t < w * w; t += blockDim.x) tmp[t] = kg[t];
-        __syncthreads();
-        auto K = [&](int gx, int gy) -> T { return tmp[gy * w + gx]; };
-        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-            const int y = t / w, x = t - y * w;
-            ce[off[l] + t] = cond_e<T>(x, y, m, K);
-            cn[off[l] + t] = cond_n<T>(x, y, m, K);
-            z[off[l] + t] = T(0);
+        if (L0 && l == 0) {
+            const T* kg = a.k0 + (size_t)s * a.kss0;
+            for (int t = threadIdx.x; t < w * w; t += blockDim.x) tmp[t] = kg[t];
+            __syncthreads();
+            auto K = [&](int gx, int gy) -> T { return tmp[gy * w + gx]; };
+            for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+                const int y = t / w, x = t - y * w;
+                ce[off[l] + t] = cond_e<T>(x, y, m, K);
+                cn[off[l] + t] = cond_n<T>(x, y, m, K);
+                z[off[l] + t] = T(0);
+            }
+        } else {
+            const T* ceg = a.ce[l] + (size_t)s * a.L[l].ss;
+            const T* cng = a.cn[l] + (size_t)s * a.L[l].ss;
+            for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+                ce[off[l] + t] = ceg[t];
+                cn[off[l] + t] = cng[t];
+                z[off[l] + t] = T(0);
+            }
         }
         __syncthreads();
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
@@ -551,26 +586,44 @@ __global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
     }
 }
 
-// coarse k: geometric mean of k over the full-weighting stencil
+// Coarse operators: each coarse edge conductance is the harmonic mean of
+// the two fine edge conductances it spans (the two fine edges in series,
+// 2ab/(a+b)), computed from level 0's nodal k or from a stored level.
+__device__ __forceinline__ double hmean2(double a, double b) {
+    const double s = a + b;
+    return s > 0.0 ? 2.0 * a * b / s : 0.0;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarsen(const T* __restrict__ kf, long long kfss, Lvl F,
-                                                    T* __restrict__ kc, Lvl C, const Scal* scal) {
+__global__ __launch_bounds__(kBlock) void k_coarsen_k(const T* __restrict__ kf, long long kfss, Lvl F,
+                                                      T* __restrict__ cec, T* __restrict__ cnc, Lvl C) {
     const int s = blockIdx.y;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= C.w * C.w) return;
     const int J = t / C.w, I = t - J * C.w;
     const T* k = kf + (size_t)s * kfss;
-    double acc = 0.0, wsum = 0.0;
-    for (int b = -1; b <= 1; ++b)
-        for (int a = -1; a <= 1; ++a) {
-            const int x = 2 * I + a, y = 2 * J + b;
-            if (x < 0 || x > F.m || y < 0 || y > F.m) continue;
-            const double wgt = (double)((2 - abs(a)) * (2 - abs(b)));
-            acc += wgt * log((double)k[(size_t)y * F.w + x]);
-            wsum += wgt;
-        }
-    kc[(size_t)s * C.ss + t] = (T)exp(acc / wsum);
-    (void)scal;
+    const int m = F.m, w = F.w;
+    auto K = [&](int gx, int gy) -> double { return (double)k[(size_t)gy * w + gx]; };
+    const double e = hmean2(cond_e<double>(2 * I, 2 * J, m, K), cond_e<double>(2 * I + 1, 2 * J, m, K));
+    const double n = hmean2(cond_n<double>(2 * I, 2 * J, m, K), cond_n<double>(2 * I, 2 * J + 1, m, K));
+    cec[(size_t)s * C.ss + t] = (T)e;
+    cnc[(size_t)s * C.ss + t] = (T)n;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarsen_c(const T* __restrict__ cef, const T* __restrict__ cnf, Lvl F,
+                                                      T* __restrict__ cec, T* __restrict__ cnc, Lvl C) {
+    const int s = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C.w * C.w) return;
+    const int J = t / C.w, I = t - J * C.w;
+    const T* ce = cef + (size_t)s * F.ss;
+    const T* cn = cnf + (size_t)s * F.ss;
+    const int m = F.m, w = F.w;
+    auto E = [&](int x, int y) -> double { return (x <= m && y <= m) ? (double)ce[(size_t)y * w + x] : 0.0; };
+    auto N = [&](int x, int y) -> double { return (x <= m && y <= m) ? (double)cn[(size_t)y * w + x] : 0.0; };
+    cec[(size_t)s * C.ss + t] = (T)hmean2(E(2 * I, 2 * J), E(2 * I + 1, 2 * J));
+    cnc[(size_t)s * C.ss + t] = (T)hmean2(N(2 * I, 2 * J), N(2 * I, 2 * J + 1));
 }
 
 // ----------------------------------------------------------- PCG (double)
@@ -896,7 +949,8 @@ public:
         o_za0_ = take(n0 * sizeof(T));
         for (int l = 1; l < nlev_; ++l) {
             const size_t nl = (size_t)cap * lv_[l].ss * sizeof(T);
-            o_k_.push_back(take(nl));
+            o_ce_.push_back(take(nl));
+            o_cn_.push_back(take(nl));
             o_rhs_.push_back(take(nl));
             o_za_.push_back(take(nl));
             o_zb_.push_back(take(nl));
@@ -952,11 +1006,14 @@ public:
         const double sT = sizeof(T);
         // coefficient hierarchy
         for (int l = 0; l + 1 < nlev_; ++l) {
-            const T* kf = l == 0 ? k0 : ptr<T>(o_k_[l - 1]);
-            const long long fss = l == 0 ? kss : lv_[l].ss;
-            launch("coarsen", (nv(l) + nv(l + 1)) * sT, S, -1, st, [&] {
-                hipLaunchKernelGGL(k_coarsen<T>, dim3(cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S),
-                                   dim3(kBlock), 0, st, kf, fss, lv_[l], ptr<T>(o_k_[l]), lv_[l + 1], scal);
+            const dim3 g(cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S);
+            launch("coarsen", (l == 0 ? nv(0) : 2.0 * nv(l)) * sT + 2.0 * nv(l + 1) * sT, S, -1, st, [&] {
+                if (l == 0)
+                    hipLaunchKernelGGL(k_coarsen_k<T>, g, dim3(kBlock), 0, st, k0, kss, lv_[0], ptr<T>(o_ce_[0]),
+                                       ptr<T>(o_cn_[0]), lv_[1]);
+                else
+                    hipLaunchKernelGGL(k_coarsen_c<T>, g, dim3(kBlock), 0, st, ptr<T>(o_ce_[l - 1]),
+                                       ptr<T>(o_cn_[l - 1]), lv_[l], ptr<T>(o_ce_[l]), ptr<T>(o_cn_[l]), lv_[l + 1]);
             });
         }
         hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
@@ -1058,8 +1115,6 @@ private:
         return a;
     }
 
-    const T* klev(int l, const T* k0) const { return l == 0 ? k0 : ptr<T>(o_k_[l - 1]); }
-    long long kss_lev(int l, long long kss0) const { return l == 0 ? kss0 : lv_[l].ss; }
 
     MgArgs<T> mg_args(int l, const T* k0, long long kss, int tiles_x, int ntiles) {
         MgArgs<T> a{};
@@ -1068,8 +1123,12 @@ private:
         a.bc = cfg_.bc;
         a.tiles_x = tiles_x;
         a.ntiles = ntiles;
-        a.k = klev(l, k0);
-        a.kss = kss_lev(l, kss);
+        a.k = k0;
+        a.kss = kss;
+        if (l > 0) {
+            a.ce = ptr<T>(o_ce_[l - 1]);
+            a.cn = ptr<T>(o_cn_[l - 1]);
+        }
         a.rhs = l == 0 ? (const void*)ptr<double>(o_R_) : (const void*)ptr<T>(o_rhs_[l - 1]);
         a.za = l == 0 ? ptr<T>(o_za0_) : ptr<T>(o_za_[l - 1]);
         a.scal = ptr<Scal>(o_scal_);
@@ -1085,7 +1144,8 @@ private:
             a.rhs_c = ptr<T>(o_rhs_[l]);
             // k, rhs in; z_pre and the coarse rhs out
             const double rb = l == 0 ? 8.0 : sT;
-            launch(l == 0 ? "mg_pre_l0" : "mg_pre", nv(l) * sT + nu(l) * (rb + sT) + nu(l + 1) * sT, S, it, st, [&] {
+            const double coef = (l == 0 ? 1.0 : 2.0) * nv(l) * sT;   // k, or two conductance arrays
+            launch(l == 0 ? "mg_pre_l0" : "mg_pre", coef + nu(l) * (rb + sT) + nu(l + 1) * sT, S, it, st, [&] {
                 if (l == 0)
                     hipLaunchKernelGGL((k_mg<T, SH, false, true>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
                 else
@@ -1098,15 +1158,19 @@ private:
             b.bc = cfg_.bc;
             for (int l = 0; l < b.nl; ++l) {
                 b.L[l] = lv_[lb_ + l];
-                b.k[l] = klev(lb_ + l, k0);
-                b.kss[l] = kss_lev(lb_ + l, kss);
+                if (lb_ + l > 0) {
+                    b.ce[l] = ptr<T>(o_ce_[lb_ + l - 1]);
+                    b.cn[l] = ptr<T>(o_cn_[lb_ + l - 1]);
+                }
             }
+            b.k0 = k0;
+            b.kss0 = kss;
             b.scal = ptr<Scal>(o_scal_);
             b.dot = ptr<double>(o_part_);
             b.dot2 = ptr<double>(o_part2_);
             b.q = ptr<double>(o_Q_);
             double kb = 0.0;
-            for (int l = lb_; l < nlev_; ++l) kb += nv(l) * sT;
+            for (int l = lb_; l < nlev_; ++l) kb += (l == 0 ? 1.0 : 2.0) * nv(l) * sT;
             const double io = lb_ == 0 ? nu(0) * (24.0 + sT) : nu(lb_) * 2.0 * sT;
             launch("mg_bottom", kb + io, S, it, st, [&] {
                 if (lb_ == 0) {
@@ -1131,7 +1195,7 @@ private:
             a.q = ptr<double>(o_Q_);
             // k, z_pre, rhs, coarse correction in; z out (level 0: r, q_old in for the dots)
             const double post = l == 0 ? nv(0) * sT + nu(0) * (sT + 8.0 + 8.0 + sT) + nu(1) * sT
-                                       : nv(l) * sT + nu(l) * 3.0 * sT + nu(l + 1) * sT;
+                                       : 2.0 * nv(l) * sT + nu(l) * 3.0 * sT + nu(l + 1) * sT;
             launch(l == 0 ? "mg_post_l0" : "mg_post", post, S, it, st, [&] {
                 if (l == 0)
                     hipLaunchKernelGGL((k_mg<T, SH, true, true>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
@@ -1148,7 +1212,7 @@ private:
     int ptx_ = 0, pty_ = 0, ptiles_ = 0, itx_ = 0, ity_ = 0, itiles_ = 0, stx_ = 0, sty_ = 0;
     int rz_parts_ = 0, max_parts_ = 0;
     size_t o_X_ = 0, o_R_ = 0, o_P0_ = 0, o_P1_ = 0, o_Q_ = 0, o_Z_ = 0, o_za0_ = 0;
-    std::vector<size_t> o_k_, o_rhs_, o_za_, o_zb_;
+    std::vector<size_t> o_ce_, o_cn_, o_rhs_, o_za_, o_zb_;
     size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0, o_hist_ = 0;
     std::vector<std::pair<int, int>> recs_;
     size_t bytes_ = 0;
