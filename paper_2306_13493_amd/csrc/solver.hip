@@ -130,28 +130,24 @@ __device__ __forceinline__ T fast_rcp(T v) {
     }
 }
 
-template <typename T, int SH, int Q0>
+template <typename T, int SH, int Q0, int PX>
 __device__ __forceinline__ void mg_half_sweep(T (&z)[SH][2], const T (&rhs)[SH][2], const T (&id)[SH][2],
                                               const T (&ce)[SH][2], const T (&cw0)[SH], const T (&cn)[SH + 1][2],
-                                              T* sz, int lx0, int ly0, int RX, int RY) {
+                                              T* sz0) {
+    // sz0 points at this lane's node (row 0 of its strip, left column) in the
+    // padded LDS array; the one-node ring keeps every neighbour in range
 #pragma unroll
     for (int r = 0; r < SH; ++r) {
         const int q = Q0 ^ (r & 1);
-        const int ly = ly0 + r;
-        T zE, zW, zN, zS;
-        if (q == 0) {
-            zE = z[r][1];
-            zW = sz[ly * RX + (lx0 > 0 ? lx0 - 1 : 0)];
-        } else {
-            zW = z[r][0];
-            zE = sz[ly * RX + (lx0 + 2 < RX ? lx0 + 2 : RX - 1)];
-        }
-        zN = (r < SH - 1) ? z[r + 1][q] : sz[(ly + 1 < RY ? ly + 1 : RY - 1) * RX + lx0 + q];
-        zS = (r > 0) ? z[r - 1][q] : sz[(ly > 0 ? ly - 1 : 0) * RX + lx0 + q];
+        T* p = sz0 + r * PX + q;
+        const T zE = q == 0 ? z[r][1] : p[1];
+        const T zW = q == 1 ? z[r][0] : p[-1];
+        const T zN = (r < SH - 1) ? z[r + 1][q] : p[PX];
+        const T zS = (r > 0) ? z[r - 1][q] : p[-PX];
         const T cW = q == 0 ? cw0[r] : ce[r][0];
         const T v = (rhs[r][q] + ce[r][q] * zE + cW * zW + cn[r + 1][q] * zN + cn[r][q] * zS) * id[r][q];
         z[r][q] = v;
-        sz[ly * RX + lx0 + q] = v;
+        p[0] = v;
     }
     __syncthreads();
 }
@@ -161,10 +157,11 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
     constexpr int RX = 64, NH = kBlock / 32, RY = NH * SH;
     constexpr int H = POST ? 4 : 6;
     constexpr int TX = RX - 2 * H, TY = RY - 2 * H;
-    constexpr int KX = RX + 2, KY = RY + 2;
-    __shared__ T sz[RY * RX];
-    __shared__ T sk[KY * KX];    // k (ring of one node); PRE reuses it for the residual
-    __shared__ T szc[POST ? (RY / 2 + 3) * (RX / 2 + 3) : 1];
+    constexpr int PX = RX + 2, PY = RY + 2;   // padded: one-node ring on every side
+    __shared__ T sz[PY * PX];
+    __shared__ T sk[PY * PX];    // level 0: k; PRE reuses it for the residual
+    constexpr int CX = RX / 2 + 3, CY = RY / 2 + 3;
+    __shared__ T szc[POST ? CY * CX : 1];
     __shared__ double red[kBlock / 64];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     const int s = wi / a.ntiles;
@@ -174,42 +171,69 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
     const int x0 = 1 + tx * TX, y0 = a.L.ylo + ty * TY;
     const int ox = x0 - H, oy = y0 - H;
     const int m = a.L.m, w = a.L.w, bc = a.bc;
+    const size_t sbase = (size_t)s * a.L.ss;
+    // k tile (level 0): lane l of wave wv loads padded column l for rows wv, wv+4, ...
     if constexpr (L0) {
+        // all loads are issued before any is used (addresses clamped into
+        // the mesh, values masked afterwards) so their latencies overlap
         const T* kk = a.k + (size_t)s * a.kss;
-        for (int t = threadIdx.x; t < KX * KY; t += blockDim.x) {
-            const int y = t / KX, x = t - y * KX;
-            const int gx = ox - 1 + x, gy = oy - 1 + y;
-            sk[t] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? kk[(size_t)gy * w + gx] : T(0);
+        constexpr int NW = kBlock / 64, NIT = (PY + NW - 1) / NW;
+        const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int col = l < PX - 64 ? 64 + l : l;   // lanes 0,1 also take the two last columns
+        const int gxa = ox - 1 + l, gxb = ox - 1 + col;
+        const int gxac = min(max(gxa, 0), m), gxbc = min(max(gxb, 0), m);
+        T ka[NIT], kb[NIT];
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int gyc = min(max(oy - 1 + wv + i * NW, 0), m);
+            ka[i] = kk[gyc * w + gxac];
+            kb[i] = kk[gyc * w + gxbc];
+        }
+        const bool oka = gxa >= 0 && gxa <= m, okb = gxb >= 0 && gxb <= m;
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int y = wv + i * NW, gy = oy - 1 + y;
+            const bool oky = gy >= 0 && gy <= m;
+            if (y < PY) {
+                sk[y * PX + l] = (oka && oky) ? ka[i] : T(0);
+                if (l < PX - 64) sk[y * PX + col] = (okb && oky) ? kb[i] : T(0);
+            }
         }
     }
-    constexpr int CX = RX / 2 + 3;
+    // zero ring of the z array (never updated, read as neighbours of the edge)
+    for (int t = threadIdx.x; t < 2 * PX + 2 * RY; t += blockDim.x) {
+        if (t < PX) sz[t] = T(0);
+        else if (t < 2 * PX) sz[(PY - 1) * PX + t - PX] = T(0);
+        else if (t < 2 * PX + RY) sz[(t - 2 * PX + 1) * PX] = T(0);
+        else sz[(t - 2 * PX - RY + 1) * PX + PX - 1] = T(0);
+    }
     const int cox = ox >> 1, coy = oy >> 1;  // floor, also for negative origins
     if constexpr (POST) {
         const T* zc = a.zc + (size_t)s * a.C.ss;
         const int cm = a.C.m, cw = a.C.w;
-        for (int t = threadIdx.x; t < (RY / 2 + 3) * CX; t += blockDim.x) {
+        for (int t = threadIdx.x; t < CY * CX; t += blockDim.x) {
             const int y = t / CX, x = t - y * CX;
             const int I = cox + x, J = coy + y;
-            szc[t] = is_unknown(I, J, cm, bc) ? zc[(size_t)J * cw + I] : T(0);
+            szc[t] = is_unknown(I, J, cm, bc) ? zc[J * cw + I] : T(0);
         }
     }
     __syncthreads();
     const int lane = threadIdx.x & 31, hw = threadIdx.x >> 5;
     const int lx0 = 2 * lane, ly0 = hw * SH;
     const int gx0 = ox + lx0;
-    // triangle sums of the squares with lower-left corner (lx, ly) (region coords)
-    auto Kl = [&](int lx, int ly) -> T { return sk[(ly + 1) * KX + lx + 1]; };
-    auto sq = [&](int lx, int ly) -> bool {
-        const int gx = ox + lx, gy = oy + ly;
-        return gx >= 0 && gx < m && gy >= 0 && gy < m;
-    };
+    // column masks of this lane
+    const bool unk_c0 = gx0 >= 1 && gx0 <= m - 1, unk_c1 = gx0 + 1 >= 1 && gx0 + 1 <= m - 1;
+    const bool sqc_m = gx0 - 1 >= 0 && gx0 - 1 <= m - 1, sqc_a = gx0 >= 0 && gx0 <= m - 1,
+               sqc_b = gx0 + 1 >= 0 && gx0 + 1 <= m - 1;
+    const int ylo = a.L.ylo, yhi = a.L.yhi;
     T ce[SH][2], cw0[SH], cn[SH + 1][2];
     if constexpr (!L0) {
         // coarser levels: stored conductances (zero outside the mesh)
-        const T* CEg = a.ce + (size_t)s * a.L.ss;
-        const T* CNg = a.cn + (size_t)s * a.L.ss;
+        const T* CEg = a.ce + sbase;
+        const T* CNg = a.cn + sbase;
         auto ld = [&](const T* g, int gx, int gy) -> T {
-            return (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? g[(size_t)gy * w + gx] : T(0);
+            const T v = g[min(max(gy, 0), m) * w + min(max(gx, 0), m)];
+            return (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? v : T(0);
         };
 #pragma unroll
         for (int q = 0; q < 2; ++q) cn[0][q] = ld(CNg, gx0 + q, oy + ly0 - 1);
@@ -224,20 +248,23 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
             }
         }
     } else {
+        // triangle sums S1, S2 of the squares at columns gx0-1, gx0, gx0+1
+        const T* k0 = sk + ly0 * PX + lx0;   // padded (lx0 - 1, ly0 - 1)
         T p2m = T(0), p2a = T(0), p2b = T(0);
         const T sixth = T(1.0 / 6.0);
 #pragma unroll
         for (int r = -1; r < SH; ++r) {
-            const int ly = ly0 + r;
-            const T k_m = Kl(lx0 - 1, ly), k_a = Kl(lx0, ly), k_b = Kl(lx0 + 1, ly), k_c = Kl(lx0 + 2, ly);
-            const T u_m = Kl(lx0 - 1, ly + 1), u_a = Kl(lx0, ly + 1), u_b = Kl(lx0 + 1, ly + 1),
-                    u_c = Kl(lx0 + 2, ly + 1);
-            const T s1m = sq(lx0 - 1, ly) ? k_m + k_a + u_a : T(0);
-            const T s2m = sq(lx0 - 1, ly) ? k_m + u_a + u_m : T(0);
-            const T s1a = sq(lx0, ly) ? k_a + k_b + u_b : T(0);
-            const T s2a = sq(lx0, ly) ? k_a + u_b + u_a : T(0);
-            const T s1b = sq(lx0 + 1, ly) ? k_b + k_c + u_c : T(0);
-            const T s2b = sq(lx0 + 1, ly) ? k_b + u_c + u_b : T(0);
+            const T* kr = k0 + (r + 1) * PX;
+            const T k_m = kr[0], k_a = kr[1], k_b = kr[2], k_c = kr[3];
+            const T u_m = kr[PX], u_a = kr[PX + 1], u_b = kr[PX + 2], u_c = kr[PX + 3];
+            const int gy = oy + ly0 + r;
+            const bool sqr = gy >= 0 && gy <= m - 1;
+            const T s1m = (sqr && sqc_m) ? k_m + k_a + u_a : T(0);
+            const T s2m = (sqr && sqc_m) ? k_m + u_a + u_m : T(0);
+            const T s1a = (sqr && sqc_a) ? k_a + k_b + u_b : T(0);
+            const T s2a = (sqr && sqc_a) ? k_a + u_b + u_a : T(0);
+            const T s1b = (sqr && sqc_b) ? k_b + k_c + u_c : T(0);
+            const T s2b = (sqr && sqc_b) ? k_b + u_c + u_b : T(0);
             if (r >= 0) {
                 ce[r][0] = (s1a + p2a) * sixth;
                 ce[r][1] = (s1b + p2b) * sixth;
@@ -251,19 +278,34 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
         }
     }
     T z[SH][2], rhs[SH][2], id[SH][2];
-    const T* zin = a.za + (size_t)s * a.L.ss;
-    const T* rhsT = L0 ? nullptr : reinterpret_cast<const T*>(a.rhs) + (size_t)s * a.L.ss;
-    const double* rhsD = L0 ? reinterpret_cast<const double*>(a.rhs) + (size_t)s * a.L.ss : nullptr;
+    const T* zin = a.za + sbase;
+    const T* rhsT = L0 ? nullptr : reinterpret_cast<const T*>(a.rhs) + sbase;
+    const double* rhsD = L0 ? reinterpret_cast<const double*>(a.rhs) + sbase : nullptr;
+    T* sz0 = sz + (ly0 + 1) * PX + lx0 + 1;
+    T zv[SH][2];
+    {
+        const int gxc0 = min(max(gx0, 0), m), gxc1 = min(max(gx0 + 1, 0), m);
+#pragma unroll
+        for (int r = 0; r < SH; ++r) {
+            const int gyc = min(max(oy + ly0 + r, 0), m);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int o = gyc * w + (q == 0 ? gxc0 : gxc1);
+                rhs[r][q] = L0 ? (T)rhsD[o] : rhsT[o];
+                if constexpr (POST) zv[r][q] = zin[o];
+            }
+        }
+    }
 #pragma unroll
     for (int r = 0; r < SH; ++r) {
         const int gy = oy + ly0 + r;
+        const bool ur = gy >= ylo && gy <= yhi;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int gx = gx0 + q;
             T rr = T(0), zz = T(0), d = T(0);
-            if (is_unknown(gx, gy, m, bc)) {
-                const size_t o = (size_t)gy * w + gx;
-                rr = L0 ? (T)rhsD[o] : rhsT[o];
+            if (ur && (q == 0 ? unk_c0 : unk_c1)) {
+                rr = rhs[r][q];
                 const T cW = q == 0 ? cw0[r] : ce[r][0];
                 d = fast_rcp(ce[r][q] + cW + cn[r + 1][q] + cn[r][q]);
                 if constexpr (POST) {
@@ -275,13 +317,13 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
                     else if (ox1 && !oy1) p = T(0.5) * (c0[0] + c0[1]);
                     else if (!ox1 && oy1) p = T(0.5) * (c0[0] + c0[CX]);
                     else p = T(0.25) * ((c0[0] + c0[1]) + (c0[CX] + c0[CX + 1]));
-                    zz = zin[o] + p;
+                    zz = zv[r][q] + p;
                 }
             }
             z[r][q] = zz;
             rhs[r][q] = rr;
             id[r][q] = d;
-            sz[(ly0 + r) * RX + lx0 + q] = zz;
+            sz0[r * PX + q] = zz;
         }
     }
     __syncthreads();
@@ -292,27 +334,36 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
     for (int h = 0; h < 4; ++h) {
         const int c = (h & 1) ? 1 - c0 : c0;
         if (((c - par) & 1) == 0)
-            mg_half_sweep<T, SH, 0>(z, rhs, id, ce, cw0, cn, sz, lx0, ly0, RX, RY);
+            mg_half_sweep<T, SH, 0, PX>(z, rhs, id, ce, cw0, cn, sz0);
         else
-            mg_half_sweep<T, SH, 1>(z, rhs, id, ce, cw0, cn, sz, lx0, ly0, RX, RY);
+            mg_half_sweep<T, SH, 1, PX>(z, rhs, id, ce, cw0, cn, sz0);
     }
-    // outputs on the tile (margin >= H)
+    // outputs on the tile (margin >= H); id != 0 marks unknown nodes
     double acc = 0.0, acc2 = 0.0;
+    T* out = POST ? a.zout + sbase : a.za + sbase;
+    double qv[POST && L0 ? SH : 1][2];
+    if constexpr (POST && L0) {
+        const int gxc0 = min(max(gx0, 0), m), gxc1 = min(max(gx0 + 1, 0), m);
+#pragma unroll
+        for (int r = 0; r < SH; ++r) {
+            const int gyc = min(max(oy + ly0 + r, 0), m);
+            qv[r][0] = a.q[sbase + gyc * w + gxc0];
+            qv[r][1] = a.q[sbase + gyc * w + gxc1];
+        }
+    }
 #pragma unroll
     for (int r = 0; r < SH; ++r) {
         const int ly = ly0 + r, gy = oy + ly;
+        const bool iny = ly >= H && ly < H + TY;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int lx = lx0 + q, gx = gx0 + q;
-            if (lx < H || lx >= H + TX || ly < H || ly >= H + TY || !is_unknown(gx, gy, m, bc)) continue;
-            const size_t o = (size_t)s * a.L.ss + (size_t)gy * w + gx;
-            if (!POST) {
-                a.za[o] = z[r][q];
-            } else {
-                a.zout[o] = z[r][q];
-                if (L0) {
-                    acc += rhsD[(size_t)gy * w + gx] * (double)z[r][q];
-                    acc2 += a.q[o] * (double)z[r][q];
+            const int lx = lx0 + q;
+            const bool in = iny && lx >= H && lx < H + TX && id[r][q] != T(0);
+            if (in) out[gy * w + gx0 + q] = z[r][q];
+            if constexpr (POST && L0) {
+                if (in) {
+                    acc += (double)rhs[r][q] * (double)z[r][q];
+                    acc2 += qv[r][q] * (double)z[r][q];
                 }
             }
         }
@@ -329,20 +380,20 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
         return;
     } else {
         // residual r - A z (difference form) into sk, on every region node
-        T* sres = sk;
+        T* sres0 = sk + (ly0 + 1) * PX + lx0 + 1;
 #pragma unroll
         for (int r = 0; r < SH; ++r) {
-            const int ly = ly0 + r;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
+                const T* p = sz0 + r * PX + q;
                 const T zp = z[r][q];
-                const T zE = q == 0 ? z[r][1] : sz[ly * RX + (lx0 + 2 < RX ? lx0 + 2 : RX - 1)];
-                const T zW = q == 1 ? z[r][0] : sz[ly * RX + (lx0 > 0 ? lx0 - 1 : 0)];
-                const T zN = (r < SH - 1) ? z[r + 1][q] : sz[(ly + 1 < RY ? ly + 1 : RY - 1) * RX + lx0 + q];
-                const T zS = (r > 0) ? z[r - 1][q] : sz[(ly > 0 ? ly - 1 : 0) * RX + lx0 + q];
+                const T zE = q == 0 ? z[r][1] : p[1];
+                const T zW = q == 1 ? z[r][0] : p[-1];
+                const T zN = (r < SH - 1) ? z[r + 1][q] : p[PX];
+                const T zS = (r > 0) ? z[r - 1][q] : p[-PX];
                 const T cW = q == 0 ? cw0[r] : ce[r][0];
                 const T az = (ce[r][q] * (zp - zE) + cW * (zp - zW)) + (cn[r + 1][q] * (zp - zN) + cn[r][q] * (zp - zS));
-                sres[ly * RX + lx0 + q] = id[r][q] != T(0) ? rhs[r][q] - az : T(0);
+                sres0[r * PX + q] = id[r][q] != T(0) ? rhs[r][q] - az : T(0);
             }
         }
         __syncthreads();
@@ -355,11 +406,10 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
             const int jj = t / nI, ii = t - jj * nI;
             const int I = I0 + ii, J = J0 + jj;
             if (!is_unknown(I, J, cm, bc)) continue;
-            const int lx = 2 * I - ox, ly = 2 * J - oy;
-            const T* c0 = sres + ly * RX + lx;
-            const T v = c0[0] + T(0.5) * ((c0[-1] + c0[1]) + (c0[-RX] + c0[RX])) +
-                        T(0.25) * ((c0[-RX - 1] + c0[-RX + 1]) + (c0[RX - 1] + c0[RX + 1]));
-            rc[(size_t)J * cwid + I] = v;
+            const T* c0 = sk + (2 * J - oy + 1) * PX + (2 * I - ox + 1);
+            const T v = c0[0] + T(0.5) * ((c0[-1] + c0[1]) + (c0[-PX] + c0[PX])) +
+                        T(0.25) * ((c0[-PX - 1] + c0[-PX + 1]) + (c0[PX - 1] + c0[PX + 1]));
+            rc[J * cwid + I] = v;
         }
     }
 }
@@ -700,11 +750,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs<T> a) {
     if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
 }
 
-// p_new = z + beta p_old; q = A p_new; partial p_new.q (unknown-region tiles)
+// p_new = z + beta p_old; q = A p_new; partial p_new.q (unknown-region tiles).
+// Lane l of wave wv owns column x0 + l, rows y0 + 4 wv .. y0 + 4 wv + 3.
+// Conductances from the triangle sums of the k tile (double).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
-    __shared__ KTile<T> K;
-    __shared__ double P[PTY + 2][PTX + 2];
+    constexpr int KX = PTX + 2, KY = PTY + 2, NR = PTY / (kBlock / 64);
+    __shared__ double K[KY * KX];
+    __shared__ double P[KY * KX];
     __shared__ double red[kBlock / 64];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     const int s = wi / a.ntiles, tile = wi - s * a.ntiles;
@@ -715,35 +768,76 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
     const double beta = first ? 0.0 : -sc.zq / sc.pq;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = 1 + tx * PTX, y0 = a.L.ylo + ty * PTY;
-    const int m = a.L.m, w = a.L.w;
-    load_ktile(K, a.k + (size_t)s * a.kss, x0, y0, m, w);
+    const int m = a.L.m, w = a.L.w, bc = a.bc;
     const size_t base = (size_t)s * a.L.ss;
-    for (int t = threadIdx.x; t < (PTX + 2) * (PTY + 2); t += blockDim.x) {
-        const int y = t / (PTX + 2), x = t - y * (PTX + 2);
+    const T* kk = a.k + (size_t)s * a.kss;
+    const T* Z = a.Z + base;
+    const double* Po = a.Pold + base;
+    // tile + one-node ring: flat index, loads first (clamped), then masked stores
+    constexpr int NT = (KX * KY + kBlock - 1) / kBlock;
+    double kv[NT], zv[NT], pv[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int t = threadIdx.x + i * kBlock;
+        const int y = t / KX, x = t - y * KX;
+        const int gx = min(max(x0 - 1 + x, 0), m), gy = min(max(y0 - 1 + y, 0), m);
+        const int o = gy * w + gx;
+        kv[i] = (double)kk[o];
+        zv[i] = (double)Z[o];
+        pv[i] = Po[o];
+    }
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int t = threadIdx.x + i * kBlock;
+        if (t >= KX * KY) break;
+        const int y = t / KX, x = t - y * KX;
         const int gx = x0 - 1 + x, gy = y0 - 1 + y;
-        double v = 0.0;
-        if (is_unknown(gx, gy, m, a.bc)) {
-            const size_t o = base + (size_t)gy * w + gx;
-            v = (double)a.Z[o] + beta * a.Pold[o];
-        }
-        P[y][x] = v;
+        const bool in = gx >= 0 && gx <= m && gy >= 0 && gy <= m;
+        K[t] = in ? kv[i] : 0.0;
+        P[t] = is_unknown(gx, gy, m, bc) ? zv[i] + beta * pv[i] : 0.0;
     }
     __syncthreads();
-    auto KF = [&](int gx, int gy) -> double { return K.k[gy - y0 + 1][gx - x0 + 1]; };
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gx = x0 + l;
+    const bool sqm = gx - 1 >= 0 && gx - 1 <= m - 1, sqa = gx >= 0 && gx <= m - 1;
+    const bool unkc = gx >= 1 && gx <= m - 1;
     double acc = 0.0;
-    for (int t = threadIdx.x; t < PTX * PTY; t += blockDim.x) {
-        const int yy = t / PTX, xx = t - yy * PTX;
-        const int gx = x0 + xx, gy = y0 + yy;
-        if (!is_unknown(gx, gy, m, a.bc)) continue;
-        const int x = xx + 1, y = yy + 1;
-        const double cE = cond_e<double>(gx, gy, m, KF), cW = cond_e<double>(gx - 1, gy, m, KF);
-        const double cN = cond_n<double>(gx, gy, m, KF), cS = cond_n<double>(gx, gy - 1, m, KF);
-        const double pc = P[y][x];
-        const double q = (cE * (pc - P[y][x + 1]) + cW * (pc - P[y][x - 1])) + (cN * (pc - P[y + 1][x]) + cS * (pc - P[y - 1][x]));
-        const size_t o = base + (size_t)gy * w + gx;
-        a.Pnew[o] = pc;
-        a.Q[o] = q;
-        acc += pc * q;
+    // triangle sums S1 (below the diagonal), S2 (above) of squares (gx-1, y) and (gx, y)
+    const double* k0 = K + (NR * wv) * KX + l;   // tile coords (l-1, row-1) -> padded (l, row)
+    double s1m_p, s2m_p, s1a_p, s2a_p;
+    {
+        const int gy = y0 + NR * wv - 1;
+        const bool sqr = gy >= 0 && gy <= m - 1;
+        const double km = k0[0], ka = k0[1], kb = k0[2], um = k0[KX], ua = k0[KX + 1], ub = k0[KX + 2];
+        s1m_p = (sqr && sqm) ? km + ka + ua : 0.0;
+        s2m_p = (sqr && sqm) ? km + ua + um : 0.0;
+        s1a_p = (sqr && sqa) ? ka + kb + ub : 0.0;
+        s2a_p = (sqr && sqa) ? ka + ub + ua : 0.0;
+    }
+    const double sixth = 1.0 / 6.0;
+    double cS = (s2a_p + s1m_p) * sixth;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int yy = NR * wv + r, gy = y0 + yy;
+        const bool sqr = gy >= 0 && gy <= m - 1;
+        const double* kr = k0 + (r + 1) * KX;
+        const double km = kr[0], ka = kr[1], kb = kr[2], um = kr[KX], ua = kr[KX + 1], ub = kr[KX + 2];
+        const double s1m = (sqr && sqm) ? km + ka + ua : 0.0;
+        const double s2m = (sqr && sqm) ? km + ua + um : 0.0;
+        const double s1a = (sqr && sqa) ? ka + kb + ub : 0.0;
+        const double s2a = (sqr && sqa) ? ka + ub + ua : 0.0;
+        const double cE = (s1a + s2a_p) * sixth, cW = (s1m + s2m_p) * sixth, cN = (s2a + s1m) * sixth;
+        const double* pp = P + (yy + 1) * KX + l + 1;
+        const double pc = pp[0];
+        const double q = (cE * (pc - pp[1]) + cW * (pc - pp[-1])) + (cN * (pc - pp[KX]) + cS * (pc - pp[-KX]));
+        if (unkc && gy >= a.L.ylo && gy <= a.L.yhi) {
+            const size_t o = base + (size_t)gy * w + gx;
+            a.Pnew[o] = pc;
+            a.Q[o] = q;
+            acc += pc * q;
+        }
+        s1m_p = s1m; s2m_p = s2m; s1a_p = s1a; s2a_p = s2a;
+        cS = cN;
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
@@ -752,6 +846,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
 // x += alpha p; r -= alpha q; partial ||r||^2
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(PcgArgs<T> a) {
+    constexpr int NR = PTY / (kBlock / 64);
     __shared__ double red[kBlock / 64];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     const int s = wi / a.ntiles, tile = wi - s * a.ntiles;
@@ -762,16 +857,29 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(PcgArgs<T> a) {
     const int x0 = 1 + tx * PTX, y0 = a.L.ylo + ty * PTY;
     const int m = a.L.m, w = a.L.w;
     const size_t base = (size_t)s * a.L.ss;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gx = x0 + l, gxc = min(gx, m);
+    double xv[NR], pv[NR], rv[NR], qv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const size_t o = base + (size_t)min(y0 + NR * wv + r, m) * w + gxc;
+        xv[r] = a.X[o];
+        pv[r] = a.Pnew[o];
+        rv[r] = a.R[o];
+        qv[r] = a.Q[o];
+    }
     double acc = 0.0;
-    for (int t = threadIdx.x; t < PTX * PTY; t += blockDim.x) {
-        const int yy = t / PTX, xx = t - yy * PTX;
-        const int gx = x0 + xx, gy = y0 + yy;
-        if (!is_unknown(gx, gy, m, a.bc)) continue;
-        const size_t o = base + (size_t)gy * w + gx;
-        a.X[o] += alpha * a.Pnew[o];
-        const double r = a.R[o] - alpha * a.Q[o];
-        a.R[o] = r;
-        acc += r * r;
+    const bool unkc = gx <= m - 1;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int gy = y0 + NR * wv + r;
+        if (unkc && gy <= a.L.yhi) {
+            const size_t o = base + (size_t)gy * w + gx;
+            a.X[o] = xv[r] + alpha * pv[r];
+            const double rn = rv[r] - alpha * qv[r];
+            a.R[o] = rn;
+            acc += rn * rn;
+        }
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
