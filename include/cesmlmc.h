@@ -151,6 +151,58 @@ int ces_sample(ces_plan plan, uint64_t seed, uint64_t first_sample, int64_t coun
                double* y_dev, double* q_fine_dev, double* q_coarse_dev,
                int32_t* iters_dev, int32_t* status_dev, void* hip_stream);
 
+/* ---- batches of levels of uneven size (MLMC rounds, served work) ------ */
+
+/* One request: samples first_sample .. first_sample+count-1 of `plan`
+ * with the outputs of ces_sample (device pointers; all but y may be NULL). */
+typedef struct {
+    ces_plan plan;
+    uint64_t seed;
+    uint64_t first_sample;
+    int64_t count;
+    double* y;
+    double* q_fine;
+    double* q_coarse;
+    int32_t* iters;
+    int32_t* status;
+} ces_request;
+
+/* Schedule of ces_sample and ces_sample_batch.  No field changes any
+ * result (each sample's arithmetic is fixed by its plan); only the speed.
+ *   depth          CG iterations of a solve enqueued ahead of its
+ *                  convergence read-back, 1..4 (default 2)
+ *   max_lanes      plans worked on concurrently, 0 = all (default 0)
+ *   chunk_samples  samples per solver launch, 0 = the plan's workspace
+ *                  capacity (default 0) */
+typedef struct {
+    int32_t depth;
+    int32_t max_lanes;
+    int64_t chunk_samples;
+} ces_schedule;
+
+/* Samples of every request, in one scheduled pass (the levels of an MLMC
+ * estimator, Section 3.4, have meshes h_0 .. h_L and sample counts N_l of
+ * very different sizes).  Each distinct plan is a lane with its own
+ * streams, forked from hip_stream and joined back into it; a plan's
+ * requests run one after another in its lane, lanes run concurrently, and
+ * meshes with m <= 32 are solved in a single launch per chunk.  Every
+ * output equals what ces_sample gives for that request alone, bit for bit.
+ * A plan may appear in several requests but not in two concurrent calls
+ * (CES_ERR_BUSY).  Returns once every solve's convergence has been seen;
+ * the outputs are complete when hip_stream reaches the join. */
+int ces_sample_batch(ces_context ctx, const ces_request* reqs, int32_t nreq, void* hip_stream);
+
+int ces_schedule_get(ces_context ctx, ces_schedule* out);
+/* Unset (zero) depth means 2. */
+int ces_schedule_set(ces_context ctx, const ces_schedule* sched);
+
+/* Autotuner: runs ces_sample_batch(reqs) under candidate schedules (each
+ * run recomputes the same samples into the requests' outputs), keeps the
+ * fastest as the context's schedule and returns it in *chosen and its
+ * time in *best_ms (either may be NULL).  Synchronous. */
+int ces_autotune(ces_context ctx, const ces_request* reqs, int32_t nreq, void* hip_stream,
+                 ces_schedule* chosen, double* best_ms);
+
 /* ---- parity hooks (same kernels as ces_sample) ------------------------ */
 
 /* Box-Muller normals of Philox counter (e, q mod 2^32, q >> 32, stream),

@@ -15,7 +15,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import CesError, LevelDesc, PlanInfo, check, load
+from ._lib import CesError, LevelDesc, PlanInfo, Request, Schedule, check, load
 
 COV = {"matern": 0, "sepexp": 1}
 LEVEL = {"single": 0, "pair": 1}
@@ -90,6 +90,56 @@ class Context:
 
     def plan(self, desc=None, **kw):
         return Plan(self, desc if desc is not None else level_desc(**kw))
+
+    @property
+    def schedule(self):
+        """(depth, max_lanes, chunk_samples) of ces_sample / ces_sample_batch."""
+        s = Schedule()
+        check(self.lib.ces_schedule_get(self.handle, ctypes.byref(s)))
+        return (s.depth, s.max_lanes, s.chunk_samples)
+
+    @schedule.setter
+    def schedule(self, v):
+        s = Schedule(int(v[0]), int(v[1]), int(v[2]))
+        check(self.lib.ces_schedule_set(self.handle, ctypes.byref(s)))
+
+    def _requests(self, reqs, outs):
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        arr = (Request * len(reqs))()
+        res = []
+        for i, r in enumerate(reqs):
+            plan, seed, first, count = r
+            o = outs[i] if outs is not None else None
+            if o is None:
+                o = {"y": torch.empty(count, dtype=torch.float64, device=dev),
+                     "q_fine": torch.empty(count, dtype=torch.float64, device=dev),
+                     "q_coarse": torch.empty(count, dtype=torch.float64, device=dev),
+                     "iters": torch.empty(count, dtype=torch.int32, device=dev),
+                     "status": torch.empty(count, dtype=torch.int32, device=dev)}
+            arr[i] = Request(plan.handle.value if plan is not None else None, int(seed), int(first), int(count),
+                             o["y"].data_ptr(), o["q_fine"].data_ptr(), o["q_coarse"].data_ptr(),
+                             o["iters"].data_ptr(), o["status"].data_ptr())
+            res.append(o)
+        return arr, res
+
+    def sample_batch(self, reqs, stream=None, outs=None):
+        """ces_sample_batch over [(plan, seed, first, count), ...]; returns
+        one output dict per request (as Plan.sample)."""
+        if not reqs:
+            return []
+        arr, res = self._requests(reqs, outs)
+        check(self.lib.ces_sample_batch(self.handle, arr, len(reqs), _stream_ptr(stream)))
+        return res
+
+    def autotune(self, reqs, stream=None, outs=None):
+        """ces_autotune over the requests: ((depth, max_lanes, chunk), best_ms, outputs)."""
+        arr, res = self._requests(reqs, outs)
+        s = Schedule()
+        ms = ctypes.c_double()
+        check(self.lib.ces_autotune(self.handle, arr, len(reqs), _stream_ptr(stream), ctypes.byref(s),
+                                    ctypes.byref(ms)))
+        return (s.depth, s.max_lanes, s.chunk_samples), ms.value, res
 
     def close(self):
         if self.handle:
@@ -217,4 +267,5 @@ def profile_read(max_entries=64):
             for i in range(min(n.value, max_entries))}
 
 
-__all__ = ["Context", "Plan", "level_desc", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc", "PlanInfo", "load"]
+__all__ = ["Context", "Plan", "level_desc", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc",
+           "PlanInfo", "Request", "Schedule", "load"]

@@ -46,6 +46,15 @@ class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", c_int64), ("total_ms", c_double), ("bytes", c_double)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("plan", c_void_p), ("seed", c_uint64), ("first_sample", c_uint64), ("count", c_int64),
+                ("y", c_dptr), ("q_fine", c_dptr), ("q_coarse", c_dptr), ("iters", c_dptr), ("status", c_dptr)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("depth", c_int32), ("max_lanes", c_int32), ("chunk_samples", c_int64)]
+
+
 # name -> (restype, argtypes); every function declared in include/cesmlmc.h
 SIGNATURES = {
     "ces_level_desc_default": (None, [ctypes.POINTER(LevelDesc)]),
@@ -56,6 +65,11 @@ SIGNATURES = {
     "ces_plan_destroy": (c_int32, [c_void_p]),
     "ces_sample": (c_int32, [c_void_p, c_uint64, c_uint64, c_int64, c_dptr, c_dptr, c_dptr, c_dptr,
                              c_dptr, c_void_p]),
+    "ces_sample_batch": (c_int32, [c_void_p, ctypes.POINTER(Request), c_int32, c_void_p]),
+    "ces_schedule_get": (c_int32, [c_void_p, ctypes.POINTER(Schedule)]),
+    "ces_schedule_set": (c_int32, [c_void_p, ctypes.POINTER(Schedule)]),
+    "ces_autotune": (c_int32, [c_void_p, ctypes.POINTER(Request), c_int32, c_void_p, ctypes.POINTER(Schedule),
+                               ctypes.POINTER(c_double)]),
     "ces_normals": (c_int32, [c_uint64, c_uint64, c_uint32, c_uint64, c_int64, c_dptr, c_void_p]),
     "ces_plan_eigenvalues": (c_int32, [c_void_p, c_void_p]),
     "ces_plan_mask": (c_int32, [c_void_p, c_void_p, c_void_p]),

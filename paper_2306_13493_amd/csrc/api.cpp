@@ -10,12 +10,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/cesmlmc.h"
-#include "internal.hpp"
+#include "plan.hpp"
 
 using namespace ces;
 
-namespace {
+namespace ces {
 
 thread_local std::string g_err;
 
@@ -27,11 +26,9 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(CES_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define CES_HIP(call, what)                         \
-    do {                                            \
-        hipError_t e__ = (call);                    \
-        if (e__ != hipSuccess) return hip_fail(e__, what); \
-    } while (0)
+}  // namespace ces
+
+namespace {
 
 constexpr double kPsdTol = 1e-13;
 
@@ -113,50 +110,7 @@ std::vector<cplx<T>> twiddles(int n) {
     return tw;
 }
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-    hipError_t alloc(size_t b) {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = b;
-        return b ? hipMalloc(&p, b) : hipSuccess;
-    }
-    template <typename U>
-    U* as() const { return reinterpret_cast<U*>(p); }
-};
-
 }  // namespace
-
-struct ces_context_s {
-    int device = 0;
-    size_t budget = 0;
-    size_t used = 0;
-};
-
-struct ces_plan_s {
-    ces_context ctx = nullptr;
-    ces_level_desc d{};
-    int n = 0, J = 0;
-    int64_t tau_f = 0, tau_c = 0;
-    double lam_min = 0, lam_max = 0, gap = 0;
-    int64_t n_clamped = 0;
-    std::vector<double> lam;            // symmetrised, clamped
-    std::vector<uint8_t> keep_f, keep_c;
-    bool is_double = false;
-    int nf = 1;                         // DFTs per unit
-    FftPlan fp{};
-    DevBuf af, ac, tw;
-    // sample workspace
-    int chunk_units = 0, chunk_slots = 0;
-    DevBuf work, kf, kc, qf, qc, itf, itc, zf, zc;
-    long long kf_ss = 0, kc_ss = 0;
-    std::unique_ptr<Solver> sf, sc;
-    size_t ws_bytes = 0;
-};
 
 namespace {
 
@@ -264,182 +218,6 @@ int upload_amplitudes(ces_plan p) {
     auto tw = twiddles<T>(n);
     CES_HIP(p->tw.alloc(tw.size() * sizeof(tw[0])), "twiddle buffer");
     CES_HIP(hipMemcpy(p->tw.p, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice), "upload twiddles");
-    return CES_OK;
-}
-
-size_t lvl_stride(int m) { return ((size_t)(m + 1) * (m + 1) + 63) / 64 * 64; }
-
-// bytes per slot (sample) of the sample workspace, estimate for chunking
-size_t slot_bytes(const ces_plan p) {
-    const int m = p->d.m_fine;
-    const size_t tb = p->is_double ? 8 : 4;
-    auto solver_bytes = [&](int mm) {
-        size_t b = lvl_stride(mm) * (6 * 8 + tb);
-        for (int l = mm / 2; l >= 2; l /= 2) b += lvl_stride(l) * 4 * tb;
-        return b + 64 * 8;
-    };
-    size_t b = solver_bytes(m) + lvl_stride(m) * tb;
-    if (p->d.level_kind == CES_LEVEL_PAIR) b += solver_bytes(m / 2) + lvl_stride(m / 2) * tb;
-    const size_t per_unit = (size_t)p->nf * (m + 1) * p->n * 2 * tb;
-    b += p->d.field_mode == CES_FIELD_PAIR ? per_unit / 2 : per_unit;
-    return b;
-}
-
-template <typename T>
-int ensure_workspace(ces_plan p) {
-    if (p->sf) return CES_OK;
-    const int m = p->d.m_fine;
-    const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
-    const size_t per_slot = slot_bytes(p);
-    size_t target = (size_t)4 << 30;
-    if (const char* env = std::getenv("CESMLMC_WORKSPACE_MB")) target = (size_t)std::atoll(env) << 20;
-    if (p->ctx->budget && p->ctx->budget - std::min(p->ctx->budget, p->ctx->used) < target)
-        target = p->ctx->budget - std::min(p->ctx->budget, p->ctx->used);
-    long long slots = (long long)(target / per_slot);
-    slots = std::min<long long>(slots, 8192);
-    if (pair_field) slots &= ~1LL;
-    if (slots < (pair_field ? 2 : 1))
-        return fail(CES_ERR_NOMEM, "device memory budget too small for one sample of this plan");
-    p->chunk_slots = (int)slots;
-    p->chunk_units = pair_field ? (int)slots / 2 : (int)slots;
-    const size_t tb = sizeof(T);
-    p->kf_ss = (long long)lvl_stride(m);
-    p->kc_ss = (long long)lvl_stride(m / 2);
-    CES_HIP(p->work.alloc((size_t)p->nf * p->chunk_units * (m + 1) * p->n * sizeof(cplx<T>)), "field workspace");
-    CES_HIP(p->kf.alloc((size_t)slots * p->kf_ss * tb), "coefficient workspace");
-    CES_HIP(hipMemset(p->kf.p, 0, p->kf.bytes), "coefficient workspace");
-    if (p->d.level_kind == CES_LEVEL_PAIR) {
-        CES_HIP(p->kc.alloc((size_t)slots * p->kc_ss * tb), "coefficient workspace");
-        CES_HIP(hipMemset(p->kc.p, 0, p->kc.bytes), "coefficient workspace");
-    }
-    CES_HIP(p->qf.alloc((size_t)slots * 8), "qoi workspace");
-    CES_HIP(p->qc.alloc((size_t)slots * 8), "qoi workspace");
-    CES_HIP(p->itf.alloc((size_t)slots * 4), "qoi workspace");
-    CES_HIP(p->itc.alloc((size_t)slots * 4), "qoi workspace");
-    SolverCfg cfg;
-    cfg.m = m;
-    cfg.bc = p->d.bc;
-    cfg.f = p->d.f_value;
-    cfg.rtol = p->d.cg_rtol;
-    cfg.maxit = p->d.cg_max_iter;
-    cfg.qoi = p->d.qoi;
-    cfg.qx = p->d.qoi_x;
-    cfg.qy = p->d.qoi_y;
-    std::string err;
-    p->sf = make_solver(cfg, (int)slots, p->is_double, &err);
-    if (!p->sf) return fail(CES_ERR_NOMEM, err);
-    if (p->d.level_kind == CES_LEVEL_PAIR) {
-        cfg.m = m / 2;
-        p->sc = make_solver(cfg, (int)slots, p->is_double, &err);
-        if (!p->sc) return fail(CES_ERR_NOMEM, err);
-    }
-    p->ws_bytes = p->work.bytes + p->kf.bytes + p->kc.bytes + p->sf->bytes() + (p->sc ? p->sc->bytes() : 0);
-    p->ctx->used += p->ws_bytes;
-    return CES_OK;
-}
-
-template <typename T>
-FieldBatch<T> field_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
-    FieldBatch<T> b;
-    b.n = p->n;
-    b.m = p->d.m_fine;
-    b.mode = p->d.field_mode == CES_FIELD_PAIR ? MODE_PAIR : MODE_HARTLEY;
-    b.nf = p->nf;
-    b.coarse = p->d.level_kind == CES_LEVEL_PAIR;
-    b.af = p->af.as<T>();
-    b.ac = p->nf == 2 ? p->ac.as<T>() : p->af.as<T>();
-    b.tw = p->tw.as<cplx<T>>();
-    b.fp = p->fp;
-    b.seed = seed;
-    b.q0 = q0;
-    b.stream = p->d.stream;
-    b.units = units;
-    b.work = p->work.as<cplx<T>>();
-    b.kf = p->kf.as<T>();
-    b.kf_stride = p->kf_ss;
-    b.kc = p->kc.as<T>();
-    b.kc_stride = p->kc_ss;
-    return b;
-}
-
-template <typename T>
-int sample_impl(ces_plan p, uint64_t seed, uint64_t first, int64_t count, double* y, double* yf, double* yc,
-                int32_t* iters, int32_t* status, hipStream_t st) {
-    int rc = ensure_workspace<T>(p);
-    if (rc != CES_OK) return rc;
-    const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
-    const bool pair_level = p->d.level_kind == CES_LEVEL_PAIR;
-    const int per_unit = pair_field ? 2 : 1;
-    const uint64_t last = first + (uint64_t)count - 1;
-    const uint64_t u_begin = first / per_unit, u_end = last / per_unit + 1;
-    for (uint64_t u0 = u_begin; u0 < u_end; u0 += (uint64_t)p->chunk_units) {
-        const int nu = (int)std::min<uint64_t>((uint64_t)p->chunk_units, u_end - u0);
-        const int nslots = nu * per_unit;
-        FieldBatch<T> b = field_batch<T>(p, seed, u0, nu);
-        CES_HIP(launch_field<T>(b, st), "field kernels");
-        CES_HIP(p->sf->solve(p->kf.p, p->kf_ss, nslots, st), "fine solve");
-        CES_HIP(p->sf->qoi(p->kf.p, p->kf_ss, nslots, p->qf.as<double>(), p->itf.as<int>(), st), "fine qoi");
-        if (pair_level) {
-            CES_HIP(p->sc->solve(p->kc.p, p->kc_ss, nslots, st), "coarse solve");
-            CES_HIP(p->sc->qoi(p->kc.p, p->kc_ss, nslots, p->qc.as<double>(), p->itc.as<int>(), st), "coarse qoi");
-        }
-        const uint64_t s0 = u0 * per_unit;
-        const uint64_t lo = std::max(first, s0), hi = std::min(last + 1, s0 + (uint64_t)nslots);
-        CES_HIP(launch_finalize(p->qf.as<double>(), pair_level ? p->qc.as<double>() : nullptr, p->itf.as<int>(),
-                                pair_level ? p->itc.as<int>() : nullptr, (int)(lo - s0), (int)(hi - lo),
-                                (long long)(lo - first), y, yf, yc, iters, status, st),
-                "finalize");
-    }
-    return CES_OK;
-}
-
-template <typename T>
-int field_impl(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, hipStream_t st) {
-    int rc = ensure_workspace<T>(p);
-    if (rc != CES_OK) return rc;
-    const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
-    const int m = p->d.m_fine;
-    const size_t nf = (size_t)(m + 1) * (m + 1), nc = (size_t)(m / 2 + 1) * (m / 2 + 1);
-    if (!p->zf.p) {
-        CES_HIP(p->zf.alloc(2 * nf * 8), "field hook buffers");
-        CES_HIP(p->zc.alloc(2 * nc * 8), "field hook buffers");
-    }
-    FieldBatch<T> b = field_batch<T>(p, seed, pair_field ? sample / 2 : sample, 1);
-    b.zf = p->zf.as<double>();
-    b.zc = p->zc.as<double>();
-    CES_HIP(launch_field<T>(b, st), "field kernels");
-    const int comp = pair_field ? (int)(sample % 2) : 0;
-    CES_HIP(hipMemcpyAsync(zf, p->zf.as<double>() + comp * nf, nf * 8, hipMemcpyDeviceToDevice, st), "copy field");
-    if (zc && p->d.level_kind == CES_LEVEL_PAIR)
-        CES_HIP(hipMemcpyAsync(zc, p->zc.as<double>() + comp * nc, nc * 8, hipMemcpyDeviceToDevice, st), "copy field");
-    return CES_OK;
-}
-
-template <typename T>
-int solve_impl(ces_plan p, int grid, int64_t count, const double* k, double* u, int32_t* iters, hipStream_t st) {
-    int rc = ensure_workspace<T>(p);
-    if (rc != CES_OK) return rc;
-    Solver* S = grid == 0 ? p->sf.get() : p->sc.get();
-    DevBuf& kb = grid == 0 ? p->kf : p->kc;
-    const long long kss = grid == 0 ? p->kf_ss : p->kc_ss;
-    const int m = grid == 0 ? p->d.m_fine : p->d.m_fine / 2;
-    const size_t nn = (size_t)(m + 1) * (m + 1);
-    for (int64_t c0 = 0; c0 < count; c0 += S->capacity()) {
-        const int ns = (int)std::min<int64_t>(S->capacity(), count - c0);
-        for (int i = 0; i < ns; ++i) {
-            const double* src = k + (size_t)(c0 + i) * nn;
-            T* dst = kb.as<T>() + (size_t)i * kss;
-            if (sizeof(T) == 8)
-                CES_HIP(hipMemcpyAsync(dst, src, nn * 8, hipMemcpyDeviceToDevice, st), "copy k");
-            else
-                CES_HIP(launch_convert_d2f(src, reinterpret_cast<float*>(dst), (long long)nn, st), "convert k");
-        }
-        CES_HIP(S->solve(kb.p, kss, ns, st), "solve");
-        CES_HIP(S->qoi(kb.p, kss, ns, nullptr, iters ? iters + c0 : nullptr, st), "solve status");
-        CES_HIP(hipMemcpy2DAsync(u + (size_t)c0 * nn, nn * 8, S->x(), (size_t)S->xstride() * 8, nn * 8, ns,
-                                 hipMemcpyDeviceToDevice, st),
-                "copy solution");
-    }
     return CES_OK;
 }
 
@@ -616,22 +394,9 @@ int ces_plan_info_get(ces_plan p, ces_plan_info* info) {
 int ces_plan_destroy(ces_plan p) {
     if (!p) return CES_OK;
     (void)hipSetDevice(p->ctx->device);
-    p->ctx->used -= std::min(p->ctx->used, p->ws_bytes);
+    p->ctx->used -= std::min(p->ctx->used.load(), p->ws_bytes);
     delete p;
     return CES_OK;
-}
-
-int ces_sample(ces_plan p, uint64_t seed, uint64_t first, int64_t count, double* y, double* yf, double* yc,
-               int32_t* iters, int32_t* status, void* stream) {
-    if (!p) return fail(CES_ERR_ARG, "plan is NULL");
-    if (count < 0) return fail(CES_ERR_ARG, "count < 0");
-    if (count == 0) return CES_OK;
-    if (!y) return fail(CES_ERR_ARG, "y is NULL");
-    if (first + (uint64_t)count < first) return fail(CES_ERR_ARG, "sample range overflows");
-    CES_HIP(hipSetDevice(p->ctx->device), "hipSetDevice");
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    return p->is_double ? sample_impl<double>(p, seed, first, count, y, yf, yc, iters, status, st)
-                        : sample_impl<float>(p, seed, first, count, y, yf, yc, iters, status, st);
 }
 
 int ces_normals(uint64_t seed, uint64_t q, uint32_t stream, uint64_t first_e, int64_t count, double* out,
@@ -660,7 +425,7 @@ int ces_field(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc
     if (!p || !zf) return fail(CES_ERR_ARG, "plan or z_fine is NULL");
     CES_HIP(hipSetDevice(p->ctx->device), "hipSetDevice");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    return p->is_double ? field_impl<double>(p, seed, sample, zf, zc, st) : field_impl<float>(p, seed, sample, zf, zc, st);
+    return field_impl(p, seed, sample, zf, zc, st);
 }
 
 int ces_solve(ces_plan p, int32_t grid, int64_t count, const double* k, double* u, int32_t* iters, void* stream) {
@@ -672,8 +437,7 @@ int ces_solve(ces_plan p, int32_t grid, int64_t count, const double* k, double* 
     if (!k || !u) return fail(CES_ERR_ARG, "k or u is NULL");
     CES_HIP(hipSetDevice(p->ctx->device), "hipSetDevice");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    return p->is_double ? solve_impl<double>(p, grid, count, k, u, iters, st)
-                        : solve_impl<float>(p, grid, count, k, u, iters, st);
+    return solve_impl(p, grid, count, k, u, iters, st);
 }
 
 }  // extern "C"

@@ -42,6 +42,30 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
     return s;
 }
 
+// Two block-wide sums in one pass (same order as block_sum for each).
+template <typename T>
+__device__ __forceinline__ void block_sum2(T& a, T& b, T* red2) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+    __syncthreads();
+    if (lane == 0) {
+        red2[wid] = a;
+        red2[nw + wid] = b;
+    }
+    __syncthreads();
+    T sa = red2[0], sb = red2[nw];
+    for (int w = 1; w < nw; ++w) {
+        sa += red2[w];
+        sb += red2[nw + w];
+    }
+    __syncthreads();
+    a = sa;
+    b = sb;
+}
+
 template <typename T>
 __device__ __forceinline__ T block_max(T v, T* red) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -70,5 +94,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+// Opt a kernel in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB).
+template <typename KernelT>
+hipError_t allow_lds(KernelT kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
 
 }  // namespace ces

@@ -1,0 +1,541 @@
+// Sample workspaces and the sampling scheduler behind ces_sample,
+// ces_sample_batch, ces_autotune and the serving loop: Algorithm 1 step 4
+// for every sample of a request and the level difference of Section 3.4,
+// for many requests of different mesh sizes at once.
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <thread>
+
+#include "plan.hpp"
+
+namespace ces {
+
+StreamPool::~StreamPool() {
+    for (auto s : streams_) (void)hipStreamDestroy(s);
+    for (auto e : events_) (void)hipEventDestroy(e);
+}
+
+hipError_t StreamPool::stream(size_t i, hipStream_t* out) {
+    while (streams_.size() <= i) {
+        hipStream_t s = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        streams_.push_back(s);
+    }
+    *out = streams_[i];
+    return hipSuccess;
+}
+
+hipError_t StreamPool::event(size_t i, hipEvent_t* out) {
+    while (events_.size() <= i) {
+        hipEvent_t v = nullptr;
+        hipError_t e = hipEventCreateWithFlags(&v, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        events_.push_back(v);
+    }
+    *out = events_[i];
+    return hipSuccess;
+}
+
+size_t lvl_stride(int m) { return ((size_t)(m + 1) * (m + 1) + 63) / 64 * 64; }
+
+size_t slot_bytes(const ces_plan p) {
+    const int m = p->d.m_fine;
+    const size_t tb = p->is_double ? 8 : 4;
+    auto solver_bytes = [&](int mm) {
+        if (mm <= 32) return lvl_stride(mm) * 8 + 64 + 16;
+        size_t b = lvl_stride(mm) * (6 * 8 + tb);
+        for (int l = mm / 2; l >= 2; l /= 2) b += lvl_stride(l) * 5 * tb;
+        return b + 64 * 8;
+    };
+    size_t b = solver_bytes(m) + lvl_stride(m) * tb;
+    if (p->d.level_kind == CES_LEVEL_PAIR) b += solver_bytes(m / 2) + lvl_stride(m / 2) * tb;
+    const size_t per_unit = (size_t)p->nf * (m + 1) * p->n * 2 * tb;
+    b += p->d.field_mode == CES_FIELD_PAIR ? per_unit / 2 : per_unit;
+    return b + 32;
+}
+
+int ensure_workspace(ces_plan p, long long max_slots) {
+    if (p->sf) return CES_OK;
+    const int m = p->d.m_fine;
+    const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
+    const size_t per_slot = slot_bytes(p);
+    size_t target = (size_t)4 << 30;
+    if (const char* env = std::getenv("CESMLMC_WORKSPACE_MB")) target = (size_t)std::atoll(env) << 20;
+    const size_t used = p->ctx->used.load();
+    if (p->ctx->budget && p->ctx->budget - std::min(p->ctx->budget, used) < target)
+        target = p->ctx->budget - std::min(p->ctx->budget, used);
+    long long slots = (long long)(target / per_slot);
+    slots = std::min<long long>(slots, 8192);
+    if (max_slots > 0) slots = std::min(slots, pair_field ? (max_slots + 1) / 2 * 2 : max_slots);
+    if (pair_field) slots &= ~1LL;
+    if (slots < (pair_field ? 2 : 1))
+        return fail(CES_ERR_NOMEM, "device memory budget too small for one sample of this plan");
+    p->chunk_slots = (int)slots;
+    p->chunk_units = pair_field ? (int)slots / 2 : (int)slots;
+    const size_t tb = p->is_double ? 8 : 4;
+    p->kf_ss = (long long)lvl_stride(m);
+    p->kc_ss = (long long)lvl_stride(m / 2);
+    CES_HIP(p->work.alloc((size_t)p->nf * p->chunk_units * (m + 1) * p->n * 2 * tb), "field workspace");
+    CES_HIP(p->kf.alloc((size_t)slots * p->kf_ss * tb), "coefficient workspace");
+    CES_HIP(hipMemset(p->kf.p, 0, p->kf.bytes), "coefficient workspace");
+    if (p->d.level_kind == CES_LEVEL_PAIR) {
+        CES_HIP(p->kc.alloc((size_t)slots * p->kc_ss * tb), "coefficient workspace");
+        CES_HIP(hipMemset(p->kc.p, 0, p->kc.bytes), "coefficient workspace");
+    }
+    CES_HIP(p->qf.alloc((size_t)slots * 8), "qoi workspace");
+    CES_HIP(p->qc.alloc((size_t)slots * 8), "qoi workspace");
+    CES_HIP(p->itf.alloc((size_t)slots * 4), "qoi workspace");
+    CES_HIP(p->itc.alloc((size_t)slots * 4), "qoi workspace");
+    SolverCfg cfg;
+    cfg.m = m;
+    cfg.bc = p->d.bc;
+    cfg.f = p->d.f_value;
+    cfg.rtol = p->d.cg_rtol;
+    cfg.maxit = p->d.cg_max_iter;
+    cfg.qoi = p->d.qoi;
+    cfg.qx = p->d.qoi_x;
+    cfg.qy = p->d.qoi_y;
+    std::string err;
+    p->sf = make_solver(cfg, (int)slots, p->is_double, &err);
+    if (!p->sf) return fail(CES_ERR_NOMEM, err);
+    if (p->d.level_kind == CES_LEVEL_PAIR) {
+        cfg.m = m / 2;
+        p->sc = make_solver(cfg, (int)slots, p->is_double, &err);
+        if (!p->sc) return fail(CES_ERR_NOMEM, err);
+    }
+    p->ws_bytes = p->work.bytes + p->kf.bytes + p->kc.bytes + p->sf->bytes() + (p->sc ? p->sc->bytes() : 0);
+    p->ctx->used += p->ws_bytes;
+    return CES_OK;
+}
+
+namespace {
+
+template <typename T>
+FieldBatch<T> field_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
+    FieldBatch<T> b;
+    b.n = p->n;
+    b.m = p->d.m_fine;
+    b.mode = p->d.field_mode == CES_FIELD_PAIR ? MODE_PAIR : MODE_HARTLEY;
+    b.nf = p->nf;
+    b.coarse = p->d.level_kind == CES_LEVEL_PAIR;
+    b.af = p->af.as<T>();
+    b.ac = p->nf == 2 ? p->ac.as<T>() : p->af.as<T>();
+    b.tw = p->tw.as<cplx<T>>();
+    b.fp = p->fp;
+    b.seed = seed;
+    b.q0 = q0;
+    b.stream = p->d.stream;
+    b.units = units;
+    b.work = p->work.as<cplx<T>>();
+    b.kf = p->kf.as<T>();
+    b.kf_stride = p->kf_ss;
+    b.kc = p->kc.as<T>();
+    b.kc_stride = p->kc_ss;
+    return b;
+}
+
+template <typename T>
+int field_t(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, hipStream_t st) {
+    const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
+    const int m = p->d.m_fine;
+    const size_t nf = (size_t)(m + 1) * (m + 1), nc = (size_t)(m / 2 + 1) * (m / 2 + 1);
+    if (!p->zf.p) {
+        CES_HIP(p->zf.alloc(2 * nf * 8), "field hook buffers");
+        CES_HIP(p->zc.alloc(2 * nc * 8), "field hook buffers");
+    }
+    FieldBatch<T> b = field_batch<T>(p, seed, pair_field ? sample / 2 : sample, 1);
+    b.zf = p->zf.as<double>();
+    b.zc = p->zc.as<double>();
+    CES_HIP(launch_field<T>(b, st), "field kernels");
+    const int comp = pair_field ? (int)(sample % 2) : 0;
+    CES_HIP(hipMemcpyAsync(zf, p->zf.as<double>() + comp * nf, nf * 8, hipMemcpyDeviceToDevice, st), "copy field");
+    if (zc && p->d.level_kind == CES_LEVEL_PAIR)
+        CES_HIP(hipMemcpyAsync(zc, p->zc.as<double>() + comp * nc, nc * 8, hipMemcpyDeviceToDevice, st), "copy field");
+    return CES_OK;
+}
+
+template <typename T>
+int solve_t(ces_plan p, int grid, int64_t count, const double* k, double* u, int32_t* iters, hipStream_t st) {
+    Solver* S = grid == 0 ? p->sf.get() : p->sc.get();
+    DevBuf& kb = grid == 0 ? p->kf : p->kc;
+    const long long kss = grid == 0 ? p->kf_ss : p->kc_ss;
+    const int m = grid == 0 ? p->d.m_fine : p->d.m_fine / 2;
+    const size_t nn = (size_t)(m + 1) * (m + 1);
+    for (int64_t c0 = 0; c0 < count; c0 += S->capacity()) {
+        const int ns = (int)std::min<int64_t>(S->capacity(), count - c0);
+        for (int i = 0; i < ns; ++i) {
+            const double* src = k + (size_t)(c0 + i) * nn;
+            T* dst = kb.as<T>() + (size_t)i * kss;
+            if (sizeof(T) == 8)
+                CES_HIP(hipMemcpyAsync(dst, src, nn * 8, hipMemcpyDeviceToDevice, st), "copy k");
+            else
+                CES_HIP(launch_convert_d2f(src, reinterpret_cast<float*>(dst), (long long)nn, st), "convert k");
+        }
+        CES_HIP(S->solve(kb.p, kss, ns, st), "solve");
+        CES_HIP(S->qoi(kb.p, kss, ns, nullptr, iters ? iters + c0 : nullptr, st), "solve status");
+        CES_HIP(hipMemcpy2DAsync(u + (size_t)c0 * nn, nn * 8, S->x(), (size_t)S->xstride() * 8, nn * 8, ns,
+                                 hipMemcpyDeviceToDevice, st),
+                "copy solution");
+    }
+    return CES_OK;
+}
+
+// marks a plan's workspace as taken for the lifetime of the guard
+struct BusyGuard {
+    ces_plan p = nullptr;
+    explicit BusyGuard(ces_plan q) {
+        int z = 0;
+        if (q->busy.compare_exchange_strong(z, 1)) p = q;
+    }
+    ~BusyGuard() {
+        if (p) p->busy.store(0);
+    }
+    bool ok() const { return p != nullptr; }
+};
+
+}  // namespace
+
+int field_impl(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, hipStream_t st) {
+    int rc = ensure_workspace(p, 0);
+    if (rc != CES_OK) return rc;
+    BusyGuard g(p);
+    if (!g.ok()) return fail(CES_ERR_BUSY, "plan is in use by another call");
+    return p->is_double ? field_t<double>(p, seed, sample, zf, zc, st) : field_t<float>(p, seed, sample, zf, zc, st);
+}
+
+int solve_impl(ces_plan p, int grid, int64_t count, const double* k, double* u, int32_t* iters, hipStream_t st) {
+    int rc = ensure_workspace(p, 0);
+    if (rc != CES_OK) return rc;
+    BusyGuard g(p);
+    if (!g.ok()) return fail(CES_ERR_BUSY, "plan is in use by another call");
+    return p->is_double ? solve_t<double>(p, grid, count, k, u, iters, st)
+                        : solve_t<float>(p, grid, count, k, u, iters, st);
+}
+
+// ------------------------------------------------------------ scheduler
+Scheduler::Scheduler(StreamPool& pool, hipStream_t caller, const ces_schedule& s)
+    : pool_(pool), caller_(caller), s_(s) {
+    if (s_.depth <= 0) s_.depth = 2;
+    s_.depth = std::min(s_.depth, 4);
+}
+
+Scheduler::~Scheduler() {
+    (void)join();
+}
+
+int Scheduler::lane_of(ces_plan p, Lane** out) {
+    for (auto& L : lanes_)
+        if (L->p == p) {
+            *out = L.get();
+            return CES_OK;
+        }
+    int z = 0;
+    if (!p->busy.compare_exchange_strong(z, 1)) return fail(CES_ERR_BUSY, "plan is in use by another call");
+    lanes_.emplace_back(new Lane);
+    lanes_.back()->p = p;
+    *out = lanes_.back().get();
+    return CES_OK;
+}
+
+int Scheduler::add(const ces_request& r, hipEvent_t done_event) {
+    ces_plan p = r.plan;
+    if (!p) return fail(CES_ERR_ARG, "request plan is NULL");
+    if (r.count < 0) return fail(CES_ERR_ARG, "count < 0");
+    if (r.count > 0 && !r.y) return fail(CES_ERR_ARG, "y is NULL");
+    if (r.first_sample + (uint64_t)r.count < r.first_sample) return fail(CES_ERR_ARG, "sample range overflows");
+    if (joined_) return fail(CES_ERR_ARG, "scheduler already joined");
+    if (r.count == 0) {
+        if (done_event) CES_HIP(hipEventRecord(done_event, caller_), "request event");
+        return CES_OK;
+    }
+    Lane* L = nullptr;
+    int rc = lane_of(p, &L);
+    if (rc != CES_OK) return rc;
+    if ((rc = ensure_workspace(p, 0)) != CES_OK) return rc;
+    const int per_unit = p->d.field_mode == CES_FIELD_PAIR ? 2 : 1;
+    long long cu = p->chunk_units;
+    if (s_.chunk_samples > 0) cu = std::max<long long>(1, std::min<long long>(cu, s_.chunk_samples / per_unit));
+    const uint64_t first = r.first_sample, last = first + (uint64_t)r.count - 1;
+    const uint64_t u_begin = first / per_unit, u_end = last / per_unit + 1;
+    for (uint64_t u0 = u_begin; u0 < u_end; u0 += (uint64_t)cu) {
+        Job j;
+        j.seed = r.seed;
+        j.u0 = u0;
+        j.units = (int)std::min<uint64_t>((uint64_t)cu, u_end - u0);
+        j.first = first;
+        const uint64_t s0 = u0 * per_unit;
+        j.lo = std::max(first, s0);
+        j.hi = std::min(last + 1, s0 + (uint64_t)j.units * per_unit);
+        j.y = r.y;
+        j.yf = r.q_fine;
+        j.yc = r.q_coarse;
+        j.iters = r.iters;
+        j.status = r.status;
+        j.done_event = u0 + (uint64_t)cu >= u_end ? done_event : nullptr;
+        L->jobs.push_back(j);
+    }
+    return CES_OK;
+}
+
+template <typename T>
+int Scheduler::start_t(Lane& L, const Job& j) {
+    ces_plan p = L.p;
+    const int per_unit = p->d.field_mode == CES_FIELD_PAIR ? 2 : 1;
+    const int nslots = j.units * per_unit;
+    FieldBatch<T> b = field_batch<T>(p, j.seed, j.u0, j.units);
+    CES_HIP(launch_field<T>(b, L.sa), "field kernels");
+    CES_HIP(p->sf->begin(p->kf.p, p->kf_ss, nslots, L.sa), "fine solve");
+    if (p->sc) {
+        CES_HIP(hipEventRecord(L.ev_f, L.sa), "lane event");
+        CES_HIP(hipStreamWaitEvent(L.sb, L.ev_f, 0), "lane event");
+        CES_HIP(p->sc->begin(p->kc.p, p->kc_ss, nslots, L.sb), "coarse solve");
+    }
+    L.solving = true;
+    L.fdone = L.cdone = false;
+    return CES_OK;
+}
+
+int Scheduler::start(Lane& L) {
+    if (!fork_) {
+        CES_HIP(pool_.event(next_event_++, &fork_), "scheduler event");
+        CES_HIP(hipEventRecord(fork_, caller_), "fork");
+    }
+    if (!L.forked) {
+        CES_HIP(pool_.stream(next_stream_++, &L.sa), "lane stream");
+        CES_HIP(pool_.stream(next_stream_++, &L.sb), "lane stream");
+        CES_HIP(pool_.event(next_event_++, &L.ev_f), "lane event");
+        CES_HIP(pool_.event(next_event_++, &L.ev_c), "lane event");
+        CES_HIP(hipStreamWaitEvent(L.sa, fork_, 0), "fork");
+        CES_HIP(hipStreamWaitEvent(L.sb, fork_, 0), "fork");
+        L.forked = true;
+    }
+    const Job& j = L.jobs[L.next];
+    return L.p->is_double ? start_t<double>(L, j) : start_t<float>(L, j);
+}
+
+int Scheduler::finish(Lane& L) {
+    ces_plan p = L.p;
+    const Job& j = L.jobs[L.next];
+    const int per_unit = p->d.field_mode == CES_FIELD_PAIR ? 2 : 1;
+    const int nslots = j.units * per_unit;
+    CES_HIP(p->sf->finish(L.sa), "fine solve");
+    CES_HIP(p->sf->qoi(p->kf.p, p->kf_ss, nslots, p->qf.as<double>(), p->itf.as<int>(), L.sa), "fine qoi");
+    if (p->sc) {
+        CES_HIP(p->sc->finish(L.sb), "coarse solve");
+        CES_HIP(p->sc->qoi(p->kc.p, p->kc_ss, nslots, p->qc.as<double>(), p->itc.as<int>(), L.sb), "coarse qoi");
+        CES_HIP(hipEventRecord(L.ev_c, L.sb), "lane event");
+        CES_HIP(hipStreamWaitEvent(L.sa, L.ev_c, 0), "lane event");
+    }
+    const uint64_t s0 = j.u0 * per_unit;
+    CES_HIP(launch_finalize(p->qf.as<double>(), p->sc ? p->qc.as<double>() : nullptr, p->itf.as<int>(),
+                            p->sc ? p->itc.as<int>() : nullptr, (int)(j.lo - s0), (int)(j.hi - j.lo),
+                            (long long)(j.lo - j.first), j.y, j.yf, j.yc, j.iters, j.status, L.sa),
+            "finalize");
+    if (j.done_event) CES_HIP(hipEventRecord(j.done_event, L.sa), "request event");
+    ++L.next;
+    L.solving = false;
+    return CES_OK;
+}
+
+int Scheduler::step(bool* progressed) {
+    *progressed = false;
+    int busy = 0;
+    for (auto& L : lanes_) busy += L->solving ? 1 : 0;
+    for (auto& Lp : lanes_) {
+        Lane& L = *Lp;
+        if (!L.solving) {
+            if (L.next < L.jobs.size() && (s_.max_lanes <= 0 || busy < s_.max_lanes)) {
+                int rc = start(L);
+                if (rc != CES_OK) return rc;
+                ++busy;
+                *progressed = true;
+            }
+            continue;
+        }
+        bool pf = false, pc = false;
+        if (!L.fdone) CES_HIP(L.p->sf->advance(L.sa, s_.depth, &L.fdone, &pf), "fine solve");
+        if (L.p->sc && !L.cdone) CES_HIP(L.p->sc->advance(L.sb, s_.depth, &L.cdone, &pc), "coarse solve");
+        if (pf || pc) *progressed = true;
+        if (L.fdone && (L.cdone || !L.p->sc)) {
+            int rc = finish(L);
+            if (rc != CES_OK) return rc;
+            --busy;
+            *progressed = true;
+        }
+    }
+    return CES_OK;
+}
+
+bool Scheduler::idle() const {
+    for (auto& L : lanes_)
+        if (L->solving || L->next < L->jobs.size()) return false;
+    return true;
+}
+
+int Scheduler::run() {
+    while (!idle()) {
+        bool prog = false;
+        int rc = step(&prog);
+        if (rc != CES_OK) return rc;
+        if (prog) continue;
+        // nothing could be enqueued: every solve has `depth` iterations in
+        // flight.  Block when one solve is pending, else poll again.
+        Solver* only = nullptr;
+        int pending = 0;
+        for (auto& L : lanes_) {
+            if (!L->solving) continue;
+            if (!L->fdone) { only = L->p->sf.get(); ++pending; }
+            if (L->p->sc && !L->cdone) { only = L->p->sc.get(); ++pending; }
+        }
+        if (pending == 1) CES_HIP(only->wait(), "solve wait");
+        else std::this_thread::yield();
+    }
+    return CES_OK;
+}
+
+int Scheduler::join() {
+    if (joined_) return CES_OK;
+    joined_ = true;
+    int rc = CES_OK;
+    for (auto& L : lanes_) {
+        if (L->forked) {
+            for (hipStream_t s : {L->sa, L->sb}) {
+                hipEvent_t e = nullptr;
+                hipError_t err = pool_.event(next_event_++, &e);
+                if (err == hipSuccess) err = hipEventRecord(e, s);
+                if (err == hipSuccess) err = hipStreamWaitEvent(caller_, e, 0);
+                if (err != hipSuccess && rc == CES_OK) rc = hip_fail(err, "join");
+            }
+        }
+        L->p->busy.store(0);
+    }
+    return rc;
+}
+
+}  // namespace ces
+
+using namespace ces;
+
+namespace {
+
+int run_batch(ces_context ctx, const ces_request* reqs, int32_t nreq, hipStream_t st, const ces_schedule& s) {
+    Scheduler S(ctx->pool, st, s);
+    for (int32_t i = 0; i < nreq; ++i) {
+        if (reqs[i].plan && reqs[i].plan->ctx != ctx) return fail(CES_ERR_ARG, "request plan belongs to another context");
+        int rc = S.add(reqs[i], nullptr);
+        if (rc != CES_OK) return rc;
+    }
+    int rc = S.run();
+    int rj = S.join();
+    return rc != CES_OK ? rc : rj;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ces_sample(ces_plan p, uint64_t seed, uint64_t first, int64_t count, double* y, double* yf, double* yc,
+               int32_t* iters, int32_t* status, void* stream) {
+    if (!p) return fail(CES_ERR_ARG, "plan is NULL");
+    if (count < 0) return fail(CES_ERR_ARG, "count < 0");
+    if (count == 0) return CES_OK;
+    if (!y) return fail(CES_ERR_ARG, "y is NULL");
+    if (first + (uint64_t)count < first) return fail(CES_ERR_ARG, "sample range overflows");
+    CES_HIP(hipSetDevice(p->ctx->device), "hipSetDevice");
+    ces_request r{p, seed, first, count, y, yf, yc, iters, status};
+    return run_batch(p->ctx, &r, 1, reinterpret_cast<hipStream_t>(stream), p->ctx->sched);
+}
+
+int ces_sample_batch(ces_context ctx, const ces_request* reqs, int32_t nreq, void* stream) {
+    if (!ctx) return fail(CES_ERR_ARG, "context is NULL");
+    if (nreq < 0 || (nreq > 0 && !reqs)) return fail(CES_ERR_ARG, "requests");
+    if (nreq == 0) return CES_OK;
+    CES_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    return run_batch(ctx, reqs, nreq, reinterpret_cast<hipStream_t>(stream), ctx->sched);
+}
+
+int ces_schedule_get(ces_context ctx, ces_schedule* out) {
+    if (!ctx || !out) return fail(CES_ERR_ARG, "context or out is NULL");
+    *out = ctx->sched;
+    if (out->depth <= 0) out->depth = 2;
+    return CES_OK;
+}
+
+int ces_schedule_set(ces_context ctx, const ces_schedule* s) {
+    if (!ctx || !s) return fail(CES_ERR_ARG, "context or schedule is NULL");
+    if (s->depth < 0 || s->depth > 4) return fail(CES_ERR_ARG, "depth must be in 0..4");
+    if (s->max_lanes < 0 || s->chunk_samples < 0) return fail(CES_ERR_ARG, "max_lanes / chunk_samples < 0");
+    ctx->sched = *s;
+    if (ctx->sched.depth == 0) ctx->sched.depth = 2;
+    return CES_OK;
+}
+
+int ces_autotune(ces_context ctx, const ces_request* reqs, int32_t nreq, void* stream, ces_schedule* chosen,
+                 double* best_ms) {
+    if (!ctx) return fail(CES_ERR_ARG, "context is NULL");
+    if (nreq <= 0 || !reqs) return fail(CES_ERR_ARG, "requests");
+    CES_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    auto timed = [&](const ces_schedule& s, double* ms) -> int {
+        double best = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            CES_HIP(hipStreamSynchronize(st), "autotune sync");
+            const auto t0 = std::chrono::steady_clock::now();
+            int rc = run_batch(ctx, reqs, nreq, st, s);
+            if (rc != CES_OK) return rc;
+            CES_HIP(hipStreamSynchronize(st), "autotune sync");
+            best = std::min(best, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        *ms = best;
+        return CES_OK;
+    };
+    int nplans = 0;
+    for (int32_t i = 0; i < nreq; ++i) {
+        bool seen = false;
+        for (int32_t j = 0; j < i; ++j) seen = seen || reqs[j].plan == reqs[i].plan;
+        nplans += seen ? 0 : 1;
+    }
+    ces_schedule best = ctx->sched;
+    if (best.depth <= 0) best.depth = 2;
+    int rc = run_batch(ctx, reqs, nreq, st, best);   // warm-up, allocates workspaces
+    if (rc != CES_OK) return rc;
+    double tbest = 0.0;
+    if ((rc = timed(best, &tbest)) != CES_OK) return rc;
+    auto consider = [&](ces_schedule c) -> int {
+        double t = 0.0;
+        int r = timed(c, &t);
+        if (r != CES_OK) return r;
+        if (t < 0.97 * tbest) {
+            best = c;
+            tbest = t;
+        }
+        return CES_OK;
+    };
+    // coordinate search: in-flight depth, concurrent lanes, chunk size
+    for (int d = 1; d <= 4; ++d)
+        if (d != best.depth) {
+            ces_schedule c = best;
+            c.depth = d;
+            if ((rc = consider(c)) != CES_OK) return rc;
+        }
+    for (int lanes : {0, 1, 2, 4})
+        if (lanes != best.max_lanes && lanes < nplans) {
+            ces_schedule c = best;
+            c.max_lanes = lanes;
+            if ((rc = consider(c)) != CES_OK) return rc;
+        }
+    for (long long ch : {0LL, 2048LL, 512LL})
+        if (ch != best.chunk_samples) {
+            ces_schedule c = best;
+            c.chunk_samples = ch;
+            if ((rc = consider(c)) != CES_OK) return rc;
+        }
+    ctx->sched = best;
+    if (chosen) *chosen = best;
+    if (best_ms) *best_ms = tbest;
+    return CES_OK;
+}
+
+}  // extern "C"

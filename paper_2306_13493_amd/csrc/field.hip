@@ -190,13 +190,6 @@ __global__ __launch_bounds__(kBlock) void k_convert_d2f(const double* __restrict
     if (t < count) out[t] = (float)in[t];
 }
 
-template <typename KernelT>
-hipError_t allow_lds(KernelT kernel, size_t bytes) {
-    if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
 template <typename T, int E, int MODE, int NF>
 hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2) {
     const size_t lds1 = (size_t)NF * L1 * b.n * sizeof(cplx<T>);

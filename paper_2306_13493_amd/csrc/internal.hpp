@@ -66,17 +66,38 @@ struct SolverCfg {
 };
 
 // Batched PCG (double) preconditioned by a geometric multigrid V(2,2) cycle
-// in T, for S samples of one mesh at a time.
+// in T, for S samples of one mesh at a time.  A solve is a small state
+// machine so that one host thread can interleave the solves of several
+// meshes on several streams: begin() enqueues the set-up, each advance()
+// enqueues at most one more iteration and notes (without blocking) which
+// enqueued iterations have finished; the solve is done once the count of
+// unconverged samples read back after some iteration is zero.
 class Solver {
 public:
     virtual ~Solver() = default;
     virtual int capacity() const = 0;
     virtual size_t bytes() const = 0;
     virtual int mg_levels() const = 0;
-    // k: capacity x kstride values of T (slot s at k + s*kstride).
-    // Runs to convergence for slots [0, S).  Polls the device a bounded
-    // number of times.  Returns hipSuccess or the first HIP error.
-    virtual hipError_t solve(const void* k, long long kstride, int S, hipStream_t st) = 0;
+    // k: capacity x kstride values of T (slot s at k + s*kstride); slots
+    // [0, S) are solved.
+    virtual hipError_t begin(const void* k, long long kstride, int S, hipStream_t st) = 0;
+    // depth: iterations allowed in flight before their convergence count
+    // has been read back (1..4).  *progressed: an iteration was enqueued.
+    virtual hipError_t advance(hipStream_t st, int depth, bool* done, bool* progressed) = 0;
+    // block until the oldest unconfirmed iteration has finished
+    virtual hipError_t wait() = 0;
+    // bookkeeping after the solve (launch profiler only; may synchronise)
+    virtual hipError_t finish(hipStream_t st) = 0;
+    // begin + advance to the end + finish
+    hipError_t solve(const void* k, long long kstride, int S, hipStream_t st, int depth = 2) {
+        hipError_t e = begin(k, kstride, S, st);
+        bool done = false, prog = false;
+        while (e == hipSuccess && !done) {
+            e = advance(st, depth, &done, &prog);
+            if (e == hipSuccess && !done && !prog) e = wait();
+        }
+        return e == hipSuccess ? finish(st) : e;
+    }
     // QoI of the last solve for slots [0, S): q[s], iters[s] (-it if not
     // converged); either may be null.
     virtual hipError_t qoi(const void* k, long long kstride, int S, double* q, int* iters,

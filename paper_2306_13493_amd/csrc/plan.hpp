@@ -1,0 +1,165 @@
+// Library-private state behind the C ABI handles and the interfaces
+// between api.cpp (plan set-up, parity hooks), exec.cpp (workspaces and
+// the sampling scheduler) and server.cpp (the serving loop).
+#pragma once
+
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/cesmlmc.h"
+#include "internal.hpp"
+
+namespace ces {
+
+// Sets the calling thread's ces_last_error() message; returns code.
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define CES_HIP(call, what)                                \
+    do {                                                   \
+        hipError_t e__ = (call);                           \
+        if (e__ != hipSuccess) return ces::hip_fail(e__, what); \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t b) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = b;
+        return b ? hipMalloc(&p, b) : hipSuccess;
+    }
+    template <typename U>
+    U* as() const { return reinterpret_cast<U*>(p); }
+};
+
+// Streams (default priority, non-blocking) and events, created on first
+// use and kept until the owner goes away.  One pool per host thread that
+// schedules work (a context's caller, a server's loop).
+class StreamPool {
+public:
+    StreamPool() = default;
+    StreamPool(const StreamPool&) = delete;
+    StreamPool& operator=(const StreamPool&) = delete;
+    ~StreamPool();
+    hipError_t stream(size_t i, hipStream_t* out);
+    hipError_t event(size_t i, hipEvent_t* out);
+
+private:
+    std::vector<hipStream_t> streams_;
+    std::vector<hipEvent_t> events_;
+};
+
+size_t lvl_stride(int m);
+
+}  // namespace ces
+
+struct ces_context_s {
+    int device = 0;
+    size_t budget = 0;
+    std::atomic<size_t> used{0};
+    ces_schedule sched{};
+    ces::StreamPool pool;
+};
+
+struct ces_plan_s {
+    ces_context ctx = nullptr;
+    ces_level_desc d{};
+    int n = 0, J = 0;
+    int64_t tau_f = 0, tau_c = 0;
+    double lam_min = 0, lam_max = 0, gap = 0;
+    int64_t n_clamped = 0;
+    std::vector<double> lam;            // symmetrised, clamped
+    std::vector<uint8_t> keep_f, keep_c;
+    bool is_double = false;
+    int nf = 1;                         // DFTs per unit
+    ces::FftPlan fp{};
+    ces::DevBuf af, ac, tw;
+    // sample workspace
+    int chunk_units = 0, chunk_slots = 0;
+    ces::DevBuf work, kf, kc, qf, qc, itf, itc, zf, zc;
+    long long kf_ss = 0, kc_ss = 0;
+    std::unique_ptr<ces::Solver> sf, sc;
+    size_t ws_bytes = 0;
+    std::atomic<int> busy{0};           // a scheduler is using the workspace
+};
+
+namespace ces {
+
+// Device bytes per in-flight sample of a plan's workspace.
+size_t slot_bytes(const ces_plan p);
+
+// Allocates the plan's sample workspace on first use.  max_slots > 0 caps
+// the samples per chunk (the serving loop sizes workspaces per request);
+// 0 sizes it for throughput (about 4 GiB, at most 8192 samples).
+int ensure_workspace(ces_plan p, long long max_slots);
+
+// Gaussian field of one sample into z_fine / z_coarse (parity hook).
+int field_impl(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, hipStream_t st);
+// Solve for caller-given coefficients (parity hook).
+int solve_impl(ces_plan p, int grid, int64_t count, const double* k, double* u, int32_t* iters,
+               hipStream_t st);
+
+// The sampling scheduler: requests are split into chunks of their plan's
+// workspace capacity; each distinct plan is a lane with two streams forked
+// from the caller's stream (field + fine solve + finalize, coarse solve)
+// and joined back at the end; one host thread interleaves the lanes,
+// keeping up to `depth` CG iterations of every solve in flight.
+class Scheduler {
+public:
+    Scheduler(StreamPool& pool, hipStream_t caller, const ces_schedule& s);
+    ~Scheduler();
+    // Queue one request; done_event (may be null) is recorded once all of
+    // its results are written.
+    int add(const ces_request& r, hipEvent_t done_event);
+    // One pass over the lanes; *progressed = some work was enqueued.
+    int step(bool* progressed);
+    bool idle() const;
+    // step() until idle, waiting on the device when nothing can progress
+    int run();
+    // make the caller's stream wait for every lane (ends the scheduler's use
+    // of the plans)
+    int join();
+
+private:
+    struct Job {
+        uint64_t seed, u0, first, lo, hi;
+        int units;
+        double *y, *yf, *yc;
+        int32_t *iters, *status;
+        hipEvent_t done_event;
+    };
+    struct Lane {
+        ces_plan p = nullptr;
+        std::vector<Job> jobs;
+        size_t next = 0;
+        bool solving = false, fdone = false, cdone = false, forked = false;
+        hipStream_t sa = nullptr, sb = nullptr;
+        hipEvent_t ev_f = nullptr, ev_c = nullptr;
+    };
+    int lane_of(ces_plan p, Lane** out);
+    int start(Lane& L);
+    int finish(Lane& L);
+    template <typename T>
+    int start_t(Lane& L, const Job& j);
+
+    StreamPool& pool_;
+    hipStream_t caller_;
+    ces_schedule s_;
+    hipEvent_t fork_ = nullptr;
+    std::vector<std::unique_ptr<Lane>> lanes_;
+    size_t next_stream_ = 0, next_event_ = 0;
+    bool joined_ = false;
+};
+
+}  // namespace ces

@@ -415,34 +415,37 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
 }
 
 // ------------------------------------------------ whole-V-cycle bottom ---
+// ------------------------------------------------- LDS-resident multigrid
+// Levels with m <= 32 (16 in double) of one sample live in one workgroup's
+// LDS: z, rhs, edge conductances and inverse diagonals of every level,
+// stored level after level (level l at off[l], row pitch m_l + 1), plus a
+// scratch array the size of the finest of them.
 template <typename T>
-struct BottomArgs {
-    int nl;            // levels handled here: m0, m0/2, ..., 2
-    int bc;
+struct LdsMg {
+    T *z, *rhs, *ce, *cn, *id, *tmp;
+    int off[8];
     Lvl L[8];
-    const T* k0;       // k of the global level 0 (when it is the bottom's first level)
-    long long kss0;
-    const T* ce[8];    // stored edge conductances of coarse levels (stride L[l].ss)
-    const T* cn[8];
-    const void* rhs;   // level-0-of-bottom rhs: double (global level 0) or T
-    void* zout;        // z of the bottom's finest level
-    double* dot;       // global level 0: partial r.z (1 per sample)
-    double* dot2;      // global level 0: partial z.q_old
-    const double* q;   // global level 0: q_old
-    const Scal* scal;
+    int nl, bc;
 };
 
-template <int MB>
-struct BottomSize {
-    static constexpr int tot() {
-        int t = 0;
-        for (int mm = MB; mm >= 2; mm /= 2) t += (mm + 1) * (mm + 1);
-        return t;
+__host__ __device__ constexpr int lds_mg_nodes(int m) {
+    int t = 0;
+    for (int mm = m; mm >= 2; mm /= 2) t += (mm + 1) * (mm + 1);
+    return t;
+}
+
+template <typename T>
+__device__ void lds_mg_layout(LdsMg<T>& g) {
+    int o = 0;
+    for (int l = 0; l < g.nl; ++l) {
+        g.off[l] = o;
+        o += g.L[l].w * g.L[l].w;
     }
-};
+}
 
-template <typename T, int MB>
-__device__ void bottom_sweep(T* z, const T* rhs, const T* ce, const T* cn, const T* id, int m, int c) {
+// one red-black half-sweep of colour c (parity of x + y) on one level
+template <typename T>
+__device__ void lds_sweep(T* z, const T* rhs, const T* ce, const T* cn, const T* id, int m, int c) {
     const int w = m + 1;
     const int half = (w + 1) / 2;
     for (int t = threadIdx.x; t < half * w; t += blockDim.x) {
@@ -462,78 +465,41 @@ __device__ void bottom_sweep(T* z, const T* rhs, const T* ce, const T* cn, const
     __syncthreads();
 }
 
-template <typename T, int MB, bool L0>
-__global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
-    constexpr int TOT = BottomSize<MB>::tot();
-    __shared__ T z[TOT], rhs[TOT], ce[TOT], cn[TOT], id[TOT];
-    __shared__ T tmp[(MB + 1) * (MB + 1)];
-    __shared__ double red[kBlock / 64];
-    const int s = blockIdx.x;
-    if (!a.scal[s].active) return;
-    int off[8];
-    {
-        int o = 0;
-        for (int l = 0; l < a.nl; ++l) {
-            off[l] = o;
-            o += a.L[l].w * a.L[l].w;
-        }
-    }
-    // conductances and inverse diagonals of every level
-    for (int l = 0; l < a.nl; ++l) {
-        const int m = a.L[l].m, w = a.L[l].w;
-        if (L0 && l == 0) {
-            const T* kg = a.k0 + (size_t)s * a.kss0;
-            for (int t = threadIdx.x; t < w * w; t += blockDim.x) tmp[t] = kg[t];
-            __syncthreads();
-            auto K = [&](int gx, int gy) -> T { return tmp[gy * w + gx]; };
-            for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-                const int y = t / w, x = t - y * w;
-                ce[off[l] + t] = cond_e<T>(x, y, m, K);
-                cn[off[l] + t] = cond_n<T>(x, y, m, K);
-                z[off[l] + t] = T(0);
-            }
-        } else {
-            const T* ceg = a.ce[l] + (size_t)s * a.L[l].ss;
-            const T* cng = a.cn[l] + (size_t)s * a.L[l].ss;
-            for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-                ce[off[l] + t] = ceg[t];
-                cn[off[l] + t] = cng[t];
-                z[off[l] + t] = T(0);
-            }
-        }
-        __syncthreads();
+// inverse diagonals of every level (zero off the unknowns)
+template <typename T>
+__device__ void lds_mg_diag(const LdsMg<T>& g) {
+    for (int l = 0; l < g.nl; ++l) {
+        const int m = g.L[l].m, w = g.L[l].w, o = g.off[l];
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
             const int y = t / w, x = t - y * w;
             T v = T(0);
-            if (is_unknown(x, y, m, a.bc)) {
-                const int p = off[l] + t;
-                v = T(1) / (ce[p] + ce[p - 1] + cn[p] + (y >= 1 ? cn[p - w] : T(0)));
+            if (is_unknown(x, y, m, g.bc)) {
+                const int p = o + t;
+                v = T(1) / (g.ce[p] + g.ce[p - 1] + g.cn[p] + (y >= 1 ? g.cn[p - w] : T(0)));
             }
-            id[off[l] + t] = v;
+            g.id[o + t] = v;
         }
-        __syncthreads();
     }
-    {
-        const int m = a.L[0].m, w = a.L[0].w;
+    __syncthreads();
+}
+
+// One V(2,2) cycle from z = 0 with the level-0 rhs in place; z of every
+// level is overwritten, level 0's holds the result.
+template <typename T>
+__device__ void lds_vcycle(const LdsMg<T>& g) {
+    const int tot = g.off[g.nl - 1] + g.L[g.nl - 1].w * g.L[g.nl - 1].w;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) g.z[t] = T(0);
+    __syncthreads();
+    T *z = g.z, *rhs = g.rhs, *tmp = g.tmp;
+    const T *ce = g.ce, *cn = g.cn, *id = g.id;
+    // down: pre-smooth, residual, restriction (transpose of bilinear)
+    for (int l = 0; l + 1 < g.nl; ++l) {
+        const int m = g.L[l].m, w = g.L[l].w, o = g.off[l];
+        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, id + o, m, c & 1);
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
             const int y = t / w, x = t - y * w;
             T r = T(0);
-            if (is_unknown(x, y, m, a.bc)) {
-                r = L0 ? (T)(reinterpret_cast<const double*>(a.rhs)[(size_t)s * a.L[0].ss + t])
-                       : reinterpret_cast<const T*>(a.rhs)[(size_t)s * a.L[0].ss + t];
-            }
-            rhs[t] = r;
-        }
-        __syncthreads();
-    }
-    // down
-    for (int l = 0; l + 1 < a.nl; ++l) {
-        const int m = a.L[l].m, w = a.L[l].w, o = off[l];
-        for (int c = 0; c < 4; ++c) bottom_sweep<T, MB>(z + o, rhs + o, ce + o, cn + o, id + o, m, c & 1);
-        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-            const int y = t / w, x = t - y * w;
-            T r = T(0);
-            if (is_unknown(x, y, m, a.bc)) {
+            if (is_unknown(x, y, m, g.bc)) {
                 const int p = o + t;
                 const T zp = z[p];
                 const T zN = y + 1 < w ? z[p + w] : T(0), zS = y >= 1 ? z[p - w] : T(0);
@@ -545,11 +511,11 @@ __global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
             tmp[t] = r;
         }
         __syncthreads();
-        const int cm = a.L[l + 1].m, cwid = a.L[l + 1].w, co = off[l + 1];
+        const int cm = g.L[l + 1].m, cwid = g.L[l + 1].w, co = g.off[l + 1];
         for (int t = threadIdx.x; t < cwid * cwid; t += blockDim.x) {
             const int J = t / cwid, I = t - J * cwid;
             T v = T(0);
-            if (is_unknown(I, J, cm, a.bc)) {
+            if (is_unknown(I, J, cm, g.bc)) {
                 const int x = 2 * I, y = 2 * J;
                 auto R = [&](int xx, int yy) -> T {
                     return (xx >= 0 && xx < w && yy >= 0 && yy < w) ? tmp[yy * w + xx] : T(0);
@@ -563,8 +529,8 @@ __global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
     }
     // coarsest (m = 2): exact tridiagonal solve along the unknown column x = 1
     if (threadIdx.x == 0) {
-        const int l = a.nl - 1, w = a.L[l].w, o = off[l];
-        const int ylo = a.L[l].ylo, yhi = a.L[l].yhi;
+        const int l = g.nl - 1, w = g.L[l].w, o = g.off[l];
+        const int ylo = g.L[l].ylo, yhi = g.L[l].yhi;
         T beta[3], yv[3];
         for (int j = ylo; j <= yhi; ++j) {
             const int p = o + j * w + 1;
@@ -588,16 +554,16 @@ __global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
         }
     }
     __syncthreads();
-    // up
-    for (int l = a.nl - 2; l >= 0; --l) {
-        const int m = a.L[l].m, w = a.L[l].w, o = off[l];
-        const int cm = a.L[l + 1].m, cwid = a.L[l + 1].w, co = off[l + 1];
+    // up: bilinear prolongation of the correction, post-smooth
+    for (int l = g.nl - 2; l >= 0; --l) {
+        const int m = g.L[l].m, w = g.L[l].w, o = g.off[l];
+        const int cm = g.L[l + 1].m, cwid = g.L[l + 1].w, co = g.off[l + 1];
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
             const int y = t / w, x = t - y * w;
-            if (!is_unknown(x, y, m, a.bc)) continue;
+            if (!is_unknown(x, y, m, g.bc)) continue;
             const int I = x >> 1, J = y >> 1;
             auto C = [&](int ci, int cj) -> T {
-                return is_unknown(ci, cj, cm, a.bc) ? z[co + cj * cwid + ci] : T(0);
+                return is_unknown(ci, cj, cm, g.bc) ? z[co + cj * cwid + ci] : T(0);
             };
             T p;
             const bool ox1 = x & 1, oy1 = y & 1;
@@ -608,31 +574,61 @@ __global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
             z[o + t] += p;
         }
         __syncthreads();
-        for (int c = 0; c < 4; ++c) bottom_sweep<T, MB>(z + o, rhs + o, ce + o, cn + o, id + o, m, 1 - (c & 1));
+        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, id + o, m, 1 - (c & 1));
     }
-    // write
+}
+
+// Bottom of the tiled V-cycle: the levels with m <= MB of each sample in
+// one workgroup (stored conductances, rhs from the next finer level).
+template <typename T>
+struct BottomArgs {
+    int nl;            // levels handled here: m0, m0/2, ..., 2
+    int bc;
+    Lvl L[8];
+    const T* ce[8];    // stored edge conductances (stride L[l].ss)
+    const T* cn[8];
+    const T* rhs;      // rhs of the first bottom level
+    T* zout;           // its z
+    const Scal* scal;
+};
+
+template <typename T, int MB>
+__global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
+    constexpr int TOT = lds_mg_nodes(MB);
+    __shared__ T z[TOT], rhs[TOT], ce[TOT], cn[TOT], id[TOT];
+    __shared__ T tmp[(MB + 1) * (MB + 1)];
+    const int s = blockIdx.x;
+    if (!a.scal[s].active) return;
+    LdsMg<T> g;
+    g.z = z; g.rhs = rhs; g.ce = ce; g.cn = cn; g.id = id; g.tmp = tmp;
+    g.nl = a.nl;
+    g.bc = a.bc;
+    for (int l = 0; l < a.nl; ++l) g.L[l] = a.L[l];
+    lds_mg_layout(g);
+    for (int l = 0; l < a.nl; ++l) {
+        const int w = a.L[l].w;
+        const T* ceg = a.ce[l] + (size_t)s * a.L[l].ss;
+        const T* cng = a.cn[l] + (size_t)s * a.L[l].ss;
+        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+            ce[g.off[l] + t] = ceg[t];
+            cn[g.off[l] + t] = cng[t];
+        }
+    }
+    {
+        const int m = a.L[0].m, w = a.L[0].w;
+        const T* rg = a.rhs + (size_t)s * a.L[0].ss;
+        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+            const int y = t / w, x = t - y * w;
+            rhs[t] = is_unknown(x, y, m, a.bc) ? rg[t] : T(0);
+        }
+    }
+    __syncthreads();
+    lds_mg_diag(g);
+    lds_vcycle(g);
     const int m = a.L[0].m, w = a.L[0].w;
-    double acc = 0.0, acc2 = 0.0;
     for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
         const int y = t / w, x = t - y * w;
-        if (!is_unknown(x, y, m, a.bc)) continue;
-        if (L0) {
-            const size_t o = (size_t)s * a.L[0].ss + t;
-            const double r = reinterpret_cast<const double*>(a.rhs)[o];
-            reinterpret_cast<T*>(a.zout)[o] = z[t];
-            acc += r * (double)z[t];
-            acc2 += a.q[o] * (double)z[t];
-        } else {
-            reinterpret_cast<T*>(a.zout)[(size_t)s * a.L[0].ss + t] = z[t];
-        }
-    }
-    if (L0) {
-        acc = block_sum(acc, red);
-        acc2 = block_sum(acc2, red);
-        if (threadIdx.x == 0) {
-            a.dot[s] = acc;
-            a.dot2[s] = acc2;
-        }
+        if (is_unknown(x, y, m, a.bc)) a.zout[(size_t)s * a.L[0].ss + t] = z[t];
     }
 }
 
@@ -674,6 +670,199 @@ __global__ __launch_bounds__(kBlock) void k_coarsen_c(const T* __restrict__ cef,
     auto N = [&](int x, int y) -> double { return (x <= m && y <= m) ? (double)cn[(size_t)y * w + x] : 0.0; };
     cec[(size_t)s * C.ss + t] = (T)hmean2(E(2 * I, 2 * J), E(2 * I + 1, 2 * J));
     cnc[(size_t)s * C.ss + t] = (T)hmean2(N(2 * I, 2 * J), N(2 * I, 2 * J + 1));
+}
+
+// ------------------------------------------- whole solve of a small mesh
+// Meshes with m <= 32: one workgroup runs one sample's entire PCG solve
+// (same method as the tiled path: flexible CG in double, one V(2,2) cycle
+// in T per iteration, harmonic-mean coarse operators) with every vector in
+// LDS or registers, so a batch of small solves is a single launch with no
+// host round trips.  Thread t owns nodes t, t + NT, ... (at most NPT of
+// them): their x, r and q_old stay in registers; p (which the operator
+// needs at neighbours), the double conductances of the CG operator and the
+// multigrid hierarchy live in LDS.
+template <typename T>
+struct SmallArgs {
+    int nl, bc, maxit;
+    Lvl L[8];
+    double f, h2, rtol2;
+    const T* k;        // nodal k (stride kss)
+    long long kss;
+    double* X;         // nodal solution out (stride L[0].ss)
+    Scal* scal;        // per-sample scalars out (it, status, bb, rr)
+};
+
+constexpr int kSmallMax = 32;   // largest mesh solved by one workgroup
+constexpr int kSmallNpt = 5;    // nodes per thread: 64 x 5 >= 17^2, 256 x 5 >= 33^2
+
+template <typename T>
+size_t small_lds_bytes(int m) {
+    const size_t n0 = (size_t)(m + 1) * (m + 1);
+    return 3 * n0 * sizeof(double) + (5 * (size_t)lds_mg_nodes(m) + n0) * sizeof(T);
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2 * (NT / 64)];
+    const int s = blockIdx.x;
+    const int m = a.L[0].m, w = a.L[0].w, n0 = w * w, bc = a.bc;
+    const int tot = lds_mg_nodes(m);
+    double* P = reinterpret_cast<double*>(smem);
+    double* cE = P + n0;
+    double* cN = cE + n0;
+    LdsMg<T> g;
+    g.z = reinterpret_cast<T*>(cN + n0);
+    g.rhs = g.z + tot;
+    g.ce = g.rhs + tot;
+    g.cn = g.ce + tot;
+    g.id = g.cn + tot;
+    g.tmp = g.id + tot;
+    g.nl = a.nl;
+    g.bc = bc;
+    for (int l = 0; l < a.nl; ++l) g.L[l] = a.L[l];
+    lds_mg_layout(g);
+    // nodal k, then the conductances of every level
+    const T* kg = a.k + (size_t)s * a.kss;
+    for (int t = threadIdx.x; t < n0; t += NT) g.tmp[t] = kg[t];
+    __syncthreads();
+    {
+        auto KT = [&](int gx, int gy) -> T { return g.tmp[gy * w + gx]; };
+        auto KD = [&](int gx, int gy) -> double { return (double)g.tmp[gy * w + gx]; };
+        for (int t = threadIdx.x; t < n0; t += NT) {
+            const int y = t / w, x = t - y * w;
+            g.ce[t] = cond_e<T>(x, y, m, KT);
+            g.cn[t] = cond_n<T>(x, y, m, KT);
+            cE[t] = cond_e<double>(x, y, m, KD);
+            cN[t] = cond_n<double>(x, y, m, KD);
+        }
+        if (a.nl > 1) {
+            const int cw = a.L[1].w, o = g.off[1];
+            for (int t = threadIdx.x; t < cw * cw; t += NT) {
+                const int J = t / cw, I = t - J * cw;
+                g.ce[o + t] = (T)hmean2(cond_e<double>(2 * I, 2 * J, m, KD), cond_e<double>(2 * I + 1, 2 * J, m, KD));
+                g.cn[o + t] = (T)hmean2(cond_n<double>(2 * I, 2 * J, m, KD), cond_n<double>(2 * I, 2 * J + 1, m, KD));
+            }
+        }
+        __syncthreads();
+    }
+    for (int l = 2; l < a.nl; ++l) {
+        const int fm = a.L[l - 1].m, fw = a.L[l - 1].w, fo = g.off[l - 1];
+        const int cw = a.L[l].w, o = g.off[l];
+        auto E = [&](int x, int y) -> double { return (x <= fm && y <= fm) ? (double)g.ce[fo + y * fw + x] : 0.0; };
+        auto N = [&](int x, int y) -> double { return (x <= fm && y <= fm) ? (double)g.cn[fo + y * fw + x] : 0.0; };
+        for (int t = threadIdx.x; t < cw * cw; t += NT) {
+            const int J = t / cw, I = t - J * cw;
+            g.ce[o + t] = (T)hmean2(E(2 * I, 2 * J), E(2 * I + 1, 2 * J));
+            g.cn[o + t] = (T)hmean2(N(2 * I, 2 * J), N(2 * I, 2 * J + 1));
+        }
+        __syncthreads();
+    }
+    lds_mg_diag(g);
+    // x = Dirichlet lifting, r = b - A x at the unknowns
+    double xr[kSmallNpt], rr_[kSmallNpt], qr[kSmallNpt];
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < kSmallNpt; ++i) {
+        const int t = threadIdx.x + i * NT;
+        xr[i] = rr_[i] = qr[i] = 0.0;
+        if (t >= n0) continue;
+        const int y = t / w, x = t - y * w;
+        if (is_unknown(x, y, m, bc)) {
+            double rv = a.f * (double)tri_count(x, y, m) * a.h2 * (1.0 / 6.0);
+            if (!is_unknown(x + 1, y, m, bc) && x + 1 <= m) rv += cE[t] * dirichlet_value(x + 1, bc);
+            if (!is_unknown(x - 1, y, m, bc) && x - 1 >= 0) rv += cE[t - 1] * dirichlet_value(x - 1, bc);
+            if (!is_unknown(x, y + 1, m, bc) && y + 1 <= m) rv += cN[t] * dirichlet_value(x, bc);
+            if (!is_unknown(x, y - 1, m, bc) && y - 1 >= 0) rv += cN[t - w] * dirichlet_value(x, bc);
+            rr_[i] = rv;
+            acc += rv * rv;
+        } else {
+            xr[i] = dirichlet_value(x, bc);
+        }
+        P[t] = 0.0;
+    }
+    const double bb = block_sum(acc, red);
+    int it = 0, status = 0;
+    double rr = bb, pq_old = 0.0;
+    bool active = bb > 0.0;
+    while (active) {
+        // z = V-cycle(r) in T
+#pragma unroll
+        for (int i = 0; i < kSmallNpt; ++i) {
+            const int t = threadIdx.x + i * NT;
+            if (t < n0) g.rhs[t] = (T)rr_[i];   // r is zero off the unknowns
+        }
+        __syncthreads();
+        lds_vcycle(g);
+        double rz = 0.0, zq = 0.0;
+        double zr[kSmallNpt];
+#pragma unroll
+        for (int i = 0; i < kSmallNpt; ++i) {
+            const int t = threadIdx.x + i * NT;
+            zr[i] = t < n0 ? (double)g.z[t] : 0.0;
+            rz += rr_[i] * zr[i];
+            zq += zr[i] * qr[i];
+        }
+        block_sum2(rz, zq, red);
+        // flexible (Polak-Ribiere) beta = -(z_new . q_old) / (p_old . q_old)
+        const double beta = it == 0 ? 0.0 : -zq / pq_old;
+#pragma unroll
+        for (int i = 0; i < kSmallNpt; ++i) {
+            const int t = threadIdx.x + i * NT;
+            if (t >= n0) continue;
+            const int y = t / w, x = t - y * w;
+            if (is_unknown(x, y, m, bc)) P[t] = zr[i] + beta * P[t];
+        }
+        __syncthreads();
+        double pq = 0.0;
+#pragma unroll
+        for (int i = 0; i < kSmallNpt; ++i) {
+            const int t = threadIdx.x + i * NT;
+            qr[i] = 0.0;
+            if (t >= n0) continue;
+            const int y = t / w, x = t - y * w;
+            if (!is_unknown(x, y, m, bc)) continue;
+            const double pc = P[t];
+            double q = cE[t] * (pc - P[t + 1]) + cE[t - 1] * (pc - P[t - 1]);
+            if (y < m) q += cN[t] * (pc - P[t + w]);
+            if (y > 0) q += cN[t - w] * (pc - P[t - w]);
+            qr[i] = q;
+            pq += pc * q;
+        }
+        pq = block_sum(pq, red);
+        const double alpha = rz / pq;
+        double racc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kSmallNpt; ++i) {
+            const int t = threadIdx.x + i * NT;
+            if (t < n0) xr[i] += alpha * P[t];
+            rr_[i] -= alpha * qr[i];
+            racc += rr_[i] * rr_[i];
+        }
+        rr = block_sum(racc, red);
+        pq_old = pq;
+        ++it;
+        if (rr <= a.rtol2 * bb) {
+            active = false;
+        } else if (it >= a.maxit) {
+            active = false;
+            status = -4;
+        }
+    }
+    double* X = a.X + (size_t)s * a.L[0].ss;
+#pragma unroll
+    for (int i = 0; i < kSmallNpt; ++i) {
+        const int t = threadIdx.x + i * NT;
+        if (t < n0) X[t] = xr[i];
+    }
+    if (threadIdx.x == 0) {
+        Scal& sc = a.scal[s];
+        sc.bb = bb;
+        sc.rr = rr;
+        sc.it = it;
+        sc.status = status;
+        sc.active = 0;
+    }
 }
 
 // ----------------------------------------------------------- PCG (double)
@@ -804,14 +993,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
     double acc = 0.0;
     // triangle sums S1 (below the diagonal), S2 (above) of squares (gx-1, y) and (gx, y)
     const double* k0 = K + (NR * wv) * KX + l;   // tile coords (l-1, row-1) -> padded (l, row)
-    double s1m_p, s2m_p, s1a_p, s2a_p;
+    double s1m_p, s2m_p, s2a_p;
     {
         const int gy = y0 + NR * wv - 1;
         const bool sqr = gy >= 0 && gy <= m - 1;
-        const double km = k0[0], ka = k0[1], kb = k0[2], um = k0[KX], ua = k0[KX + 1], ub = k0[KX + 2];
+        const double km = k0[0], ka = k0[1], um = k0[KX], ua = k0[KX + 1], ub = k0[KX + 2];
         s1m_p = (sqr && sqm) ? km + ka + ua : 0.0;
         s2m_p = (sqr && sqm) ? km + ua + um : 0.0;
-        s1a_p = (sqr && sqa) ? ka + kb + ub : 0.0;
         s2a_p = (sqr && sqa) ? ka + ub + ua : 0.0;
     }
     const double sixth = 1.0 / 6.0;
@@ -836,7 +1024,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
             a.Q[o] = q;
             acc += pc * q;
         }
-        s1m_p = s1m; s2m_p = s2m; s1a_p = s1a; s2a_p = s2a;
+        s1m_p = s1m; s2m_p = s2m; s2a_p = s2a;
         cS = cN;
     }
     acc = block_sum(acc, red);
@@ -983,6 +1171,10 @@ __global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ X, Lv
     }
 }
 
+__global__ void k_set_int(int* dst, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+}
+
 // copy of the active-sample counter (launch profiler only)
 __global__ void k_snapshot(const int* cnt, int* dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *cnt;
@@ -1019,6 +1211,10 @@ public:
     static constexpr int PRE_TX = 64 - 12, PRE_TY = RYT - 12;   // halo 6
     static constexpr int POST_TX = 64 - 8, POST_TY = RYT - 8;   // halo 4
     static constexpr int MB = sizeof(T) == 4 ? 32 : 16;
+    static constexpr int RING = 4;   // iterations that may be unconfirmed
+
+    SolverCfg cfg_;
+    int cap_;
 
     SolverImpl(const SolverCfg& cfg, int cap) : cfg_(cfg), cap_(cap) {
         for (int mm = cfg.m; mm >= 2; mm /= 2) {
@@ -1031,9 +1227,25 @@ public:
             lv_.push_back(l);
         }
         nlev_ = (int)lv_.size();
+        small_ = cfg.m <= kSmallMax;
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t o = off;
+            off = align_up(off + bytes, 256);
+            return o;
+        };
+        const Lvl& L0 = lv_[0];
+        const size_t n0 = (size_t)cap * L0.ss;
+        if (small_) {
+            o_X_ = take(n0 * 8);
+            o_scal_ = take((size_t)cap * sizeof(Scal));
+            o_q_ = take((size_t)cap * 8);
+            o_it_ = take((size_t)cap * 4);
+            bytes_ = off;
+            return;
+        }
         lb_ = 0;
         while (lv_[lb_].m > MB) ++lb_;
-        const Lvl& L0 = lv_[0];
         ptx_ = cdiv(L0.m - 1, PTX);
         pty_ = cdiv(L0.yhi - L0.ylo + 1, PTY);
         ptiles_ = ptx_ * pty_;
@@ -1042,16 +1254,8 @@ public:
         itiles_ = itx_ * ity_;
         stx_ = cdiv(L0.m - 1, POST_TX);
         sty_ = cdiv(L0.yhi - L0.ylo + 1, POST_TY);
-        rz_parts_ = lb_ == 0 ? 1 : stx_ * sty_;
+        rz_parts_ = stx_ * sty_;
         max_parts_ = std::max(std::max(ptiles_, itiles_), rz_parts_);
-        // memory plan
-        size_t off = 0;
-        auto take = [&](size_t bytes) {
-            size_t o = off;
-            off = align_up(off + bytes, 256);
-            return o;
-        };
-        const size_t n0 = (size_t)cap * L0.ss;
         o_X_ = take(n0 * 8); o_R_ = take(n0 * 8); o_P0_ = take(n0 * 8); o_P1_ = take(n0 * 8);
         o_Q_ = take(n0 * 8); o_Z_ = take(n0 * sizeof(T));
         o_za0_ = take(n0 * sizeof(T));
@@ -1086,9 +1290,13 @@ public:
             return false;
         }
         e = hipMemset(base_, 0, bytes_);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&hcnt_, 2 * sizeof(int), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&hcnt_, RING * sizeof(int), hipHostMallocDefault);
         for (auto& ev : ev_)
             if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess && small_) {
+            e = sizeof(T) == 8 || cfg_.m > 16 ? allow_lds(k_small_pcg<T, kBlock>, small_lds_bytes<T>(cfg_.m))
+                                              : allow_lds(k_small_pcg<T, 64>, small_lds_bytes<T>(cfg_.m));
+        }
         if (e != hipSuccess) {
             *err = std::string("solver set-up failed: ") + hipGetErrorString(e);
             return false;
@@ -1101,75 +1309,113 @@ public:
     const double* x() const override { return ptr<double>(o_X_); }
     long long xstride() const override { return lv_[0].ss; }
 
-    hipError_t solve(const void* kv, long long kss, int S, hipStream_t st) override {
-        if (S <= 0) return hipSuccess;
-        const T* k0 = reinterpret_cast<const T*>(kv);
+    hipError_t begin(const void* kv, long long kss, int S, hipStream_t st) override {
+        k0_ = reinterpret_cast<const T*>(kv);
+        kss_ = kss;
+        S_ = S;
+        it_next_ = confirmed_ = 0;
+        done_ = S <= 0;
+        recs_.clear();
+        if (done_) return hipSuccess;
+        const double sT = sizeof(T);
+        if (small_) {
+            SmallArgs<T> a{};
+            a.nl = nlev_;
+            a.bc = cfg_.bc;
+            a.maxit = cfg_.maxit;
+            for (int l = 0; l < nlev_; ++l) a.L[l] = lv_[l];
+            a.f = cfg_.f;
+            a.h2 = 1.0 / ((double)cfg_.m * cfg_.m);
+            a.rtol2 = cfg_.rtol * cfg_.rtol;
+            a.k = k0_;
+            a.kss = kss;
+            a.X = ptr<double>(o_X_);
+            a.scal = ptr<Scal>(o_scal_);
+            const size_t lds = small_lds_bytes<T>(cfg_.m);
+            launch("small_pcg", nv(0) * (sT + 8.0), S, -1, st, [&] {
+                if (sizeof(T) == 8 || cfg_.m > 16)
+                    hipLaunchKernelGGL((k_small_pcg<T, kBlock>), dim3(S), dim3(kBlock), lds, st, a);
+                else
+                    hipLaunchKernelGGL((k_small_pcg<T, 64>), dim3(S), dim3(64), lds, st, a);
+            });
+            done_ = true;
+            return hipGetLastError();
+        }
         Scal* scal = ptr<Scal>(o_scal_);
         int* cnt = ptr<int>(o_cnt_);
-        int* hist = ptr<int>(o_hist_);
         double* part = ptr<double>(o_part_);
-        double* part2 = ptr<double>(o_part2_);
-        const bool prof = Profiler::get().on();
-        recs_.clear();
-        const double sT = sizeof(T);
         // coefficient hierarchy
         for (int l = 0; l + 1 < nlev_; ++l) {
             const dim3 g(cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S);
             launch("coarsen", (l == 0 ? nv(0) : 2.0 * nv(l)) * sT + 2.0 * nv(l + 1) * sT, S, -1, st, [&] {
                 if (l == 0)
-                    hipLaunchKernelGGL(k_coarsen_k<T>, g, dim3(kBlock), 0, st, k0, kss, lv_[0], ptr<T>(o_ce_[0]),
+                    hipLaunchKernelGGL(k_coarsen_k<T>, g, dim3(kBlock), 0, st, k0_, kss, lv_[0], ptr<T>(o_ce_[0]),
                                        ptr<T>(o_cn_[0]), lv_[1]);
                 else
                     hipLaunchKernelGGL(k_coarsen_c<T>, g, dim3(kBlock), 0, st, ptr<T>(o_ce_[l - 1]),
                                        ptr<T>(o_cn_[l - 1]), lv_[l], ptr<T>(o_ce_[l]), ptr<T>(o_cn_[l]), lv_[l + 1]);
             });
         }
-        hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
-        if (e != hipSuccess) return e;
-        PcgArgs<T> pa = pcg_args(k0, kss, 0);
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, cnt, 0);
+        PcgArgs<T> pa = pcg_args(0);
         pa.tiles_x = itx_;
         pa.ntiles = itiles_;
         launch("pcg_init", nv(0) * (2.0 * sT + 40.0), S, -1, st, [&] {
             hipLaunchKernelGGL(k_pcg_init<T>, dim3(itiles_ * S), dim3(kBlock), 0, st, pa);
         });
-        const double rtol2 = cfg_.rtol * cfg_.rtol;
-        hipLaunchKernelGGL(k_reduce<RED_BB>, dim3(S), dim3(kBlock), 0, st, part, part, itiles_, scal, rtol2, cfg_.maxit, cnt);
-        if (prof) hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, hist);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        int iters_run = 0;
-        for (int it = 0; it < cfg_.maxit; ++it) {
-            iters_run = it + 1;
-            vcycle(k0, kss, S, it, st);
-            hipLaunchKernelGGL(k_reduce<RED_RZ>, dim3(S), dim3(kBlock), 0, st, part, part2, rz_parts_, scal, rtol2, cfg_.maxit, cnt);
-            PcgArgs<T> a = pcg_args(k0, kss, it);
-            launch("pcg_dir", nu(0) * (24.0 + sT) + nv(0) * sT, S, it, st, [&] {
-                hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
-            });
-            hipLaunchKernelGGL(k_reduce<RED_PQ>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
-            launch("pcg_update", nu(0) * 48.0, S, it, st, [&] {
-                hipLaunchKernelGGL(k_pcg_update<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a);
-            });
-            hipLaunchKernelGGL(k_reduce<RED_RR>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
-            if (prof) hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, hist + it + 1);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            // lagged convergence poll: read the count of iteration it-1
-            // while iteration it is queued.
-            if ((e = hipMemcpyAsync(&hcnt_[it & 1], cnt, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-            if ((e = hipEventRecord(ev_[it & 1], st)) != hipSuccess) return e;
-            if (it >= 1) {
-                if ((e = hipEventSynchronize(ev_[(it - 1) & 1])) != hipSuccess) return e;
-                if (hcnt_[(it - 1) & 1] == 0) break;
-            }
-        }
-        if (prof) {
-            // samples active in iteration it = counter after iteration it-1
-            std::vector<int> h(iters_run + 1);
-            if ((e = hipMemcpyAsync(h.data(), hist, h.size() * sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-            for (auto& r : recs_)
-                if (r.second >= 0) Profiler::get().set_samples(r.first, h[r.second]);
-        }
+        hipLaunchKernelGGL(k_reduce<RED_BB>, dim3(S), dim3(kBlock), 0, st, part, part, itiles_, scal,
+                           cfg_.rtol * cfg_.rtol, cfg_.maxit, cnt);
+        if (Profiler::get().on())
+            hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, ptr<int>(o_hist_));
         return hipGetLastError();
+    }
+
+    hipError_t advance(hipStream_t st, int depth, bool* done, bool* progressed) override {
+        *progressed = false;
+        depth = std::max(1, std::min(depth, RING));
+        // confirm finished iterations in order: the active-sample count
+        // after iteration i lands in hcnt_[i % RING]
+        while (!done_ && confirmed_ < it_next_) {
+            const hipError_t q = hipEventQuery(ev_[confirmed_ % RING]);
+            if (q == hipErrorNotReady) {
+                (void)hipGetLastError();
+                break;
+            }
+            if (q != hipSuccess) return q;
+            const int c = hcnt_[confirmed_ % RING];
+            ++confirmed_;
+            if (c == 0) done_ = true;
+        }
+        if (!done_ && confirmed_ == it_next_ && it_next_ >= cfg_.maxit) done_ = true;
+        if (!done_ && it_next_ < cfg_.maxit && it_next_ - confirmed_ < depth) {
+            hipError_t e = iteration(it_next_, st);
+            if (e != hipSuccess) return e;
+            const int slot = it_next_ % RING;
+            if ((e = hipMemcpyAsync(&hcnt_[slot], ptr<int>(o_cnt_), sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+                return e;
+            if ((e = hipEventRecord(ev_[slot], st)) != hipSuccess) return e;
+            ++it_next_;
+            *progressed = true;
+        }
+        *done = done_;
+        return hipSuccess;
+    }
+
+    hipError_t wait() override {
+        if (done_ || confirmed_ >= it_next_) return hipSuccess;
+        return hipEventSynchronize(ev_[confirmed_ % RING]);
+    }
+
+    hipError_t finish(hipStream_t st) override {
+        if (!Profiler::get().on() || small_ || recs_.empty()) return hipSuccess;
+        // samples active in iteration it = counter after iteration it-1
+        std::vector<int> h(it_next_ + 1);
+        hipError_t e = hipMemcpyAsync(h.data(), ptr<int>(o_hist_), h.size() * sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        for (auto& r : recs_)
+            if (r.second >= 0 && r.second < (int)h.size()) Profiler::get().set_samples(r.first, h[r.second]);
+        return hipSuccess;
     }
 
     hipError_t qoi(const void* kv, long long kss, int S, double* q, int* iters, hipStream_t st) override {
@@ -1202,7 +1448,33 @@ private:
         }
     }
 
-    PcgArgs<T> pcg_args(const T* k0, long long kss, int it) {
+    // one PCG iteration of the tiled path: z = V-cycle(r); r.z and z.q_old;
+    // p, q = A p and p.q; x, r and ||r||^2 with the convergence test
+    hipError_t iteration(int it, hipStream_t st) {
+        const int S = S_;
+        Scal* scal = ptr<Scal>(o_scal_);
+        int* cnt = ptr<int>(o_cnt_);
+        double* part = ptr<double>(o_part_);
+        double* part2 = ptr<double>(o_part2_);
+        const double rtol2 = cfg_.rtol * cfg_.rtol;
+        const double sT = sizeof(T);
+        vcycle(it, st);
+        hipLaunchKernelGGL(k_reduce<RED_RZ>, dim3(S), dim3(kBlock), 0, st, part, part2, rz_parts_, scal, rtol2, cfg_.maxit, cnt);
+        PcgArgs<T> a = pcg_args(it);
+        launch("pcg_dir", nu(0) * (24.0 + sT) + nv(0) * sT, S, it, st, [&] {
+            hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
+        });
+        hipLaunchKernelGGL(k_reduce<RED_PQ>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
+        launch("pcg_update", nu(0) * 48.0, S, it, st, [&] {
+            hipLaunchKernelGGL(k_pcg_update<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a);
+        });
+        hipLaunchKernelGGL(k_reduce<RED_RR>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
+        if (Profiler::get().on())
+            hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, ptr<int>(o_hist_) + it + 1);
+        return hipGetLastError();
+    }
+
+    PcgArgs<T> pcg_args(int it) {
         PcgArgs<T> a{};
         a.L = lv_[0];
         a.bc = cfg_.bc;
@@ -1210,8 +1482,8 @@ private:
         a.ntiles = ptiles_;
         a.f = cfg_.f;
         a.h2 = 1.0 / ((double)cfg_.m * cfg_.m);
-        a.k = k0;
-        a.kss = kss;
+        a.k = k0_;
+        a.kss = kss_;
         a.X = ptr<double>(o_X_);
         a.R = ptr<double>(o_R_);
         a.Pold = ptr<double>((it & 1) ? o_P1_ : o_P0_);
@@ -1223,16 +1495,15 @@ private:
         return a;
     }
 
-
-    MgArgs<T> mg_args(int l, const T* k0, long long kss, int tiles_x, int ntiles) {
+    MgArgs<T> mg_args(int l, int tiles_x, int ntiles) {
         MgArgs<T> a{};
         a.L = lv_[l];
         a.C = lv_[l + 1];
         a.bc = cfg_.bc;
         a.tiles_x = tiles_x;
         a.ntiles = ntiles;
-        a.k = k0;
-        a.kss = kss;
+        a.k = k0_;
+        a.kss = kss_;
         if (l > 0) {
             a.ce = ptr<T>(o_ce_[l - 1]);
             a.cn = ptr<T>(o_cn_[l - 1]);
@@ -1243,12 +1514,13 @@ private:
         return a;
     }
 
-    void vcycle(const T* k0, long long kss, int S, int it, hipStream_t st) {
+    void vcycle(int it, hipStream_t st) {
+        const int S = S_;
         const double sT = sizeof(T);
         for (int l = 0; l < lb_; ++l) {
             const Lvl& L = lv_[l];
             const int tx = cdiv(L.m - 1, PRE_TX), ty = cdiv(L.yhi - L.ylo + 1, PRE_TY);
-            MgArgs<T> a = mg_args(l, k0, kss, tx, tx * ty);
+            MgArgs<T> a = mg_args(l, tx, tx * ty);
             a.rhs_c = ptr<T>(o_rhs_[l]);
             // k, rhs in; z_pre and the coarse rhs out
             const double rb = l == 0 ? 8.0 : sT;
@@ -1266,36 +1538,22 @@ private:
             b.bc = cfg_.bc;
             for (int l = 0; l < b.nl; ++l) {
                 b.L[l] = lv_[lb_ + l];
-                if (lb_ + l > 0) {
-                    b.ce[l] = ptr<T>(o_ce_[lb_ + l - 1]);
-                    b.cn[l] = ptr<T>(o_cn_[lb_ + l - 1]);
-                }
+                b.ce[l] = ptr<T>(o_ce_[lb_ + l - 1]);
+                b.cn[l] = ptr<T>(o_cn_[lb_ + l - 1]);
             }
-            b.k0 = k0;
-            b.kss0 = kss;
+            b.rhs = ptr<T>(o_rhs_[lb_ - 1]);
+            b.zout = ptr<T>(o_zb_[lb_ - 1]);
             b.scal = ptr<Scal>(o_scal_);
-            b.dot = ptr<double>(o_part_);
-            b.dot2 = ptr<double>(o_part2_);
-            b.q = ptr<double>(o_Q_);
             double kb = 0.0;
-            for (int l = lb_; l < nlev_; ++l) kb += (l == 0 ? 1.0 : 2.0) * nv(l) * sT;
-            const double io = lb_ == 0 ? nu(0) * (24.0 + sT) : nu(lb_) * 2.0 * sT;
-            launch("mg_bottom", kb + io, S, it, st, [&] {
-                if (lb_ == 0) {
-                    b.rhs = ptr<double>(o_R_);
-                    b.zout = ptr<T>(o_Z_);
-                    hipLaunchKernelGGL((k_bottom<T, MB, true>), dim3(S), dim3(kBlock), 0, st, b);
-                } else {
-                    b.rhs = ptr<T>(o_rhs_[lb_ - 1]);
-                    b.zout = ptr<T>(o_zb_[lb_ - 1]);
-                    hipLaunchKernelGGL((k_bottom<T, MB, false>), dim3(S), dim3(kBlock), 0, st, b);
-                }
+            for (int l = lb_; l < nlev_; ++l) kb += 2.0 * nv(l) * sT;
+            launch("mg_bottom", kb + nu(lb_) * 2.0 * sT, S, it, st, [&] {
+                hipLaunchKernelGGL((k_bottom<T, MB>), dim3(S), dim3(kBlock), 0, st, b);
             });
         }
         for (int l = lb_ - 1; l >= 0; --l) {
             const Lvl& L = lv_[l];
             const int tx = cdiv(L.m - 1, POST_TX), ty = cdiv(L.yhi - L.ylo + 1, POST_TY);
-            MgArgs<T> a = mg_args(l, k0, kss, tx, tx * ty);
+            MgArgs<T> a = mg_args(l, tx, tx * ty);
             a.zc = ptr<T>(o_zb_[l]);
             a.zout = l == 0 ? ptr<T>(o_Z_) : ptr<T>(o_zb_[l - 1]);
             a.dot = ptr<double>(o_part_);
@@ -1313,10 +1571,9 @@ private:
         }
     }
 
-    SolverCfg cfg_;
-    int cap_;
     std::vector<Lvl> lv_;
     int nlev_ = 0, lb_ = 0;
+    bool small_ = false;
     int ptx_ = 0, pty_ = 0, ptiles_ = 0, itx_ = 0, ity_ = 0, itiles_ = 0, stx_ = 0, sty_ = 0;
     int rz_parts_ = 0, max_parts_ = 0;
     size_t o_X_ = 0, o_R_ = 0, o_P0_ = 0, o_P1_ = 0, o_Q_ = 0, o_Z_ = 0, o_za0_ = 0;
@@ -1326,7 +1583,12 @@ private:
     size_t bytes_ = 0;
     void* base_ = nullptr;
     int* hcnt_ = nullptr;
-    hipEvent_t ev_[2] = {nullptr, nullptr};
+    hipEvent_t ev_[RING] = {nullptr, nullptr, nullptr, nullptr};
+    // state of the solve in progress
+    const T* k0_ = nullptr;
+    long long kss_ = 0;
+    int S_ = 0, it_next_ = 0, confirmed_ = 0;
+    bool done_ = true;
 };
 
 }  // namespace

@@ -60,3 +60,15 @@ def test_argument_errors_without_device(lib):
     assert lib.ces_plan_info_get(None, None) == -1
     assert lib.ces_plan_destroy(None) == 0
     assert lib.ces_context_destroy(None) == 0
+
+
+def test_batch_entry_points_reject_bad_arguments(lib):
+    from paper_2306_13493_amd import _lib
+    assert ctypes.sizeof(_lib.Request) == 72
+    assert ctypes.sizeof(_lib.Schedule) == 16
+    reqs = (_lib.Request * 1)()
+    assert lib.ces_sample_batch(None, reqs, 1, None) == -1
+    assert lib.ces_schedule_get(None, None) == -1
+    assert lib.ces_schedule_set(None, None) == -1
+    assert lib.ces_autotune(None, reqs, 1, None, None, None) == -1
+    assert b"NULL" in lib.ces_last_error()
