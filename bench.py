@@ -25,16 +25,53 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLMC level samples/sec (field+solve) at 1 GPU, p50/p99 latency, % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# library kernel name -> device kernel symbol prefix (for rocprofv3 summaries)
+# library kernel name -> device kernel symbol (mixed path) in rocprofv3 output
 KERNEL_SYMBOL = {
-    "mg_post_l0": "k_smooth<float, 8, true, true>",
-    "mg_pre_l0": "k_smooth<float, 8, false, true>",
-    "mg_restrict_l0": "k_restrict<float, 32, 8, true>",
+    "mg_post_l0": "k_mg<float, 8, true, true>",
+    "mg_pre_l0": "k_mg<float, 8, false, true>",
+    "mg_post": "k_mg<float, 8, true, false>",
+    "mg_pre": "k_mg<float, 8, false, false>",
+    "mg_bottom": "k_bottom<float, 32, 256>",
     "pcg_dir": "k_pcg_dir<float>",
     "pcg_update": "k_pcg_update<float>",
-    "mg_post": "k_smooth<float, 8, true, false>",
-    "mg_pre": "k_smooth<float, 8, false, false>",
+    "pcg_init": "k_pcg_init<float>",
+    "small_pcg": "k_small_pcg<float, 256>",
+    "field_rows": "k_field_rows<float, 16, 0, 1>",
+    "field_cols": "k_field_cols<float, 16, 0, 1, false>",
+    "qoi": "k_qoi<float>",
 }
+# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters,
+# scaled by a plain copy's counters; valid only for the kernel sources it
+# was measured on (their SHA-256 is recorded with the figures).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_mixed_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_13493_amd", "csrc", f)
+                  for f in ("solver.hip", "field.hip", "common.hpp", "fft_lds.hpp", "philox_bm.hpp")]
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(symbol):
+    """Calibrated HBM bytes per launch of `symbol`, or None when no counter
+    figures exist for the current kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest, row = None, None
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("sources-sha256:"):
+            digest = line.split(":", 1)[1].strip()
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0] == symbol:
+            row = cells
+    if digest != sources_digest() or row is None:
+        return None
+    return float(row[4])
 
 
 def log(*a):
@@ -67,6 +104,40 @@ def cpu_baseline(workload, seed, nsamples, nproc):
     return y, dt
 
 
+def c3_batch(ces, ctx, W, log, reps=5):
+    """Five MLMC levels (m = 16 .. 256, N = 20000/5000/1200/300/80) in one
+    ces_sample_batch call, against the same levels one ces_sample call at a
+    time; wall time per estimator round with results on the device."""
+    import numpy as np
+    import torch
+    plans = [ctx.plan(ces.level_desc(**W.c3_level(l))) for l in range(len(W.C3_M))]
+    reqs = [(p, 0, 0, n) for p, n in zip(plans, W.C3_N)]
+    outs = ctx.sample_batch(reqs)
+    seq = [p.sample(0, 0, n) for p, n in zip(plans, W.C3_N)]
+    torch.cuda.synchronize()
+    same = all(bool(torch.equal(a["y"], b["y"])) for a, b in zip(outs, seq))
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts))
+
+    t_batch = timed(lambda: ctx.sample_batch(reqs, outs=outs))
+    t_seq = timed(lambda: [p.sample(0, 0, n, out=o) for p, n, o in zip(plans, W.C3_N, seq)])
+    total = sum(W.C3_N)
+    log("C3 five-level batch: %.2f ms per round (%d level samples), one call per level %.2f ms; identical %s"
+        % (t_batch, total, t_seq, same))
+    return {"ms_per_round": round(t_batch, 3), "level_samples_per_round": total,
+            "level_samples_per_s": round(total / (t_batch * 1e-3), 1),
+            "ms_one_call_per_level": round(t_seq, 3), "batch_equals_per_level_bitwise": same,
+            "schedule": list(ctx.schedule)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +147,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=0)
+    ap.add_argument("--no-c3", action="store_true", help="skip the five-level batched estimator line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (scale for HBM counters)")
     args = ap.parse_args()
@@ -145,9 +217,12 @@ def main():
     name, (launches, ms, nbytes) = max(prof.items(), key=lambda kv: kv[1][1])
     achieved = nbytes / (ms * 1e-3) / 1e9
     total_ms = sum(v[1] for v in prof.values())
-    roofline = {"bound": "hbm", "kernel": name, "symbol": KERNEL_SYMBOL.get(name, name),
+    symbol = KERNEL_SYMBOL.get(name, name)
+    traffic = measured_traffic(symbol)
+    roofline = {"bound": "hbm", "kernel": name, "symbol": symbol,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic) if traffic is not None else None,
                 "avg_launch_us": round(ms * 1e3 / launches, 2), "launches": launches,
                 "algorithmic_bytes_per_launch": round(nbytes / launches),
                 "share_of_kernel_time": round(ms / total_ms, 4)}
@@ -192,6 +267,9 @@ def main():
         extra["fp64_plain_path"] = {"value": round(v64, 1), "unit": "samples/s",
                                     "mixed_vs_fp64_max_rel_diff_Y": diff}
         log("plain FP64 path %.1f samples/s; mixed vs FP64 max rel diff %.2e" % (v64, diff))
+
+    if not args.no_c3:
+        extra["c3_mlmc_batch"] = c3_batch(ces, ctx, W, log)
 
     line = {
         "metric": METRIC,

@@ -67,7 +67,9 @@ int ensure_workspace(ces_plan p, long long max_slots) {
     if (p->ctx->budget && p->ctx->budget - std::min(p->ctx->budget, used) < target)
         target = p->ctx->budget - std::min(p->ctx->budget, used);
     long long slots = (long long)(target / per_slot);
-    slots = std::min<long long>(slots, 8192);
+    // samples per chunk: small meshes solve in one launch per chunk, so
+    // allow more of them; larger meshes fill the device well before 8192
+    slots = std::min<long long>(slots, m <= 32 ? 65536 : 8192);
     if (max_slots > 0) slots = std::min(slots, pair_field ? (max_slots + 1) / 2 * 2 : max_slots);
     if (pair_field) slots &= ~1LL;
     if (slots < (pair_field ? 2 : 1))

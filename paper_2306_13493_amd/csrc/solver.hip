@@ -420,12 +420,17 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
 // LDS: z, rhs, edge conductances and inverse diagonals of every level,
 // stored level after level (level l at off[l], row pitch m_l + 1), plus a
 // scratch array the size of the finest of them.
+// Level l has m0 >> l intervals; its arrays start at off[l] (an LDS table,
+// so that no per-level array sits in private memory).
 template <typename T>
 struct LdsMg {
     T *z, *rhs, *ce, *cn, *id, *tmp;
-    int off[8];
-    Lvl L[8];
-    int nl, bc;
+    int* off;
+    int nl, bc, m0;
+    __device__ int m(int l) const { return m0 >> l; }
+    __device__ int w(int l) const { return (m0 >> l) + 1; }
+    __device__ int ylo(int) const { return bc == BC_FLOWCELL ? 0 : 1; }
+    __device__ int yhi(int l) const { return bc == BC_FLOWCELL ? (m0 >> l) : (m0 >> l) - 1; }
 };
 
 __host__ __device__ constexpr int lds_mg_nodes(int m) {
@@ -434,12 +439,19 @@ __host__ __device__ constexpr int lds_mg_nodes(int m) {
     return t;
 }
 
+// Threads per workgroup of the whole-solve kernel: fixed by m, because the
+// workgroup's dot products sum in an order that depends on it.
+__host__ __device__ constexpr int small_threads(int m) { return m <= 16 ? 256 : 512; }
+
+// fills the offset table (call before the first barrier of the kernel)
 template <typename T>
-__device__ void lds_mg_layout(LdsMg<T>& g) {
-    int o = 0;
-    for (int l = 0; l < g.nl; ++l) {
-        g.off[l] = o;
-        o += g.L[l].w * g.L[l].w;
+__device__ void lds_mg_layout(const LdsMg<T>& g) {
+    if (threadIdx.x == 0) {
+        int o = 0;
+        for (int l = 0; l < g.nl; ++l) {
+            g.off[l] = o;
+            o += g.w(l) * g.w(l);
+        }
     }
 }
 
@@ -469,7 +481,7 @@ __device__ void lds_sweep(T* z, const T* rhs, const T* ce, const T* cn, const T*
 template <typename T>
 __device__ void lds_mg_diag(const LdsMg<T>& g) {
     for (int l = 0; l < g.nl; ++l) {
-        const int m = g.L[l].m, w = g.L[l].w, o = g.off[l];
+        const int m = g.m(l), w = g.w(l), o = g.off[l];
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
             const int y = t / w, x = t - y * w;
             T v = T(0);
@@ -487,14 +499,14 @@ __device__ void lds_mg_diag(const LdsMg<T>& g) {
 // level is overwritten, level 0's holds the result.
 template <typename T>
 __device__ void lds_vcycle(const LdsMg<T>& g) {
-    const int tot = g.off[g.nl - 1] + g.L[g.nl - 1].w * g.L[g.nl - 1].w;
+    const int tot = g.off[g.nl - 1] + g.w(g.nl - 1) * g.w(g.nl - 1);
     for (int t = threadIdx.x; t < tot; t += blockDim.x) g.z[t] = T(0);
     __syncthreads();
     T *z = g.z, *rhs = g.rhs, *tmp = g.tmp;
     const T *ce = g.ce, *cn = g.cn, *id = g.id;
     // down: pre-smooth, residual, restriction (transpose of bilinear)
     for (int l = 0; l + 1 < g.nl; ++l) {
-        const int m = g.L[l].m, w = g.L[l].w, o = g.off[l];
+        const int m = g.m(l), w = g.w(l), o = g.off[l];
         for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, id + o, m, c & 1);
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
             const int y = t / w, x = t - y * w;
@@ -511,7 +523,7 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
             tmp[t] = r;
         }
         __syncthreads();
-        const int cm = g.L[l + 1].m, cwid = g.L[l + 1].w, co = g.off[l + 1];
+        const int cm = g.m(l + 1), cwid = g.w(l + 1), co = g.off[l + 1];
         for (int t = threadIdx.x; t < cwid * cwid; t += blockDim.x) {
             const int J = t / cwid, I = t - J * cwid;
             T v = T(0);
@@ -529,10 +541,12 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
     }
     // coarsest (m = 2): exact tridiagonal solve along the unknown column x = 1
     if (threadIdx.x == 0) {
-        const int l = g.nl - 1, w = g.L[l].w, o = g.off[l];
-        const int ylo = g.L[l].ylo, yhi = g.L[l].yhi;
-        T beta[3], yv[3];
-        for (int j = ylo; j <= yhi; ++j) {
+        const int l = g.nl - 1, w = g.w(l), o = g.off[l];
+        const int ylo = g.ylo(l), yhi = g.yhi(l);
+        T beta[3] = {T(1), T(1), T(1)}, yv[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (j < ylo || j > yhi) continue;
             const int p = o + j * w + 1;
             const T d = T(1) / id[p];
             if (j == ylo) {
@@ -545,7 +559,9 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
             }
         }
         T zn = T(0);
-        for (int j = yhi; j >= ylo; --j) {
+#pragma unroll
+        for (int j = 2; j >= 0; --j) {
+            if (j < ylo || j > yhi) continue;
             const int p = o + j * w + 1;
             const T cN = (j < yhi) ? cn[p] : T(0);
             const T v = (yv[j] + cN * zn) / beta[j];
@@ -556,8 +572,8 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
     __syncthreads();
     // up: bilinear prolongation of the correction, post-smooth
     for (int l = g.nl - 2; l >= 0; --l) {
-        const int m = g.L[l].m, w = g.L[l].w, o = g.off[l];
-        const int cm = g.L[l + 1].m, cwid = g.L[l + 1].w, co = g.off[l + 1];
+        const int m = g.m(l), w = g.w(l), o = g.off[l];
+        const int cm = g.m(l + 1), cwid = g.w(l + 1), co = g.off[l + 1];
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
             const int y = t / w, x = t - y * w;
             if (!is_unknown(x, y, m, g.bc)) continue;
@@ -583,40 +599,44 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
 template <typename T>
 struct BottomArgs {
     int nl;            // levels handled here: m0, m0/2, ..., 2
-    int bc;
-    Lvl L[8];
-    const T* ce[8];    // stored edge conductances (stride L[l].ss)
+    int bc, m0;
+    long long ss[8];   // per-sample stride of each level's arrays
+    const T* ce[8];    // stored edge conductances
     const T* cn[8];
     const T* rhs;      // rhs of the first bottom level
     T* zout;           // its z
     const Scal* scal;
 };
 
-template <typename T, int MB>
-__global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
+// NT threads per workgroup; the result does not depend on NT.
+template <typename T, int MB, int NT>
+__global__ __launch_bounds__(NT) void k_bottom(BottomArgs<T> a) {
     constexpr int TOT = lds_mg_nodes(MB);
     __shared__ T z[TOT], rhs[TOT], ce[TOT], cn[TOT], id[TOT];
     __shared__ T tmp[(MB + 1) * (MB + 1)];
+    __shared__ int off[8];
     const int s = blockIdx.x;
     if (!a.scal[s].active) return;
     LdsMg<T> g;
     g.z = z; g.rhs = rhs; g.ce = ce; g.cn = cn; g.id = id; g.tmp = tmp;
+    g.off = off;
     g.nl = a.nl;
     g.bc = a.bc;
-    for (int l = 0; l < a.nl; ++l) g.L[l] = a.L[l];
+    g.m0 = a.m0;
     lds_mg_layout(g);
+    __syncthreads();
     for (int l = 0; l < a.nl; ++l) {
-        const int w = a.L[l].w;
-        const T* ceg = a.ce[l] + (size_t)s * a.L[l].ss;
-        const T* cng = a.cn[l] + (size_t)s * a.L[l].ss;
+        const int w = g.w(l), o = off[l];
+        const T* ceg = a.ce[l] + (size_t)s * a.ss[l];
+        const T* cng = a.cn[l] + (size_t)s * a.ss[l];
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-            ce[g.off[l] + t] = ceg[t];
-            cn[g.off[l] + t] = cng[t];
+            ce[o + t] = ceg[t];
+            cn[o + t] = cng[t];
         }
     }
     {
-        const int m = a.L[0].m, w = a.L[0].w;
-        const T* rg = a.rhs + (size_t)s * a.L[0].ss;
+        const int m = g.m(0), w = g.w(0);
+        const T* rg = a.rhs + (size_t)s * a.ss[0];
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
             const int y = t / w, x = t - y * w;
             rhs[t] = is_unknown(x, y, m, a.bc) ? rg[t] : T(0);
@@ -625,10 +645,10 @@ __global__ __launch_bounds__(kBlock) void k_bottom(BottomArgs<T> a) {
     __syncthreads();
     lds_mg_diag(g);
     lds_vcycle(g);
-    const int m = a.L[0].m, w = a.L[0].w;
+    const int m = g.m(0), w = g.w(0);
     for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
         const int y = t / w, x = t - y * w;
-        if (is_unknown(x, y, m, a.bc)) a.zout[(size_t)s * a.L[0].ss + t] = z[t];
+        if (is_unknown(x, y, m, a.bc)) a.zout[(size_t)s * a.ss[0] + t] = z[t];
     }
 }
 
@@ -683,8 +703,8 @@ __global__ __launch_bounds__(kBlock) void k_coarsen_c(const T* __restrict__ cef,
 // multigrid hierarchy live in LDS.
 template <typename T>
 struct SmallArgs {
-    int nl, bc, maxit;
-    Lvl L[8];
+    int nl, bc, maxit, m;
+    long long xss;     // per-sample stride of X
     double f, h2, rtol2;
     const T* k;        // nodal k (stride kss)
     long long kss;
@@ -693,7 +713,7 @@ struct SmallArgs {
 };
 
 constexpr int kSmallMax = 32;   // largest mesh solved by one workgroup
-constexpr int kSmallNpt = 5;    // nodes per thread: 64 x 5 >= 17^2, 256 x 5 >= 33^2
+constexpr int kSmallNpt = 3;    // nodes per thread (256 x 3 >= 17^2, 512 x 3 >= 33^2)
 
 template <typename T>
 size_t small_lds_bytes(int m) {
@@ -703,10 +723,12 @@ size_t small_lds_bytes(int m) {
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
+    static_assert(NT * kSmallNpt >= 17 * 17 && (NT < 512 || NT * kSmallNpt >= 33 * 33), "nodes per thread");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[2 * (NT / 64)];
+    __shared__ int off[8];
     const int s = blockIdx.x;
-    const int m = a.L[0].m, w = a.L[0].w, n0 = w * w, bc = a.bc;
+    const int m = a.m, w = m + 1, n0 = w * w, bc = a.bc;
     const int tot = lds_mg_nodes(m);
     double* P = reinterpret_cast<double*>(smem);
     double* cE = P + n0;
@@ -718,9 +740,10 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
     g.cn = g.ce + tot;
     g.id = g.cn + tot;
     g.tmp = g.id + tot;
+    g.off = off;
     g.nl = a.nl;
     g.bc = bc;
-    for (int l = 0; l < a.nl; ++l) g.L[l] = a.L[l];
+    g.m0 = m;
     lds_mg_layout(g);
     // nodal k, then the conductances of every level
     const T* kg = a.k + (size_t)s * a.kss;
@@ -737,7 +760,7 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
             cN[t] = cond_n<double>(x, y, m, KD);
         }
         if (a.nl > 1) {
-            const int cw = a.L[1].w, o = g.off[1];
+            const int cw = g.w(1), o = g.off[1];
             for (int t = threadIdx.x; t < cw * cw; t += NT) {
                 const int J = t / cw, I = t - J * cw;
                 g.ce[o + t] = (T)hmean2(cond_e<double>(2 * I, 2 * J, m, KD), cond_e<double>(2 * I + 1, 2 * J, m, KD));
@@ -747,8 +770,8 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
         __syncthreads();
     }
     for (int l = 2; l < a.nl; ++l) {
-        const int fm = a.L[l - 1].m, fw = a.L[l - 1].w, fo = g.off[l - 1];
-        const int cw = a.L[l].w, o = g.off[l];
+        const int fm = g.m(l - 1), fw = g.w(l - 1), fo = g.off[l - 1];
+        const int cw = g.w(l), o = g.off[l];
         auto E = [&](int x, int y) -> double { return (x <= fm && y <= fm) ? (double)g.ce[fo + y * fw + x] : 0.0; };
         auto N = [&](int x, int y) -> double { return (x <= fm && y <= fm) ? (double)g.cn[fo + y * fw + x] : 0.0; };
         for (int t = threadIdx.x; t < cw * cw; t += NT) {
@@ -849,7 +872,7 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
             status = -4;
         }
     }
-    double* X = a.X + (size_t)s * a.L[0].ss;
+    double* X = a.X + (size_t)s * a.xss;
 #pragma unroll
     for (int i = 0; i < kSmallNpt; ++i) {
         const int t = threadIdx.x + i * NT;
@@ -1294,8 +1317,8 @@ public:
         for (auto& ev : ev_)
             if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess && small_) {
-            e = sizeof(T) == 8 || cfg_.m > 16 ? allow_lds(k_small_pcg<T, kBlock>, small_lds_bytes<T>(cfg_.m))
-                                              : allow_lds(k_small_pcg<T, 64>, small_lds_bytes<T>(cfg_.m));
+            e = cfg_.m > 16 ? allow_lds(k_small_pcg<T, small_threads(32)>, small_lds_bytes<T>(cfg_.m))
+                            : allow_lds(k_small_pcg<T, small_threads(16)>, small_lds_bytes<T>(cfg_.m));
         }
         if (e != hipSuccess) {
             *err = std::string("solver set-up failed: ") + hipGetErrorString(e);
@@ -1323,7 +1346,8 @@ public:
             a.nl = nlev_;
             a.bc = cfg_.bc;
             a.maxit = cfg_.maxit;
-            for (int l = 0; l < nlev_; ++l) a.L[l] = lv_[l];
+            a.m = cfg_.m;
+            a.xss = lv_[0].ss;
             a.f = cfg_.f;
             a.h2 = 1.0 / ((double)cfg_.m * cfg_.m);
             a.rtol2 = cfg_.rtol * cfg_.rtol;
@@ -1333,10 +1357,10 @@ public:
             a.scal = ptr<Scal>(o_scal_);
             const size_t lds = small_lds_bytes<T>(cfg_.m);
             launch("small_pcg", nv(0) * (sT + 8.0), S, -1, st, [&] {
-                if (sizeof(T) == 8 || cfg_.m > 16)
-                    hipLaunchKernelGGL((k_small_pcg<T, kBlock>), dim3(S), dim3(kBlock), lds, st, a);
+                if (cfg_.m > 16)
+                    hipLaunchKernelGGL((k_small_pcg<T, small_threads(32)>), dim3(S), dim3(small_threads(32)), lds, st, a);
                 else
-                    hipLaunchKernelGGL((k_small_pcg<T, 64>), dim3(S), dim3(64), lds, st, a);
+                    hipLaunchKernelGGL((k_small_pcg<T, small_threads(16)>), dim3(S), dim3(small_threads(16)), lds, st, a);
             });
             done_ = true;
             return hipGetLastError();
@@ -1536,8 +1560,9 @@ private:
             BottomArgs<T> b{};
             b.nl = nlev_ - lb_;
             b.bc = cfg_.bc;
+            b.m0 = lv_[lb_].m;
             for (int l = 0; l < b.nl; ++l) {
-                b.L[l] = lv_[lb_ + l];
+                b.ss[l] = lv_[lb_ + l].ss;
                 b.ce[l] = ptr<T>(o_ce_[lb_ + l - 1]);
                 b.cn[l] = ptr<T>(o_cn_[lb_ + l - 1]);
             }
@@ -1547,7 +1572,12 @@ private:
             double kb = 0.0;
             for (int l = lb_; l < nlev_; ++l) kb += 2.0 * nv(l) * sT;
             launch("mg_bottom", kb + nu(lb_) * 2.0 * sT, S, it, st, [&] {
-                hipLaunchKernelGGL((k_bottom<T, MB>), dim3(S), dim3(kBlock), 0, st, b);
+                // few samples: more threads per sample shorten each phase;
+                // many: more workgroups per CU hide the latency instead
+                if (S >= 512)
+                    hipLaunchKernelGGL((k_bottom<T, MB, 256>), dim3(S), dim3(256), 0, st, b);
+                else
+                    hipLaunchKernelGGL((k_bottom<T, MB, 1024>), dim3(S), dim3(1024), 0, st, b);
             });
         }
         for (int l = lb_ - 1; l >= 0; --l) {
