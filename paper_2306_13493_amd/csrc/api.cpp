@@ -32,73 +32,6 @@ namespace {
 
 constexpr double kPsdTol = 1e-13;
 
-// ------------------------------------------------------------ covariance
-struct Cov {
-    int kind;
-    double nu, lam, sigma2;
-    // Matern, eq. (matern-cov-function); separable exponential,
-    // eq. (p-norm-cov-function) with p = 1.
-    double operator()(double t1, double t2) const {
-        if (kind == CES_COV_SEPEXP) return sigma2 * std::exp(-(std::fabs(t1) + std::fabs(t2)) / lam);
-        const double r = std::sqrt(t1 * t1 + t2 * t2);
-        const double x = std::sqrt(2.0 * nu) * r / lam;
-        if (x == 0.0) return sigma2;
-        if (nu == 0.5) return sigma2 * std::exp(-x);
-        if (nu == 1.5) return sigma2 * (1.0 + x) * std::exp(-x);
-        if (nu == 2.5) return sigma2 * (1.0 + x + x * x / 3.0) * std::exp(-x);
-        if (x > 700.0) return 0.0;
-        return sigma2 * std::pow(2.0, 1.0 - nu) / std::tgamma(nu) * std::pow(x, nu) * std::cyl_bessel_k(nu, x);
-    }
-};
-
-double eta(double x) { return x > 0.0 ? std::exp(-1.0 / x) : 0.0; }
-
-// First column of the embedding (Section 2.1.2 mirroring for J = 0; the
-// 2 ell-periodic extension of eq. (periodic-cov-fun) for J > 0), n x n,
-// index [j2][j1].  Computed on the quadrant j <= n/2 and mirrored (the
-// column is even in each index).
-std::vector<double> first_column(const Cov& C, int m, int J, int reading) {
-    const int n = 2 * (m + J);
-    const double h = 1.0 / m;
-    const int nh = n / 2;
-    std::vector<double> q((size_t)(nh + 1) * (nh + 1));
-    if (J == 0) {
-        for (int b = 0; b <= nh; ++b)
-            for (int a = 0; a <= nh; ++a) q[(size_t)b * (nh + 1) + a] = C(a * h, b * h);
-    } else {
-        const double ell = 1.0 + (double)J / m;
-        const double lo = reading == CES_PERIOD_INF ? 1.0 : std::sqrt(2.0);
-        const double kappa = reading == CES_PERIOD_INF ? 2.0 * ell - 1.0 : 2.0 * ell - std::sqrt(2.0);
-        const double wdt = kappa - lo;
-        auto phi = [&](double t) {
-            const double a = eta((kappa - t) / wdt), b = eta((t - lo) / wdt);
-            return a / (a + b);
-        };
-        for (int b = 0; b <= nh; ++b)
-            for (int a = 0; a <= nh; ++a) {
-                double acc = 0.0;
-                for (int s2 = 0; s2 >= -1; --s2)
-                    for (int s1 = 0; s1 >= -1; --s1) {
-                        const double y1 = a * h + 2.0 * ell * s1, y2 = b * h + 2.0 * ell * s2;
-                        const double t = reading == CES_PERIOD_INF ? std::max(std::fabs(y1), std::fabs(y2))
-                                                                   : std::sqrt(y1 * y1 + y2 * y2);
-                        if (t >= kappa) continue;
-                        acc += C(y1, y2) * phi(t);
-                    }
-                q[(size_t)b * (nh + 1) + a] = acc;
-            }
-    }
-    std::vector<double> s((size_t)n * n);
-    for (int j2 = 0; j2 < n; ++j2) {
-        const int b = std::min(j2, n - j2);
-        for (int j1 = 0; j1 < n; ++j1) {
-            const int a = std::min(j1, n - j1);
-            s[(size_t)j2 * n + j1] = q[(size_t)b * (nh + 1) + a];
-        }
-    }
-    return s;
-}
-
 template <typename T>
 std::vector<cplx<T>> twiddles(int n) {
     std::vector<cplx<T>> tw(n);
@@ -110,73 +43,7 @@ std::vector<cplx<T>> twiddles(int n) {
     return tw;
 }
 
-}  // namespace
-
-namespace {
-
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-
-int validate(const ces_level_desc* d) {
-    if (!d) return fail(CES_ERR_ARG, "desc is NULL");
-    if (d->struct_size != (int32_t)sizeof(ces_level_desc)) return fail(CES_ERR_ARG, "desc.struct_size mismatch");
-    if (d->cov_kind != CES_COV_MATERN && d->cov_kind != CES_COV_SEPEXP) return fail(CES_ERR_ARG, "cov_kind");
-    if (d->cov_kind == CES_COV_MATERN && !(d->nu > 0.0)) return fail(CES_ERR_ARG, "nu must be > 0");
-    if (!(d->lambda > 0.0) || !(d->sigma2 > 0.0)) return fail(CES_ERR_ARG, "lambda and sigma2 must be > 0");
-    if (!is_pow2(d->m_fine) || d->m_fine < 4 || d->m_fine > 4096)
-        return fail(CES_ERR_ARG, "m_fine must be a power of two in [4, 4096]");
-    if (d->level_kind != CES_LEVEL_SINGLE && d->level_kind != CES_LEVEL_PAIR) return fail(CES_ERR_ARG, "level_kind");
-    if (d->level_kind == CES_LEVEL_PAIR && d->m_fine < 8) return fail(CES_ERR_ARG, "PAIR levels need m_fine >= 8");
-    if (d->psd_policy < 0 || d->psd_policy > 2) return fail(CES_ERR_ARG, "psd_policy");
-    if (d->periodization != CES_PERIOD_EUCLID && d->periodization != CES_PERIOD_INF) return fail(CES_ERR_ARG, "periodization");
-    if (d->max_pad_factor < 2 || d->max_pad_factor > 4) return fail(CES_ERR_ARG, "max_pad_factor must be in [2, 4]");
-    if (d->field_mode != CES_FIELD_PAIR && d->field_mode != CES_FIELD_HARTLEY) return fail(CES_ERR_ARG, "field_mode");
-    if (d->precision != CES_PREC_FP64 && d->precision != CES_PREC_MIXED) return fail(CES_ERR_ARG, "precision");
-    if (d->bc != CES_BC_DIRICHLET0 && d->bc != CES_BC_FLOWCELL) return fail(CES_ERR_ARG, "bc");
-    if (d->qoi < CES_QOI_INTEGRAL || d->qoi > CES_QOI_OUTFLUX) return fail(CES_ERR_ARG, "qoi");
-    if (d->qoi == CES_QOI_POINT && !(d->qoi_x >= 0 && d->qoi_x <= 1 && d->qoi_y >= 0 && d->qoi_y <= 1))
-        return fail(CES_ERR_ARG, "qoi point outside the unit square");
-    if (!(d->cg_rtol > 0.0) || d->cg_max_iter < 1) return fail(CES_ERR_ARG, "cg_rtol / cg_max_iter");
-    if (d->tau_fine < -1 || d->tau_coarse < -1) return fail(CES_ERR_ARG, "tau must be >= -1");
-    return CES_OK;
-}
-
-// Orbit symmetrisation: each index takes the value at its representative
-// (min(k1, n-k1), min(k2, n-k2)) with the pair sorted.
-void symmetrise(std::vector<double>& lam, int n) {
-    std::vector<double> out((size_t)n * n);
-    for (int k2 = 0; k2 < n; ++k2)
-        for (int k1 = 0; k1 < n; ++k1) {
-            const int a = std::min(k1, n - k1), b = std::min(k2, n - k2);
-            const int lo = std::min(a, b), hi = std::max(a, b);
-            out[(size_t)k2 * n + k1] = lam[(size_t)hi * n + lo];
-        }
-    lam.swap(out);
-}
-
-// Device FP64 DFT of the first column -> eigenvalues on the host.
-int eigenvalues(const std::vector<double>& s, int n, std::vector<double>& lam, double* imag_max) {
-    FftPlan fp = make_fft_plan(n);
-    if (fp.nst < 0) return fail(CES_ERR_ARG, "embedding size not of the form 2^a 3^b");
-    auto tw = twiddles<double>(n);
-    DevBuf ds, dw, dl, dtw, di;
-    CES_HIP(ds.alloc(s.size() * 8), "eigen buffers");
-    CES_HIP(dw.alloc(s.size() * 16), "eigen buffers");
-    CES_HIP(dl.alloc(s.size() * 8), "eigen buffers");
-    CES_HIP(dtw.alloc(tw.size() * sizeof(tw[0])), "eigen buffers");
-    CES_HIP(di.alloc((size_t)n * 8), "eigen buffers");
-    CES_HIP(hipMemcpy(ds.p, s.data(), s.size() * 8, hipMemcpyHostToDevice), "upload column");
-    CES_HIP(hipMemcpy(dtw.p, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice), "upload twiddles");
-    int nblk = 0;
-    CES_HIP(launch_eigen_fft(ds.as<double>(), n, fp, dtw.as<cplx<double>>(), dw.as<cplx<double>>(), dl.as<double>(),
-                             di.as<double>(), &nblk, nullptr),
-            "eigen DFT launch");
-    lam.resize(s.size());
-    std::vector<double> im(nblk);
-    CES_HIP(hipMemcpy(lam.data(), dl.p, s.size() * 8, hipMemcpyDeviceToHost), "download eigenvalues");
-    CES_HIP(hipMemcpy(im.data(), di.p, (size_t)nblk * 8, hipMemcpyDeviceToHost), "download eigenvalues");
-    *imag_max = im.empty() ? 0.0 : *std::max_element(im.begin(), im.end());
-    return CES_OK;
-}
 
 // Algorithm 2 step 4(b): the tau smallest in the order (Lambda descending,
 // index ascending) are dropped.  drop_order receives the first `tmax`
@@ -199,29 +66,195 @@ void smallest_order(const std::vector<double>& lam, int64_t tmax, std::vector<in
     if (tmax < s) drop_order.push_back(*std::min_element(idx.begin() + tmax, idx.end(), less));  // first kept
 }
 
-template <typename T>
-int upload_amplitudes(ces_plan p) {
-    const int n = p->n;
-    const size_t s = (size_t)n * n;
-    std::vector<T> a(s), c(s);
-    for (size_t i = 0; i < s; ++i) {
-        const double base = std::sqrt(std::max(p->lam[i], 0.0)) / n;
-        a[i] = (T)(p->keep_f[i] ? base : 0.0);
-        c[i] = (T)(p->keep_c[i] ? base : 0.0);
-    }
-    CES_HIP(p->af.alloc(s * sizeof(T)), "amplitude buffers");
-    CES_HIP(hipMemcpy(p->af.p, a.data(), s * sizeof(T), hipMemcpyHostToDevice), "upload amplitudes");
-    if (p->nf == 2) {
-        CES_HIP(p->ac.alloc(s * sizeof(T)), "amplitude buffers");
-        CES_HIP(hipMemcpy(p->ac.p, c.data(), s * sizeof(T), hipMemcpyHostToDevice), "upload amplitudes");
-    }
-    auto tw = twiddles<T>(n);
-    CES_HIP(p->tw.alloc(tw.size() * sizeof(tw[0])), "twiddle buffer");
-    CES_HIP(hipMemcpy(p->tw.p, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice), "upload twiddles");
+// Scratch of one embedding-size candidate: column, DFT work, raw and
+// symmetrised eigenvalues, per-block reductions.
+struct SetupBufs {
+    DevBuf s, work, raw, tw, blk;
+};
+
+// Algorithm 1 steps 2-3(a) at embedding size n = 2(m + J) on the device:
+// column, FP64 2-D DFT, orbit symmetrisation into `lam`; host receives the
+// extremes, the count of negatives and the largest imaginary part.
+int eigen_candidate(const ces_level_desc* d, const CovParams& cp, int J, DeviceAllocator* A, hipStream_t st,
+                    SetupBufs& B, DevBuf& lam, double* lmin, double* lmax, int64_t* nneg, double* imag) {
+    const int m = d->m_fine, n = 2 * (m + J);
+    const size_t nn = (size_t)n * n;
+    const FftPlan fp = make_fft_plan(n);
+    const int nsym = symmetrise_blocks(n);
+    const size_t blk_bytes = (size_t)(n + 2 * nsym) * 8 + (size_t)nsym * 4;
+    CES_HIP(B.s.alloc(nn * 8, A), "set-up buffers");
+    CES_HIP(B.work.alloc(nn * 16, A), "set-up buffers");
+    CES_HIP(B.raw.alloc(nn * 8, A), "set-up buffers");
+    CES_HIP(B.tw.alloc((size_t)n * sizeof(cplx<double>), A), "set-up buffers");
+    CES_HIP(B.blk.alloc(blk_bytes, A), "set-up buffers");
+    CES_HIP(lam.alloc(nn * 8, A), "eigenvalue buffer");
+    const auto tw = twiddles<double>(n);
+    CES_HIP(hipMemcpyAsync(B.tw.p, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice, st), "twiddles");
+    double* imag_blk = B.blk.as<double>();
+    double* bmin = imag_blk + n;
+    double* bmax = bmin + nsym;
+    int* bneg = reinterpret_cast<int*>(bmax + nsym);
+    CES_HIP(launch_cov_column(B.s.as<double>(), n, m, J, d->periodization, cp, st), "covariance column");
+    int nblk = 0, nb2 = 0;
+    CES_HIP(launch_eigen_fft(B.s.as<double>(), n, fp, B.tw.as<cplx<double>>(), B.work.as<cplx<double>>(),
+                             B.raw.as<double>(), imag_blk, &nblk, st),
+            "eigenvalue DFT");
+    CES_HIP(launch_symmetrise(B.raw.as<double>(), lam.as<double>(), n, bmin, bmax, bneg, &nb2, st), "symmetrise");
+    std::vector<unsigned char> h(blk_bytes);
+    CES_HIP(hipMemcpyAsync(h.data(), B.blk.p, blk_bytes, hipMemcpyDeviceToHost, st), "eigenvalue extremes");
+    CES_HIP(hipStreamSynchronize(st), "plan set-up");
+    const double* hi = reinterpret_cast<const double*>(h.data());
+    const double* hmin = hi + n;
+    const double* hmax = hmin + nsym;
+    const int* hneg = reinterpret_cast<const int*>(hmax + nsym);
+    *imag = *std::max_element(hi, hi + nblk);
+    *lmin = *std::min_element(hmin, hmin + nb2);
+    *lmax = *std::max_element(hmax, hmax + nb2);
+    int64_t c = 0;
+    for (int i = 0; i < nb2; ++i) c += hneg[i];
+    *nneg = c;
     return CES_OK;
 }
 
 }  // namespace
+
+namespace ces {
+
+int validate_desc(const ces_level_desc* d) {
+    if (!d) return fail(CES_ERR_ARG, "desc is NULL");
+    if (d->struct_size != (int32_t)sizeof(ces_level_desc)) return fail(CES_ERR_ARG, "desc.struct_size mismatch");
+    if (d->cov_kind != CES_COV_MATERN && d->cov_kind != CES_COV_SEPEXP) return fail(CES_ERR_ARG, "cov_kind");
+    if (d->cov_kind == CES_COV_MATERN && !(d->nu > 0.0 && d->nu <= 5.0))
+        return fail(CES_ERR_ARG, "nu must be in (0, 5]");
+    if (!(d->lambda > 0.0) || !(d->sigma2 > 0.0)) return fail(CES_ERR_ARG, "lambda and sigma2 must be > 0");
+    if (!is_pow2(d->m_fine) || d->m_fine < 4 || d->m_fine > 4096)
+        return fail(CES_ERR_ARG, "m_fine must be a power of two in [4, 4096]");
+    if (d->level_kind != CES_LEVEL_SINGLE && d->level_kind != CES_LEVEL_PAIR) return fail(CES_ERR_ARG, "level_kind");
+    if (d->level_kind == CES_LEVEL_PAIR && d->m_fine < 8) return fail(CES_ERR_ARG, "PAIR levels need m_fine >= 8");
+    if (d->psd_policy < 0 || d->psd_policy > 2) return fail(CES_ERR_ARG, "psd_policy");
+    if (d->periodization != CES_PERIOD_EUCLID && d->periodization != CES_PERIOD_INF) return fail(CES_ERR_ARG, "periodization");
+    if (d->max_pad_factor < 2 || d->max_pad_factor > 4) return fail(CES_ERR_ARG, "max_pad_factor must be in [2, 4]");
+    if (d->field_mode != CES_FIELD_PAIR && d->field_mode != CES_FIELD_HARTLEY) return fail(CES_ERR_ARG, "field_mode");
+    if (d->precision != CES_PREC_FP64 && d->precision != CES_PREC_MIXED) return fail(CES_ERR_ARG, "precision");
+    if (d->bc != CES_BC_DIRICHLET0 && d->bc != CES_BC_FLOWCELL) return fail(CES_ERR_ARG, "bc");
+    if (d->qoi < CES_QOI_INTEGRAL || d->qoi > CES_QOI_OUTFLUX) return fail(CES_ERR_ARG, "qoi");
+    if (d->qoi == CES_QOI_POINT && !(d->qoi_x >= 0 && d->qoi_x <= 1 && d->qoi_y >= 0 && d->qoi_y <= 1))
+        return fail(CES_ERR_ARG, "qoi point outside the unit square");
+    if (!(d->cg_rtol > 0.0) || d->cg_max_iter < 1) return fail(CES_ERR_ARG, "cg_rtol / cg_max_iter");
+    if (d->tau_fine < -1 || d->tau_coarse < -1) return fail(CES_ERR_ARG, "tau must be >= -1");
+    return CES_OK;
+}
+
+int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* A, hipStream_t st, ces_plan* out) {
+    *out = nullptr;
+    int rc = validate_desc(desc);
+    if (rc != CES_OK) return rc;
+    std::unique_ptr<ces_plan_s> p(new ces_plan_s);
+    p->ctx = ctx;
+    p->d = *desc;
+    p->alloc = A;
+    const int m = desc->m_fine;
+    CovParams cp;
+    cp.kind = desc->cov_kind == CES_COV_SEPEXP ? COV_SEPEXP : COV_MATERN;
+    cp.nu = desc->nu;
+    cp.lam = desc->lambda;
+    cp.sigma2 = desc->sigma2;
+    cp.pref = desc->sigma2 * std::pow(2.0, 1.0 - desc->nu) / std::tgamma(desc->nu);
+    std::vector<int> cands;
+    if (desc->psd_policy == CES_PSD_GROW) {
+        for (int J : {0, m / 2, m})
+            if (2 * (m + J) <= desc->max_pad_factor * m) cands.push_back(J);
+    } else {
+        cands.push_back(0);
+    }
+    bool ok = false;
+    int64_t nneg = 0;
+    {
+        SetupBufs B;
+        for (int J : cands) {
+            // the Euclidean cutoff needs a plateau radius sqrt(2) < kappa
+            if (J > 0 && desc->periodization == CES_PERIOD_EUCLID && !(1.0 + (double)J / m > std::sqrt(2.0))) continue;
+            const int n = 2 * (m + J);
+            if (make_fft_plan(n).nst < 0) continue;
+            double lmin = 0, lmax = 0, imag = 0;
+            rc = eigen_candidate(desc, cp, J, A, st, B, p->lam, &lmin, &lmax, &nneg, &imag);
+            if (rc != CES_OK) return rc;
+            p->n = n;
+            p->J = J;
+            p->lam_min = lmin;
+            p->lam_max = lmax;
+            p->imag_max = imag;
+            ok = lmin >= -kPsdTol * lmax;
+            if (ok || desc->psd_policy == CES_PSD_CLAMP) break;
+        }
+    }
+    if (p->n == 0) return fail(CES_ERR_ARG, "no admissible embedding size");
+    if (!ok && desc->psd_policy != CES_PSD_CLAMP)
+        return fail(CES_ERR_NOT_PSD, "embedding has negative eigenvalues up to the padding cap (min/max = " +
+                                         std::to_string(p->lam_min / p->lam_max) + ")");
+    // after acceptance every negative (noise, or CLAMP) becomes zero
+    p->n_clamped = nneg;
+    const int n = p->n;
+    const int64_t s = (int64_t)n * n;
+    p->tau_f = desc->tau_fine < 0 ? n : desc->tau_fine;
+    p->tau_c = desc->tau_coarse < 0 ? n : desc->tau_coarse;
+    if (desc->level_kind == CES_LEVEL_SINGLE) p->tau_c = p->tau_f;
+    if (p->tau_f > s || p->tau_c > s) return fail(CES_ERR_ARG, "tau exceeds the number of eigenvalues");
+    p->is_double = desc->precision == CES_PREC_FP64;
+    p->nf = (desc->level_kind == CES_LEVEL_PAIR && p->tau_f != p->tau_c) ? 2 : 1;
+    p->fp = make_fft_plan(n);
+    DevBuf kf_d, kc_d;
+    if (p->tau_f > 0 || p->tau_c > 0) {
+        // masks: the host orders the clamped eigenvalues
+        std::vector<double> lam(s);
+        CES_HIP(hipMemcpyAsync(lam.data(), p->lam.p, (size_t)s * 8, hipMemcpyDeviceToHost, st), "eigenvalues");
+        CES_HIP(hipStreamSynchronize(st), "plan set-up");
+        for (double& v : lam) v = std::max(v, 0.0);
+        std::vector<int64_t> order;
+        smallest_order(lam, std::max(p->tau_f, p->tau_c), order);
+        p->keep_f.assign(s, 1);
+        p->keep_c.assign(s, 1);
+        for (int64_t i = 0; i < p->tau_f; ++i) p->keep_f[order[i]] = 0;
+        for (int64_t i = 0; i < p->tau_c; ++i) p->keep_c[order[i]] = 0;
+        if (p->tau_c > 0 && p->tau_c < s) {
+            double kept_min = 1e308;
+            for (int64_t i = 0; i < s; ++i)
+                if (p->keep_c[i]) kept_min = std::min(kept_min, lam[i]);
+            p->gap = (kept_min - lam[order[p->tau_c - 1]]) / std::max(p->lam_max, 1e-300);
+        }
+        CES_HIP(kf_d.alloc((size_t)s, A), "mask buffers");
+        CES_HIP(kc_d.alloc((size_t)s, A), "mask buffers");
+        CES_HIP(hipMemcpyAsync(kf_d.p, p->keep_f.data(), (size_t)s, hipMemcpyHostToDevice, st), "masks");
+        CES_HIP(hipMemcpyAsync(kc_d.p, p->keep_c.data(), (size_t)s, hipMemcpyHostToDevice, st), "masks");
+    }
+    const size_t tb = p->is_double ? 8 : 4;
+    CES_HIP(p->af.alloc((size_t)s * tb, A), "amplitude buffers");
+    if (p->nf == 2) CES_HIP(p->ac.alloc((size_t)s * tb, A), "amplitude buffers");
+    const uint8_t* mf = kf_d.as<uint8_t>();
+    const uint8_t* mc = kc_d.as<uint8_t>();
+    if (p->is_double)
+        CES_HIP(launch_amplitudes<double>(p->lam.as<double>(), n, mf, mc, p->af.as<double>(),
+                                          p->nf == 2 ? p->ac.as<double>() : nullptr, st),
+                "amplitudes");
+    else
+        CES_HIP(launch_amplitudes<float>(p->lam.as<double>(), n, mf, mc, p->af.as<float>(),
+                                         p->nf == 2 ? p->ac.as<float>() : nullptr, st),
+                "amplitudes");
+    CES_HIP(p->tw.alloc((size_t)n * (p->is_double ? sizeof(cplx<double>) : sizeof(cplx<float>)), A), "twiddles");
+    if (p->is_double) {
+        const auto tw = twiddles<double>(n);
+        CES_HIP(hipMemcpyAsync(p->tw.p, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice, st), "twiddles");
+        CES_HIP(hipStreamSynchronize(st), "plan set-up");
+    } else {
+        const auto tw = twiddles<float>(n);
+        CES_HIP(hipMemcpyAsync(p->tw.p, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice, st), "twiddles");
+        CES_HIP(hipStreamSynchronize(st), "plan set-up");
+    }
+    *out = p.release();
+    return CES_OK;
+}
+
+}  // namespace ces
 
 extern "C" {
 
@@ -299,78 +332,12 @@ int ces_context_destroy(ces_context ctx) {
 int ces_plan_create(ces_context ctx, const ces_level_desc* desc, ces_plan* out) {
     if (!ctx || !out) return fail(CES_ERR_ARG, "context or out is NULL");
     *out = nullptr;
-    int rc = validate(desc);
+    int rc = validate_desc(desc);
     if (rc != CES_OK) return rc;
     CES_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    std::unique_ptr<ces_plan_s> p(new ces_plan_s);
-    p->ctx = ctx;
-    p->d = *desc;
-    const int m = desc->m_fine;
-    Cov C{desc->cov_kind, desc->nu, desc->lambda, desc->sigma2};
-    std::vector<int> cands;
-    if (desc->psd_policy == CES_PSD_GROW) {
-        for (int J : {0, m / 2, m})
-            if (2 * (m + J) <= desc->max_pad_factor * m) cands.push_back(J);
-    } else {
-        cands.push_back(0);
-    }
-    bool ok = false;
-    for (int J : cands) {
-        if (J > 0 && desc->periodization == CES_PERIOD_EUCLID && !(1.0 + (double)J / m > std::sqrt(2.0))) continue;
-        const int n = 2 * (m + J);
-        if (make_fft_plan(n).nst < 0) continue;
-        std::vector<double> s = first_column(C, m, J, desc->periodization);
-        std::vector<double> lam;
-        double imag = 0.0;
-        rc = eigenvalues(s, n, lam, &imag);
-        if (rc != CES_OK) return rc;
-        symmetrise(lam, n);
-        const double lmin = *std::min_element(lam.begin(), lam.end());
-        const double lmax = *std::max_element(lam.begin(), lam.end());
-        p->n = n;
-        p->J = J;
-        p->lam_min = lmin;
-        p->lam_max = lmax;
-        p->lam.swap(lam);
-        ok = lmin >= -kPsdTol * lmax;
-        if (ok || desc->psd_policy == CES_PSD_CLAMP) break;
-    }
-    if (p->n == 0) return fail(CES_ERR_ARG, "no admissible embedding size");
-    if (!ok && desc->psd_policy != CES_PSD_CLAMP)
-        return fail(CES_ERR_NOT_PSD, "embedding has negative eigenvalues up to the padding cap (min/max = " +
-                                         std::to_string(p->lam_min / p->lam_max) + ")");
-    for (double& v : p->lam)
-        if (v < 0.0) {
-            v = 0.0;
-            ++p->n_clamped;
-        }
-    const int n = p->n;
-    const int64_t s = (int64_t)n * n;
-    p->tau_f = desc->tau_fine < 0 ? n : desc->tau_fine;
-    p->tau_c = desc->tau_coarse < 0 ? n : desc->tau_coarse;
-    if (desc->level_kind == CES_LEVEL_SINGLE) p->tau_c = p->tau_f;
-    if (p->tau_f > s || p->tau_c > s) return fail(CES_ERR_ARG, "tau exceeds the number of eigenvalues");
-    std::vector<int64_t> order;
-    smallest_order(p->lam, std::max(p->tau_f, p->tau_c), order);
-    p->keep_f.assign(s, 1);
-    p->keep_c.assign(s, 1);
-    for (int64_t i = 0; i < p->tau_f; ++i) p->keep_f[order[i]] = 0;
-    for (int64_t i = 0; i < p->tau_c; ++i) p->keep_c[order[i]] = 0;
-    if (p->tau_c > 0 && p->tau_c < s) {
-        // order[tau_c - 1]: largest dropped; smallest kept is the minimum
-        // over kept indices (order holds it only when tau_c is the max tau)
-        double kept_min = 1e308;
-        for (int64_t i = 0; i < s; ++i)
-            if (p->keep_c[i]) kept_min = std::min(kept_min, p->lam[i]);
-        p->gap = (kept_min - p->lam[order[p->tau_c - 1]]) / std::max(p->lam_max, 1e-300);
-    }
-    p->is_double = desc->precision == CES_PREC_FP64;
-    p->nf = (desc->level_kind == CES_LEVEL_PAIR && p->tau_f != p->tau_c) ? 2 : 1;
-    p->fp = make_fft_plan(n);
-    rc = p->is_double ? upload_amplitudes<double>(p.get()) : upload_amplitudes<float>(p.get());
-    if (rc != CES_OK) return rc;
-    *out = p.release();
-    return CES_OK;
+    hipStream_t st = nullptr;
+    CES_HIP(ctx->pool.stream(0, &st), "set-up stream");
+    return plan_create(ctx, desc, default_allocator(), st, out);
 }
 
 int ces_plan_info_get(ces_plan p, ces_plan_info* info) {
@@ -410,14 +377,22 @@ int ces_normals(uint64_t seed, uint64_t q, uint32_t stream, uint64_t first_e, in
 
 int ces_plan_eigenvalues(ces_plan p, double* host_out) {
     if (!p || !host_out) return fail(CES_ERR_ARG, "plan or out is NULL");
-    std::memcpy(host_out, p->lam.data(), p->lam.size() * 8);
+    CES_HIP(hipSetDevice(p->ctx->device), "hipSetDevice");
+    CES_HIP(hipMemcpy(host_out, p->lam.p, (size_t)p->n * p->n * 8, hipMemcpyDeviceToHost), "download eigenvalues");
     return CES_OK;
 }
 
 int ces_plan_mask(ces_plan p, uint8_t* f, uint8_t* c) {
     if (!p) return fail(CES_ERR_ARG, "plan is NULL");
-    if (f) std::memcpy(f, p->keep_f.data(), p->keep_f.size());
-    if (c) std::memcpy(c, p->keep_c.data(), p->keep_c.size());
+    const size_t s = (size_t)p->n * p->n;
+    if (f) {
+        if (p->keep_f.empty()) std::memset(f, 1, s);
+        else std::memcpy(f, p->keep_f.data(), s);
+    }
+    if (c) {
+        if (p->keep_c.empty()) std::memset(c, 1, s);
+        else std::memcpy(c, p->keep_c.data(), s);
+    }
     return CES_OK;
 }
 

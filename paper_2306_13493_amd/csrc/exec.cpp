@@ -38,6 +38,116 @@ hipError_t StreamPool::event(size_t i, hipEvent_t* out) {
     return hipSuccess;
 }
 
+namespace {
+
+class HipAllocator final : public DeviceAllocator {
+public:
+    hipError_t alloc(size_t bytes, void** p) override { return hipMalloc(p, bytes); }
+    void release(void* p) override { (void)hipFree(p); }
+};
+
+struct PinnedSlots {
+    std::mutex mu;
+    std::vector<int*> free;
+    std::vector<void*> slabs;
+};
+PinnedSlots& pinned() {
+    static PinnedSlots* s = new PinnedSlots;   // lives until the process ends
+    return *s;
+}
+
+}  // namespace
+
+DeviceAllocator* default_allocator() {
+    static HipAllocator a;
+    return &a;
+}
+
+int* pinned_slot_acquire() {
+    PinnedSlots& P = pinned();
+    std::lock_guard<std::mutex> g(P.mu);
+    if (P.free.empty()) {
+        constexpr int kSlots = 256, kInts = 16;   // 64-byte slots
+        void* slab = nullptr;
+        if (hipHostMalloc(&slab, (size_t)kSlots * kInts * sizeof(int), hipHostMallocDefault) != hipSuccess)
+            return nullptr;
+        P.slabs.push_back(slab);
+        for (int i = 0; i < kSlots; ++i) P.free.push_back(reinterpret_cast<int*>(slab) + i * kInts);
+    }
+    int* s = P.free.back();
+    P.free.pop_back();
+    return s;
+}
+
+void pinned_slot_release(int* slot) {
+    if (!slot) return;
+    PinnedSlots& P = pinned();
+    std::lock_guard<std::mutex> g(P.mu);
+    P.free.push_back(slot);
+}
+
+DevicePool::~DevicePool() {
+    trim();
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& kv : size_) (void)hipFree(kv.first);
+    size_.clear();
+}
+
+hipError_t DevicePool::alloc(size_t bytes, void** p) {
+    const size_t b = std::max<size_t>(256, (bytes + 255) / 256 * 256);
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = free_.lower_bound(b);
+        if (it != free_.end() && it->first <= 2 * b) {
+            *p = it->second;
+            cached_ -= it->first;
+            in_use_ += it->first;
+            free_.erase(it);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, b);
+    if (e != hipSuccess) {
+        // give the cached blocks back and try once more
+        trim();
+        e = hipMalloc(p, b);
+        if (e != hipSuccess) return e;
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    size_[*p] = b;
+    in_use_ += b;
+    return hipSuccess;
+}
+
+void DevicePool::release(void* p) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = size_.find(p);
+    if (it == size_.end()) return;
+    free_.emplace(it->second, p);
+    in_use_ -= it->second;
+    cached_ += it->second;
+}
+
+void DevicePool::trim() {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& kv : free_) {
+        (void)hipFree(kv.second);
+        size_.erase(kv.second);
+    }
+    free_.clear();
+    cached_ = 0;
+}
+
+size_t DevicePool::in_use() const {
+    std::lock_guard<std::mutex> g(mu_);
+    return in_use_;
+}
+
+size_t DevicePool::cached() const {
+    std::lock_guard<std::mutex> g(mu_);
+    return cached_;
+}
+
 size_t lvl_stride(int m) { return ((size_t)(m + 1) * (m + 1) + 63) / 64 * 64; }
 
 size_t slot_bytes(const ces_plan p) {
@@ -56,8 +166,9 @@ size_t slot_bytes(const ces_plan p) {
     return b + 32;
 }
 
-int ensure_workspace(ces_plan p, long long max_slots) {
-    if (p->sf) return CES_OK;
+namespace {
+
+long long workspace_slots(const ces_plan p, long long max_slots) {
     const int m = p->d.m_fine;
     const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
     const size_t per_slot = slot_bytes(p);
@@ -72,24 +183,40 @@ int ensure_workspace(ces_plan p, long long max_slots) {
     slots = std::min<long long>(slots, m <= 32 ? 65536 : 8192);
     if (max_slots > 0) slots = std::min(slots, pair_field ? (max_slots + 1) / 2 * 2 : max_slots);
     if (pair_field) slots &= ~1LL;
+    return slots;
+}
+
+}  // namespace
+
+size_t workspace_bytes(const ces_plan p, long long max_slots) {
+    const long long slots = workspace_slots(p, max_slots);
+    return slots > 0 ? (size_t)slots * slot_bytes(p) : 0;
+}
+
+int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st) {
+    if (p->sf) return CES_OK;
+    const int m = p->d.m_fine;
+    const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
+    const long long slots = workspace_slots(p, max_slots);
     if (slots < (pair_field ? 2 : 1))
         return fail(CES_ERR_NOMEM, "device memory budget too small for one sample of this plan");
     p->chunk_slots = (int)slots;
     p->chunk_units = pair_field ? (int)slots / 2 : (int)slots;
     const size_t tb = p->is_double ? 8 : 4;
+    DeviceAllocator* A = p->alloc;
     p->kf_ss = (long long)lvl_stride(m);
     p->kc_ss = (long long)lvl_stride(m / 2);
-    CES_HIP(p->work.alloc((size_t)p->nf * p->chunk_units * (m + 1) * p->n * 2 * tb), "field workspace");
-    CES_HIP(p->kf.alloc((size_t)slots * p->kf_ss * tb), "coefficient workspace");
-    CES_HIP(hipMemset(p->kf.p, 0, p->kf.bytes), "coefficient workspace");
+    CES_HIP(p->work.alloc((size_t)p->nf * p->chunk_units * (m + 1) * p->n * 2 * tb, A), "field workspace");
+    CES_HIP(p->kf.alloc((size_t)slots * p->kf_ss * tb, A), "coefficient workspace");
+    CES_HIP(hipMemsetAsync(p->kf.p, 0, p->kf.bytes, st), "coefficient workspace");
     if (p->d.level_kind == CES_LEVEL_PAIR) {
-        CES_HIP(p->kc.alloc((size_t)slots * p->kc_ss * tb), "coefficient workspace");
-        CES_HIP(hipMemset(p->kc.p, 0, p->kc.bytes), "coefficient workspace");
+        CES_HIP(p->kc.alloc((size_t)slots * p->kc_ss * tb, A), "coefficient workspace");
+        CES_HIP(hipMemsetAsync(p->kc.p, 0, p->kc.bytes, st), "coefficient workspace");
     }
-    CES_HIP(p->qf.alloc((size_t)slots * 8), "qoi workspace");
-    CES_HIP(p->qc.alloc((size_t)slots * 8), "qoi workspace");
-    CES_HIP(p->itf.alloc((size_t)slots * 4), "qoi workspace");
-    CES_HIP(p->itc.alloc((size_t)slots * 4), "qoi workspace");
+    CES_HIP(p->qf.alloc((size_t)slots * 8, A), "qoi workspace");
+    CES_HIP(p->qc.alloc((size_t)slots * 8, A), "qoi workspace");
+    CES_HIP(p->itf.alloc((size_t)slots * 4, A), "qoi workspace");
+    CES_HIP(p->itc.alloc((size_t)slots * 4, A), "qoi workspace");
     SolverCfg cfg;
     cfg.m = m;
     cfg.bc = p->d.bc;
@@ -100,11 +227,11 @@ int ensure_workspace(ces_plan p, long long max_slots) {
     cfg.qx = p->d.qoi_x;
     cfg.qy = p->d.qoi_y;
     std::string err;
-    p->sf = make_solver(cfg, (int)slots, p->is_double, &err);
+    p->sf = make_solver(cfg, (int)slots, p->is_double, A, st, &err);
     if (!p->sf) return fail(CES_ERR_NOMEM, err);
     if (p->d.level_kind == CES_LEVEL_PAIR) {
         cfg.m = m / 2;
-        p->sc = make_solver(cfg, (int)slots, p->is_double, &err);
+        p->sc = make_solver(cfg, (int)slots, p->is_double, A, st, &err);
         if (!p->sc) return fail(CES_ERR_NOMEM, err);
     }
     p->ws_bytes = p->work.bytes + p->kf.bytes + p->kc.bytes + p->sf->bytes() + (p->sc ? p->sc->bytes() : 0);
@@ -144,8 +271,8 @@ int field_t(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, 
     const int m = p->d.m_fine;
     const size_t nf = (size_t)(m + 1) * (m + 1), nc = (size_t)(m / 2 + 1) * (m / 2 + 1);
     if (!p->zf.p) {
-        CES_HIP(p->zf.alloc(2 * nf * 8), "field hook buffers");
-        CES_HIP(p->zc.alloc(2 * nc * 8), "field hook buffers");
+        CES_HIP(p->zf.alloc(2 * nf * 8, p->alloc), "field hook buffers");
+        CES_HIP(p->zc.alloc(2 * nc * 8, p->alloc), "field hook buffers");
     }
     FieldBatch<T> b = field_batch<T>(p, seed, pair_field ? sample / 2 : sample, 1);
     b.zf = p->zf.as<double>();
@@ -200,7 +327,7 @@ struct BusyGuard {
 }  // namespace
 
 int field_impl(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, hipStream_t st) {
-    int rc = ensure_workspace(p, 0);
+    int rc = ensure_workspace(p, 0, st);
     if (rc != CES_OK) return rc;
     BusyGuard g(p);
     if (!g.ok()) return fail(CES_ERR_BUSY, "plan is in use by another call");
@@ -208,7 +335,7 @@ int field_impl(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* z
 }
 
 int solve_impl(ces_plan p, int grid, int64_t count, const double* k, double* u, int32_t* iters, hipStream_t st) {
-    int rc = ensure_workspace(p, 0);
+    int rc = ensure_workspace(p, 0, st);
     if (rc != CES_OK) return rc;
     BusyGuard g(p);
     if (!g.ok()) return fail(CES_ERR_BUSY, "plan is in use by another call");
@@ -241,7 +368,25 @@ int Scheduler::lane_of(ces_plan p, Lane** out) {
     return CES_OK;
 }
 
-int Scheduler::add(const ces_request& r, hipEvent_t done_event) {
+hipError_t Scheduler::get_stream(hipStream_t* out) {
+    if (!free_streams_.empty()) {
+        *out = free_streams_.back();
+        free_streams_.pop_back();
+        return hipSuccess;
+    }
+    return pool_.stream(next_stream_++, out);
+}
+
+hipError_t Scheduler::get_event(hipEvent_t* out) {
+    if (!free_events_.empty()) {
+        *out = free_events_.back();
+        free_events_.pop_back();
+        return hipSuccess;
+    }
+    return pool_.event(next_event_++, out);
+}
+
+int Scheduler::add(const ces_request& r, hipEvent_t done_event, long long max_slots) {
     ces_plan p = r.plan;
     if (!p) return fail(CES_ERR_ARG, "request plan is NULL");
     if (r.count < 0) return fail(CES_ERR_ARG, "count < 0");
@@ -255,7 +400,7 @@ int Scheduler::add(const ces_request& r, hipEvent_t done_event) {
     Lane* L = nullptr;
     int rc = lane_of(p, &L);
     if (rc != CES_OK) return rc;
-    if ((rc = ensure_workspace(p, 0)) != CES_OK) return rc;
+    if ((rc = ensure_workspace(p, max_slots, caller_)) != CES_OK) return rc;
     const int per_unit = p->d.field_mode == CES_FIELD_PAIR ? 2 : 1;
     long long cu = p->chunk_units;
     if (s_.chunk_samples > 0) cu = std::max<long long>(1, std::min<long long>(cu, s_.chunk_samples / per_unit));
@@ -300,17 +445,17 @@ int Scheduler::start_t(Lane& L, const Job& j) {
 }
 
 int Scheduler::start(Lane& L) {
-    if (!fork_) {
-        CES_HIP(pool_.event(next_event_++, &fork_), "scheduler event");
-        CES_HIP(hipEventRecord(fork_, caller_), "fork");
-    }
     if (!L.forked) {
-        CES_HIP(pool_.stream(next_stream_++, &L.sa), "lane stream");
-        CES_HIP(pool_.stream(next_stream_++, &L.sb), "lane stream");
-        CES_HIP(pool_.event(next_event_++, &L.ev_f), "lane event");
-        CES_HIP(pool_.event(next_event_++, &L.ev_c), "lane event");
-        CES_HIP(hipStreamWaitEvent(L.sa, fork_, 0), "fork");
-        CES_HIP(hipStreamWaitEvent(L.sb, fork_, 0), "fork");
+        // the lane's streams start after everything the caller's stream
+        // holds now (workspace zeroing included)
+        CES_HIP(get_stream(&L.sa), "lane stream");
+        CES_HIP(get_stream(&L.sb), "lane stream");
+        CES_HIP(get_event(&L.ev_f), "lane event");
+        CES_HIP(get_event(&L.ev_c), "lane event");
+        CES_HIP(get_event(&L.ev_fork), "lane event");
+        CES_HIP(hipEventRecord(L.ev_fork, caller_), "fork");
+        CES_HIP(hipStreamWaitEvent(L.sa, L.ev_fork, 0), "fork");
+        CES_HIP(hipStreamWaitEvent(L.sb, L.ev_fork, 0), "fork");
         L.forked = true;
     }
     const Job& j = L.jobs[L.next];
@@ -405,7 +550,7 @@ int Scheduler::join() {
         if (L->forked) {
             for (hipStream_t s : {L->sa, L->sb}) {
                 hipEvent_t e = nullptr;
-                hipError_t err = pool_.event(next_event_++, &e);
+                hipError_t err = get_event(&e);
                 if (err == hipSuccess) err = hipEventRecord(e, s);
                 if (err == hipSuccess) err = hipStreamWaitEvent(caller_, e, 0);
                 if (err != hipSuccess && rc == CES_OK) rc = hip_fail(err, "join");
@@ -414,6 +559,38 @@ int Scheduler::join() {
         L->p->busy.store(0);
     }
     return rc;
+}
+
+void Scheduler::retire(std::vector<ces_plan>* released) {
+    std::vector<std::unique_ptr<Lane>> keep;
+    for (auto& L : lanes_) {
+        if (L->solving || L->next < L->jobs.size()) {
+            keep.push_back(std::move(L));
+            continue;
+        }
+        if (L->forked) {
+            // later work on these streams only depends on what is enqueued
+            // after it, so they can serve another lane at once
+            free_streams_.push_back(L->sa);
+            free_streams_.push_back(L->sb);
+            free_events_.push_back(L->ev_f);
+            free_events_.push_back(L->ev_c);
+            free_events_.push_back(L->ev_fork);
+        }
+        L->p->busy.store(0);
+        released->push_back(L->p);
+    }
+    lanes_.swap(keep);
+}
+
+int Scheduler::pending_solves() const {
+    int n = 0;
+    for (auto& L : lanes_) {
+        if (!L->solving) continue;
+        n += L->fdone ? 0 : 1;
+        n += (L->p->sc && !L->cdone) ? 1 : 0;
+    }
+    return n;
 }
 
 }  // namespace ces

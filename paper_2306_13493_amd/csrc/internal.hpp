@@ -13,6 +13,50 @@ namespace ces {
 enum { MODE_PAIR = 0, MODE_HARTLEY = 1 };
 enum { BC_DIRICHLET0 = 0, BC_FLOWCELL = 1 };
 enum { Q_INTEGRAL = 0, Q_POINT = 1, Q_L2 = 2, Q_OUTFLUX = 3 };
+enum { COV_MATERN = 0, COV_SEPEXP = 1 };
+enum { PERIOD_EUCLID = 0, PERIOD_INF = 1 };
+
+// ------------------------------------------------------ device memory --
+// Source of the library's device workspaces: plain hipMalloc/hipFree, or
+// a caching pool that keeps released blocks for reuse, so that a serving
+// loop never frees (and so never synchronises the device) while other
+// streams run.
+class DeviceAllocator {
+public:
+    virtual ~DeviceAllocator() = default;
+    virtual hipError_t alloc(size_t bytes, void** p) = 0;
+    virtual void release(void* p) = 0;
+};
+DeviceAllocator* default_allocator();
+
+// Pinned host slots of 4 ints for convergence read-backs, recycled for the
+// life of the process (freeing pinned memory would synchronise the device).
+int* pinned_slot_acquire();
+void pinned_slot_release(int* slot);
+
+// ---------------------------------------------------------- plan set-up --
+// Covariance model (Section 2.1): Matern with smoothness nu (pref =
+// sigma2 2^(1-nu) / Gamma(nu)), or the separable exponential.
+struct CovParams {
+    int kind = COV_MATERN;
+    double nu = 0.5, lam = 0.1, sigma2 = 1.0, pref = 1.0;
+};
+// First column of the n x n embedding (Algorithm 1 step 2; n = 2(m + J)),
+// index [j2][j1]: C at the minimum-image offsets for J = 0, the smoothly
+// periodised covariance of Section 2.2 for J > 0 (cutoff norm `reading`).
+hipError_t launch_cov_column(double* s, int n, int m, int J, int reading, const CovParams& c,
+                             hipStream_t st);
+// out[k] = lam[rep(k)] with rep the orbit representative (min(k, n-k) per
+// axis, pair sorted); per-block minimum, maximum and count of negatives.
+// nblk receives the number of blocks.
+hipError_t launch_symmetrise(const double* lam, double* out, int n, double* bmin, double* bmax,
+                             int* bneg, int* nblk, hipStream_t st);
+int symmetrise_blocks(int n);
+// lam <- max(lam, 0); af = sqrt(lam)/n masked by keep_f (null = all kept),
+// ac likewise with keep_c (ac may be null).
+template <typename T>
+hipError_t launch_amplitudes(double* lam, int n, const uint8_t* keep_f, const uint8_t* keep_c, T* af,
+                             T* ac, hipStream_t st);
 
 // ---------------------------------------------------------------- field --
 // One batch of DFT units (pairs in PAIR mode, samples in HARTLEY mode):
@@ -106,9 +150,10 @@ public:
     virtual const double* x() const = 0;
     virtual long long xstride() const = 0;
 };
-// is_double selects T = double (plain path) or float (mixed path).
+// is_double selects T = double (plain path) or float (mixed path).  The
+// workspace comes from `alloc` and is zeroed on stream st.
 std::unique_ptr<Solver> make_solver(const SolverCfg& cfg, int capacity, bool is_double,
-                                    std::string* err);
+                                    DeviceAllocator* alloc, hipStream_t st, std::string* err);
 
 // y[i] = qf[i] - qc[i] (or qf if qc null) scattered to out slots.
 hipError_t launch_finalize(const double* qf, const double* qc, const int* itf, const int* itc,

@@ -5,7 +5,9 @@
 
 #include <atomic>
 #include <cstdint>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,20 +29,46 @@ int hip_fail(hipError_t e, const char* what);
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    DeviceAllocator* a = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-    hipError_t alloc(size_t b) {
-        if (p) (void)hipFree(p);
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p) a->release(p);
         p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t b, DeviceAllocator* from = nullptr) {
+        reset();
+        a = from ? from : default_allocator();
         bytes = b;
-        return b ? hipMalloc(&p, b) : hipSuccess;
+        return b ? a->alloc(b, &p) : hipSuccess;
     }
     template <typename U>
     U* as() const { return reinterpret_cast<U*>(p); }
+};
+
+// Caching device allocator: released blocks are kept (keyed by size) and
+// handed out again for requests they fit within a factor of two; nothing
+// is returned to HIP until trim() or destruction.  Thread-safe.
+class DevicePool final : public DeviceAllocator {
+public:
+    DevicePool() = default;
+    DevicePool(const DevicePool&) = delete;
+    DevicePool& operator=(const DevicePool&) = delete;
+    ~DevicePool() override;
+    hipError_t alloc(size_t bytes, void** p) override;
+    void release(void* p) override;
+    void trim();                 // frees every cached block (synchronises)
+    size_t in_use() const;       // bytes handed out
+    size_t cached() const;       // bytes kept for reuse
+
+private:
+    mutable std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    std::map<void*, size_t> size_;
+    size_t in_use_ = 0, cached_ = 0;
 };
 
 // Streams (default priority, non-blocking) and events, created on first
@@ -75,12 +103,13 @@ struct ces_context_s {
 struct ces_plan_s {
     ces_context ctx = nullptr;
     ces_level_desc d{};
+    ces::DeviceAllocator* alloc = nullptr;   // source of every device buffer of the plan
     int n = 0, J = 0;
     int64_t tau_f = 0, tau_c = 0;
-    double lam_min = 0, lam_max = 0, gap = 0;
+    double lam_min = 0, lam_max = 0, gap = 0, imag_max = 0;
     int64_t n_clamped = 0;
-    std::vector<double> lam;            // symmetrised, clamped
-    std::vector<uint8_t> keep_f, keep_c;
+    ces::DevBuf lam;                    // symmetrised, clamped eigenvalues (n*n doubles)
+    std::vector<uint8_t> keep_f, keep_c;  // masks; empty = every eigenvalue kept
     bool is_double = false;
     int nf = 1;                         // DFTs per unit
     ces::FftPlan fp{};
@@ -99,10 +128,19 @@ namespace ces {
 // Device bytes per in-flight sample of a plan's workspace.
 size_t slot_bytes(const ces_plan p);
 
-// Allocates the plan's sample workspace on first use.  max_slots > 0 caps
-// the samples per chunk (the serving loop sizes workspaces per request);
-// 0 sizes it for throughput (about 4 GiB, at most 8192 samples).
-int ensure_workspace(ces_plan p, long long max_slots);
+// Plan set-up (Algorithm 1 steps 1-3 and the masks of Algorithm 2) with
+// device buffers from `alloc`, device work on stream st (synchronised).
+int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* alloc, hipStream_t st,
+                ces_plan* out);
+int validate_desc(const ces_level_desc* d);
+
+// Allocates the plan's sample workspace on first use (zeroed on stream st).
+// max_slots > 0 caps the samples per chunk (the serving loop sizes
+// workspaces per request); 0 sizes it for throughput (about 4 GiB, at
+// most 8192 samples, 65536 for m <= 32).
+int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st);
+// Device bytes ensure_workspace(p, max_slots) would allocate.
+size_t workspace_bytes(const ces_plan p, long long max_slots);
 
 // Gaussian field of one sample into z_fine / z_coarse (parity hook).
 int field_impl(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, hipStream_t st);
@@ -111,17 +149,21 @@ int solve_impl(ces_plan p, int grid, int64_t count, const double* k, double* u, 
                hipStream_t st);
 
 // The sampling scheduler: requests are split into chunks of their plan's
-// workspace capacity; each distinct plan is a lane with two streams forked
-// from the caller's stream (field + fine solve + finalize, coarse solve)
-// and joined back at the end; one host thread interleaves the lanes,
-// keeping up to `depth` CG iterations of every solve in flight.
+// workspace capacity; each distinct plan is a lane with two streams
+// (field + fine solve + finalize, coarse solve) forked from the caller's
+// stream when the lane starts; one host thread interleaves the lanes,
+// keeping up to `depth` CG iterations of every solve in flight.  A batch
+// call joins every lane back into the caller's stream; the serving loop
+// instead retires lanes whose work is all enqueued and reuses their
+// streams.
 class Scheduler {
 public:
     Scheduler(StreamPool& pool, hipStream_t caller, const ces_schedule& s);
     ~Scheduler();
     // Queue one request; done_event (may be null) is recorded once all of
-    // its results are written.
-    int add(const ces_request& r, hipEvent_t done_event);
+    // its results are written.  max_slots > 0 sizes a new workspace for at
+    // most that many samples per chunk.
+    int add(const ces_request& r, hipEvent_t done_event, long long max_slots = 0);
     // One pass over the lanes; *progressed = some work was enqueued.
     int step(bool* progressed);
     bool idle() const;
@@ -130,6 +172,12 @@ public:
     // make the caller's stream wait for every lane (ends the scheduler's use
     // of the plans)
     int join();
+    // Drop the lanes whose queued jobs are all enqueued; their plans are
+    // appended to *released (no longer used by the scheduler).
+    void retire(std::vector<ces_plan>* released);
+    int lanes() const { return (int)lanes_.size(); }
+    // solves in progress (for an idle wait of the serving loop)
+    int pending_solves() const;
 
 private:
     struct Job {
@@ -145,19 +193,22 @@ private:
         size_t next = 0;
         bool solving = false, fdone = false, cdone = false, forked = false;
         hipStream_t sa = nullptr, sb = nullptr;
-        hipEvent_t ev_f = nullptr, ev_c = nullptr;
+        hipEvent_t ev_f = nullptr, ev_c = nullptr, ev_fork = nullptr;
     };
     int lane_of(ces_plan p, Lane** out);
     int start(Lane& L);
     int finish(Lane& L);
     template <typename T>
     int start_t(Lane& L, const Job& j);
+    hipError_t get_stream(hipStream_t* s);
+    hipError_t get_event(hipEvent_t* e);
 
     StreamPool& pool_;
     hipStream_t caller_;
     ces_schedule s_;
-    hipEvent_t fork_ = nullptr;
     std::vector<std::unique_ptr<Lane>> lanes_;
+    std::vector<hipStream_t> free_streams_;
+    std::vector<hipEvent_t> free_events_;
     size_t next_stream_ = 0, next_event_ = 0;
     bool joined_ = false;
 };

@@ -1300,20 +1300,24 @@ public:
         bytes_ = off;
     }
     ~SolverImpl() override {
-        if (base_) (void)hipFree(base_);
-        if (hcnt_) (void)hipHostFree(hcnt_);
+        if (base_) alloc_->release(base_);
+        if (hcnt_) pinned_slot_release(hcnt_);
         for (auto& e : ev_)
             if (e) (void)hipEventDestroy(e);
     }
-    bool alloc(std::string* err) {
-        hipError_t e = hipMalloc(&base_, bytes_);
+    bool alloc(DeviceAllocator* a, hipStream_t st, std::string* err) {
+        alloc_ = a;
+        hipError_t e = alloc_->alloc(bytes_, &base_);
         if (e != hipSuccess) {
             base_ = nullptr;
             *err = std::string("solver workspace allocation failed: ") + hipGetErrorString(e);
             return false;
         }
-        e = hipMemset(base_, 0, bytes_);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&hcnt_, RING * sizeof(int), hipHostMallocDefault);
+        e = hipMemsetAsync(base_, 0, bytes_, st);
+        if (e == hipSuccess) {
+            hcnt_ = pinned_slot_acquire();
+            if (!hcnt_) e = hipErrorOutOfMemory;
+        }
         for (auto& ev : ev_)
             if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess && small_) {
@@ -1611,6 +1615,7 @@ private:
     size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0, o_hist_ = 0;
     std::vector<std::pair<int, int>> recs_;
     size_t bytes_ = 0;
+    DeviceAllocator* alloc_ = nullptr;
     void* base_ = nullptr;
     int* hcnt_ = nullptr;
     hipEvent_t ev_[RING] = {nullptr, nullptr, nullptr, nullptr};
@@ -1623,18 +1628,19 @@ private:
 
 }  // namespace
 
-std::unique_ptr<Solver> make_solver(const SolverCfg& cfg, int capacity, bool is_double, std::string* err) {
+std::unique_ptr<Solver> make_solver(const SolverCfg& cfg, int capacity, bool is_double, DeviceAllocator* alloc,
+                                    hipStream_t st, std::string* err) {
     if (cfg.m < 4 || (cfg.m & (cfg.m - 1)) != 0) {
         *err = "solver mesh must be a power of two >= 4";
         return nullptr;
     }
     if (is_double) {
         auto s = std::make_unique<SolverImpl<double>>(cfg, capacity);
-        if (!s->alloc(err)) return nullptr;
+        if (!s->alloc(alloc, st, err)) return nullptr;
         return s;
     }
     auto s = std::make_unique<SolverImpl<float>>(cfg, capacity);
-    if (!s->alloc(err)) return nullptr;
+    if (!s->alloc(alloc, st, err)) return nullptr;
     return s;
 }
 

@@ -64,6 +64,13 @@ EIG_CASES = {
     "sepexp": dict(cov="sepexp", lam=0.1, m=32),
     "c3_l2_smoothed": W.c3_level(2),
     "c3_l4_finest": W.c3_level(4),
+    # general nu (Bessel K from the device routine), periodised
+    "matern_nu23_grow": dict(cov="matern", nu=2.3, lam=0.2, m=32, psd="grow"),
+    "matern_nu1_grow_inf": dict(cov="matern", nu=1.0, lam=0.25, m=32, psd="grow", period="inf"),
+    "sepexp_grow_m64": dict(cov="sepexp", lam=0.3, m=64, psd="grow"),
+    # large embeddings: C5 (n = 4096) and a padded nu = 1 pair level (n = 1536)
+    "c5_n4096": W.C5,
+    "nu1_grow_m512_pair": dict(cov="matern", nu=1.0, lam=0.3, m=512, level="pair"),
 }
 
 
