@@ -138,6 +138,87 @@ def c3_batch(ces, ctx, W, log, reps=5):
             "schedule": list(ctx.schedule)}
 
 
+def serve(args):
+    """Serving workload: replay the arrival trace (Poisson arrivals, mixed
+    meshes 33^2 .. 1025^2, counts 1..256, a fresh covariance per request)
+    into one server and drain.  Prints one JSON line."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_2306_13493_amd as ces
+    from paper_2306_13493_amd import workloads as W
+
+    torch.cuda.init()
+    ces.load()
+    ctx = ces.Context(0)
+    trace = W.c4_trace(duration_s=args.duration, rate=args.rate)
+    log("serving trace: %d requests over %.1f s (rate %.0f/s), %d level samples"
+        % (len(trace), args.duration, args.rate, sum(r["count"] for r in trace)))
+    # warm the kernels on a throwaway server (first launches load code objects)
+    warm = ces.Server(ctx)
+    for m in (32, 64, 1024):
+        warm.submit(dict(trace[0]["w"], m=m, level="single" if m == 32 else "pair"), 0, 0, 2)
+    warm.drain()
+    warm.close()
+    srv = ces.Server(ctx, mem_budget=int(args.mem_gb * (1 << 30)), max_inflight=args.max_inflight)
+    ids = [None] * len(trace)
+    t0 = time.perf_counter()
+
+    def replay():
+        for i, r in enumerate(trace):
+            d = r["t"] - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            ids[i] = srv.submit(r["w"], r["seed"], r["first"], r["count"])
+
+    th = threading.Thread(target=replay)
+    th.start()
+    last = time.perf_counter()
+    while th.is_alive():
+        th.join(timeout=5.0)
+        st = srv.stats()
+        log("t=%.1f s submitted %d completed %d admitted %d queued %d mem %.1f GB"
+            % (time.perf_counter() - t0, st["submitted"], st["completed"], st["admitted"], st["queued"],
+               st["mem_in_use"] / 2 ** 30))
+    t_submit_end = time.perf_counter() - t0
+    done = threading.Event()
+
+    def drainer():
+        srv.drain()
+        done.set()
+
+    dt = threading.Thread(target=drainer)
+    dt.start()
+    while not done.wait(timeout=10.0):
+        st = srv.stats()
+        log("draining: t=%.1f s completed %d / %d" % (time.perf_counter() - t0, st["completed"], st["submitted"]))
+    dt.join()
+    t_end = time.perf_counter() - t0
+    st = srv.stats()
+    lat = np.array([srv.poll(i)[1] for i in ids])
+    states = np.array([srv.poll(i)[0] for i in ids])
+    samples = sum(r["count"] for r in trace)
+    srv.close()
+    line = {
+        "metric": "served level samples/sec at 1 GPU, p50/p99 request latency",
+        "value": round(samples / t_end, 1), "unit": "samples/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": "serving trace: Poisson arrivals %.0f/s for %.0f s; m uniform on 32..1024 "
+                               "(pair (m, m/2) except single at 32), count 1..256, Matern nu in {1/2, 1, 3/2}, "
+                               "lambda in [0.02, 0.3], tau 0, embedding grown up to 4x, mixed precision; then drain"
+                               % (args.rate, args.duration),
+                   "requests": len(trace), "level_samples": samples, "mem_budget_gb": args.mem_gb,
+                   "max_inflight": args.max_inflight},
+        "requests_per_s": round(len(trace) / t_end, 2),
+        "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                      "max": round(float(lat.max()), 4), "per": "request, submit to results in host memory"},
+        "wall_s": round(t_end, 2), "arrivals_end_s": round(t_submit_end, 2),
+        "completed": int((states == 2).sum()), "failed": int((states < 0).sum()),
+        "mem_peak_gb": round(st["mem_peak"] / 2 ** 30, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,11 +231,21 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the five-level batched estimator line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (scale for HBM counters)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
+                    help="c2: throughput of the single-level workload (default); c4: serving trace")
+    ap.add_argument("--rate", type=float, default=200.0, help="c4: arrivals per second")
+    ap.add_argument("--duration", type=float, default=30.0, help="c4: seconds of arrivals")
+    ap.add_argument("--mem-gb", type=float, default=200.0, help="c4: server memory budget")
+    ap.add_argument("--max-inflight", type=int, default=64, help="c4: admitted requests at most")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(samples shard by index across GPUs; see the design notes). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        serve(args)
+        return
 
     import numpy as np
     import torch

@@ -203,6 +203,59 @@ int ces_schedule_set(ces_context ctx, const ces_schedule* sched);
 int ces_autotune(ces_context ctx, const ces_request* reqs, int32_t nreq, void* hip_stream,
                  ces_schedule* chosen, double* best_ms);
 
+/* ---- serving: continuous batching with memory admission -------------- */
+
+/* A server owns a host thread that plans, admits and runs requests as they
+ * arrive.  Each request is one level descriptor (its own covariance, mesh,
+ * precision ...) with a seed and a sample range; its results are written
+ * to caller-owned host memory.  Requests with identical descriptors share
+ * one plan.  Set-up (ces_plan_create's work) runs on a planner thread; a
+ * planned request is admitted when its device memory (workspace sized for
+ * its sample count, plus outputs) fits within mem_budget_bytes next to the
+ * admitted ones and fewer than max_inflight are admitted; admitted
+ * requests join the running batch at once (no waiting for a round to end)
+ * and leave it as they complete.  Y of a request equals what ces_sample
+ * returns for the same descriptor, seed and range, bit for bit.  Device
+ * memory comes from a caching pool owned by the server. */
+typedef struct ces_server_s* ces_server;
+
+typedef struct {
+    int64_t submitted;     /* requests accepted by ces_server_submit */
+    int64_t completed;     /* requests whose results are in host memory */
+    int64_t failed;        /* requests that ended with an error */
+    int64_t queued;        /* submitted, not yet admitted */
+    int64_t admitted;      /* admitted, not yet complete */
+    int64_t samples_done;  /* level samples of completed requests */
+    size_t mem_in_use;     /* device bytes of the server's pool in use */
+    size_t mem_peak;       /* largest mem_in_use seen */
+    int32_t plans_cached;  /* plans alive (shared by identical descriptors) */
+    int32_t reserved;
+} ces_server_stats;
+
+/* mem_budget_bytes = 0: 90% of the context's budget.  max_inflight <= 0:
+ * 64.  The context must outlive the server and may be used by its owner
+ * thread meanwhile (the server has its own streams and memory pool). */
+int ces_server_create(ces_context ctx, size_t mem_budget_bytes, int32_t max_inflight, ces_server* out);
+
+/* Queue a request; returns at once.  y_host (count doubles) and status_host
+ * (count int32, may be NULL) must stay valid until the request is done.
+ * The descriptor is copied; invalid descriptors fail here (CES_ERR_ARG). */
+int ces_server_submit(ces_server srv, const ces_level_desc* desc, uint64_t seed, uint64_t first_sample,
+                      int64_t count, double* y_host, int32_t* status_host, int64_t* request_id);
+
+/* *state: 0 queued, 1 admitted, 2 done (results in host memory), or a
+ * negative CES_ERR_* code.  *latency_s (may be NULL): submit to completion
+ * for done requests, time since submit otherwise. */
+int ces_server_poll(ces_server srv, int64_t request_id, int32_t* state, double* latency_s);
+
+/* Block until every request submitted so far is done or failed. */
+int ces_server_drain(ces_server srv);
+
+int ces_server_get_stats(ces_server srv, ces_server_stats* out);
+
+/* Drain, stop the threads, free the plans and the memory pool. */
+int ces_server_destroy(ces_server srv);
+
 /* ---- parity hooks (same kernels as ces_sample) ------------------------ */
 
 /* Box-Muller normals of Philox counter (e, q mod 2^32, q >> 32, stream),

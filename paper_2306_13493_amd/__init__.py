@@ -15,7 +15,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import CesError, LevelDesc, PlanInfo, Request, Schedule, check, load
+from ._lib import CesError, LevelDesc, PlanInfo, Request, Schedule, ServerStats, check, load
 
 COV = {"matern": 0, "sepexp": 1}
 LEVEL = {"single": 0, "pair": 1}
@@ -242,6 +242,65 @@ class Plan:
             pass
 
 
+class Server:
+    """ces_server: continuous batching of level-sample requests with device
+    memory admission.  Results land in host numpy arrays owned here."""
+
+    QUEUED, ADMITTED, DONE = 0, 1, 2
+
+    def __init__(self, ctx, mem_budget=0, max_inflight=0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = ctypes.c_void_p()
+        check(self.lib.ces_server_create(ctx.handle, int(mem_budget), int(max_inflight), ctypes.byref(h)))
+        self.handle = h
+        self._bufs = {}
+
+    def submit(self, desc, seed, first, count):
+        """Queue one request (desc: a LevelDesc or a dict of level_desc
+        arguments); returns its id."""
+        if isinstance(desc, dict):
+            desc = level_desc(**desc)
+        y = np.empty(int(count), dtype=np.float64)
+        st = np.empty(int(count), dtype=np.int32)
+        rid = ctypes.c_int64()
+        check(self.lib.ces_server_submit(self.handle, ctypes.byref(desc), int(seed), int(first), int(count),
+                                         y.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.byref(rid)))
+        self._bufs[rid.value] = (y, st)
+        return rid.value
+
+    def poll(self, rid):
+        """(state, latency_s): state 0 queued, 1 admitted, 2 done, < 0 error."""
+        state = ctypes.c_int32()
+        lat = ctypes.c_double()
+        check(self.lib.ces_server_poll(self.handle, int(rid), ctypes.byref(state), ctypes.byref(lat)))
+        return state.value, lat.value
+
+    def result(self, rid):
+        """(y, status) host arrays of a request (complete once poll says done)."""
+        return self._bufs[rid]
+
+    def drain(self):
+        check(self.lib.ces_server_drain(self.handle))
+
+    def stats(self):
+        s = ServerStats()
+        check(self.lib.ces_server_get_stats(self.handle, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_ if k != "reserved"}
+
+    def close(self):
+        if self.handle:
+            self.lib.ces_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def normals(seed, q, stream_tag, first_e, count, device=0, stream=None):
     """(count, 2) float64 device tensor of Box-Muller pairs (parity hook)."""
     torch = _torch()
@@ -267,5 +326,5 @@ def profile_read(max_entries=64):
             for i in range(min(n.value, max_entries))}
 
 
-__all__ = ["Context", "Plan", "level_desc", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc",
+__all__ = ["Context", "Plan", "Server", "level_desc", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc",
            "PlanInfo", "Request", "Schedule", "load"]

@@ -55,6 +55,12 @@ class Schedule(ctypes.Structure):
     _fields_ = [("depth", c_int32), ("max_lanes", c_int32), ("chunk_samples", c_int64)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_int64), ("completed", c_int64), ("failed", c_int64), ("queued", c_int64),
+                ("admitted", c_int64), ("samples_done", c_int64), ("mem_in_use", c_size_t),
+                ("mem_peak", c_size_t), ("plans_cached", c_int32), ("reserved", c_int32)]
+
+
 # name -> (restype, argtypes); every function declared in include/cesmlmc.h
 SIGNATURES = {
     "ces_level_desc_default": (None, [ctypes.POINTER(LevelDesc)]),
@@ -70,6 +76,13 @@ SIGNATURES = {
     "ces_schedule_set": (c_int32, [c_void_p, ctypes.POINTER(Schedule)]),
     "ces_autotune": (c_int32, [c_void_p, ctypes.POINTER(Request), c_int32, c_void_p, ctypes.POINTER(Schedule),
                                ctypes.POINTER(c_double)]),
+    "ces_server_create": (c_int32, [c_void_p, c_size_t, c_int32, ctypes.POINTER(c_void_p)]),
+    "ces_server_submit": (c_int32, [c_void_p, ctypes.POINTER(LevelDesc), c_uint64, c_uint64, c_int64, c_void_p,
+                                    c_void_p, ctypes.POINTER(c_int64)]),
+    "ces_server_poll": (c_int32, [c_void_p, c_int64, ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
+    "ces_server_drain": (c_int32, [c_void_p]),
+    "ces_server_get_stats": (c_int32, [c_void_p, ctypes.POINTER(ServerStats)]),
+    "ces_server_destroy": (c_int32, [c_void_p]),
     "ces_normals": (c_int32, [c_uint64, c_uint64, c_uint32, c_uint64, c_int64, c_dptr, c_void_p]),
     "ces_plan_eigenvalues": (c_int32, [c_void_p, c_void_p]),
     "ces_plan_mask": (c_int32, [c_void_p, c_void_p, c_void_p]),

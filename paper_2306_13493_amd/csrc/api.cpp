@@ -145,7 +145,8 @@ int validate_desc(const ces_level_desc* d) {
     return CES_OK;
 }
 
-int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* A, hipStream_t st, ces_plan* out) {
+int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* A, hipStream_t st, ces_plan* out,
+                bool keep_eigenvalues) {
     *out = nullptr;
     int rc = validate_desc(desc);
     if (rc != CES_OK) return rc;
@@ -250,6 +251,7 @@ int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* A,
         CES_HIP(hipMemcpyAsync(p->tw.p, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice, st), "twiddles");
         CES_HIP(hipStreamSynchronize(st), "plan set-up");
     }
+    if (!keep_eigenvalues) p->lam.reset();
     *out = p.release();
     return CES_OK;
 }
@@ -377,6 +379,7 @@ int ces_normals(uint64_t seed, uint64_t q, uint32_t stream, uint64_t first_e, in
 
 int ces_plan_eigenvalues(ces_plan p, double* host_out) {
     if (!p || !host_out) return fail(CES_ERR_ARG, "plan or out is NULL");
+    if (!p->lam.p) return fail(CES_ERR_ARG, "plan kept no eigenvalues");
     CES_HIP(hipSetDevice(p->ctx->device), "hipSetDevice");
     CES_HIP(hipMemcpy(host_out, p->lam.p, (size_t)p->n * p->n * 8, hipMemcpyDeviceToHost), "download eigenvalues");
     return CES_OK;

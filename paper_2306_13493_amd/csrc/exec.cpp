@@ -326,12 +326,26 @@ struct BusyGuard {
 
 }  // namespace
 
+// Records the plan's workspace-free event on the stream that ran the last
+// work using the workspace (a lane's coarse stream joins its main stream
+// before every finalize, so for a lane that is its main stream).
+static hipError_t mark_workspace_free(ces_plan p, hipStream_t st) {
+    if (!p->ws_free) {
+        hipError_t e = hipEventCreateWithFlags(&p->ws_free, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(p->ws_free, st);
+}
+
 int field_impl(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, hipStream_t st) {
     int rc = ensure_workspace(p, 0, st);
     if (rc != CES_OK) return rc;
     BusyGuard g(p);
     if (!g.ok()) return fail(CES_ERR_BUSY, "plan is in use by another call");
-    return p->is_double ? field_t<double>(p, seed, sample, zf, zc, st) : field_t<float>(p, seed, sample, zf, zc, st);
+    if (p->ws_free) CES_HIP(hipStreamWaitEvent(st, p->ws_free, 0), "workspace");
+    rc = p->is_double ? field_t<double>(p, seed, sample, zf, zc, st) : field_t<float>(p, seed, sample, zf, zc, st);
+    if (rc == CES_OK) CES_HIP(mark_workspace_free(p, st), "workspace");
+    return rc;
 }
 
 int solve_impl(ces_plan p, int grid, int64_t count, const double* k, double* u, int32_t* iters, hipStream_t st) {
@@ -339,8 +353,11 @@ int solve_impl(ces_plan p, int grid, int64_t count, const double* k, double* u, 
     if (rc != CES_OK) return rc;
     BusyGuard g(p);
     if (!g.ok()) return fail(CES_ERR_BUSY, "plan is in use by another call");
-    return p->is_double ? solve_t<double>(p, grid, count, k, u, iters, st)
-                        : solve_t<float>(p, grid, count, k, u, iters, st);
+    if (p->ws_free) CES_HIP(hipStreamWaitEvent(st, p->ws_free, 0), "workspace");
+    rc = p->is_double ? solve_t<double>(p, grid, count, k, u, iters, st)
+                      : solve_t<float>(p, grid, count, k, u, iters, st);
+    if (rc == CES_OK) CES_HIP(mark_workspace_free(p, st), "workspace");
+    return rc;
 }
 
 // ------------------------------------------------------------ scheduler
@@ -386,7 +403,8 @@ hipError_t Scheduler::get_event(hipEvent_t* out) {
     return pool_.event(next_event_++, out);
 }
 
-int Scheduler::add(const ces_request& r, hipEvent_t done_event, long long max_slots) {
+int Scheduler::add(const ces_request& r, hipEvent_t done_event, long long max_slots, double* y_host,
+                   int32_t* status_host, std::atomic<int>* recorded) {
     ces_plan p = r.plan;
     if (!p) return fail(CES_ERR_ARG, "request plan is NULL");
     if (r.count < 0) return fail(CES_ERR_ARG, "count < 0");
@@ -395,6 +413,7 @@ int Scheduler::add(const ces_request& r, hipEvent_t done_event, long long max_sl
     if (joined_) return fail(CES_ERR_ARG, "scheduler already joined");
     if (r.count == 0) {
         if (done_event) CES_HIP(hipEventRecord(done_event, caller_), "request event");
+        if (recorded) recorded->store(1);
         return CES_OK;
     }
     Lane* L = nullptr;
@@ -420,7 +439,12 @@ int Scheduler::add(const ces_request& r, hipEvent_t done_event, long long max_sl
         j.yc = r.q_coarse;
         j.iters = r.iters;
         j.status = r.status;
-        j.done_event = u0 + (uint64_t)cu >= u_end ? done_event : nullptr;
+        const bool last = u0 + (uint64_t)cu >= u_end;
+        j.done_event = last ? done_event : nullptr;
+        j.count = r.count;
+        j.y_host = last ? y_host : nullptr;
+        j.status_host = last ? status_host : nullptr;
+        j.recorded = last ? recorded : nullptr;
         L->jobs.push_back(j);
     }
     return CES_OK;
@@ -456,6 +480,10 @@ int Scheduler::start(Lane& L) {
         CES_HIP(hipEventRecord(L.ev_fork, caller_), "fork");
         CES_HIP(hipStreamWaitEvent(L.sa, L.ev_fork, 0), "fork");
         CES_HIP(hipStreamWaitEvent(L.sb, L.ev_fork, 0), "fork");
+        if (L.p->ws_free) {
+            CES_HIP(hipStreamWaitEvent(L.sa, L.p->ws_free, 0), "workspace");
+            CES_HIP(hipStreamWaitEvent(L.sb, L.p->ws_free, 0), "workspace");
+        }
         L.forked = true;
     }
     const Job& j = L.jobs[L.next];
@@ -480,7 +508,13 @@ int Scheduler::finish(Lane& L) {
                             p->sc ? p->itc.as<int>() : nullptr, (int)(j.lo - s0), (int)(j.hi - j.lo),
                             (long long)(j.lo - j.first), j.y, j.yf, j.yc, j.iters, j.status, L.sa),
             "finalize");
+    if (j.y_host)
+        CES_HIP(hipMemcpyAsync(j.y_host, j.y, (size_t)j.count * 8, hipMemcpyDeviceToHost, L.sa), "copy results");
+    if (j.status_host && j.status)
+        CES_HIP(hipMemcpyAsync(j.status_host, j.status, (size_t)j.count * 4, hipMemcpyDeviceToHost, L.sa),
+                "copy results");
     if (j.done_event) CES_HIP(hipEventRecord(j.done_event, L.sa), "request event");
+    if (j.recorded) j.recorded->store(1);
     ++L.next;
     L.solving = false;
     return CES_OK;
@@ -555,20 +589,25 @@ int Scheduler::join() {
                 if (err == hipSuccess) err = hipStreamWaitEvent(caller_, e, 0);
                 if (err != hipSuccess && rc == CES_OK) rc = hip_fail(err, "join");
             }
+            hipError_t err = mark_workspace_free(L->p, L->sa);
+            if (err != hipSuccess && rc == CES_OK) rc = hip_fail(err, "join");
         }
         L->p->busy.store(0);
     }
     return rc;
 }
 
-void Scheduler::retire(std::vector<ces_plan>* released) {
+int Scheduler::retire(std::vector<ces_plan>* released) {
     std::vector<std::unique_ptr<Lane>> keep;
+    int rc = CES_OK;
     for (auto& L : lanes_) {
         if (L->solving || L->next < L->jobs.size()) {
             keep.push_back(std::move(L));
             continue;
         }
         if (L->forked) {
+            hipError_t err = mark_workspace_free(L->p, L->sa);
+            if (err != hipSuccess && rc == CES_OK) rc = hip_fail(err, "retire");
             // later work on these streams only depends on what is enqueued
             // after it, so they can serve another lane at once
             free_streams_.push_back(L->sa);
@@ -581,6 +620,7 @@ void Scheduler::retire(std::vector<ces_plan>* released) {
         released->push_back(L->p);
     }
     lanes_.swap(keep);
+    return rc;
 }
 
 int Scheduler::pending_solves() const {

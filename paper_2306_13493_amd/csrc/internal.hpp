@@ -1,7 +1,9 @@
 // Host-side interfaces between the translation units of the library.
 #pragma once
 
+#include <atomic>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -162,6 +164,7 @@ hipError_t launch_finalize(const double* qf, const double* qc, const int* itf, c
 
 // ------------------------------------------------------------- profiler
 // Process-wide; records HIP events around launches while enabled.
+// Thread-safe (a server's loop may launch while its owner reads).
 class Profiler {
 public:
     struct Entry {
@@ -171,7 +174,7 @@ public:
         double bytes = 0.0;   // algorithmic bytes summed over launches
     };
     static Profiler& get();
-    bool on() const { return on_; }
+    bool on() const { return on_.load(std::memory_order_relaxed); }
     void enable(bool on);
     int begin(hipStream_t st);   // -1 when off
     void end(int idx, const char* name, double bytes_per_sample, int samples, hipStream_t st);
@@ -185,7 +188,8 @@ private:
         double bps = 0.0;
         int samples = 0;
     };
-    bool on_ = false;
+    std::atomic<bool> on_{false};
+    std::mutex mu_;
     std::vector<Rec> recs_;
     std::vector<hipEvent_t> pool_;
     size_t used_ = 0;

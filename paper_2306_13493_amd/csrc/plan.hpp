@@ -121,6 +121,13 @@ struct ces_plan_s {
     std::unique_ptr<ces::Solver> sf, sc;
     size_t ws_bytes = 0;
     std::atomic<int> busy{0};           // a scheduler is using the workspace
+    // recorded after the last work that used the workspace; the next lane
+    // of this plan waits for it (lanes of successive calls may run on
+    // different streams)
+    hipEvent_t ws_free = nullptr;
+    ~ces_plan_s() {
+        if (ws_free) (void)hipEventDestroy(ws_free);
+    }
 };
 
 namespace ces {
@@ -130,8 +137,10 @@ size_t slot_bytes(const ces_plan p);
 
 // Plan set-up (Algorithm 1 steps 1-3 and the masks of Algorithm 2) with
 // device buffers from `alloc`, device work on stream st (synchronised).
+// keep_eigenvalues = false drops the n*n eigenvalue array once the
+// amplitudes exist (ces_plan_eigenvalues then fails).
 int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* alloc, hipStream_t st,
-                ces_plan* out);
+                ces_plan* out, bool keep_eigenvalues = true);
 int validate_desc(const ces_level_desc* d);
 
 // Allocates the plan's sample workspace on first use (zeroed on stream st).
@@ -163,7 +172,12 @@ public:
     // Queue one request; done_event (may be null) is recorded once all of
     // its results are written.  max_slots > 0 sizes a new workspace for at
     // most that many samples per chunk.
-    int add(const ces_request& r, hipEvent_t done_event, long long max_slots = 0);
+    // y_host / status_host (pinned, may be null): the request's outputs are
+    // also copied there before done_event.  *recorded (may be null) is set
+    // to 1 once done_event has been recorded: an event that was never
+    // recorded counts as complete, so it must not be polled before that.
+    int add(const ces_request& r, hipEvent_t done_event, long long max_slots = 0, double* y_host = nullptr,
+            int32_t* status_host = nullptr, std::atomic<int>* recorded = nullptr);
     // One pass over the lanes; *progressed = some work was enqueued.
     int step(bool* progressed);
     bool idle() const;
@@ -174,7 +188,7 @@ public:
     int join();
     // Drop the lanes whose queued jobs are all enqueued; their plans are
     // appended to *released (no longer used by the scheduler).
-    void retire(std::vector<ces_plan>* released);
+    int retire(std::vector<ces_plan>* released);
     int lanes() const { return (int)lanes_.size(); }
     // solves in progress (for an idle wait of the serving loop)
     int pending_solves() const;
@@ -186,6 +200,11 @@ private:
         double *y, *yf, *yc;
         int32_t *iters, *status;
         hipEvent_t done_event;
+        // last chunk of a request: copies of its outputs to host memory
+        int64_t count;
+        double* y_host;
+        int32_t* status_host;
+        std::atomic<int>* recorded;
     };
     struct Lane {
         ces_plan p = nullptr;

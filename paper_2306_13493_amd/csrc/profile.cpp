@@ -25,6 +25,7 @@ hipEvent_t Profiler::event() {
 
 int Profiler::begin(hipStream_t st) {
     if (!on_) return -1;
+    std::lock_guard<std::mutex> g(mu_);
     Rec r;
     r.a = event();
     r.b = event();
@@ -35,6 +36,7 @@ int Profiler::begin(hipStream_t st) {
 }
 
 void Profiler::end(int idx, const char* name, double bytes_per_sample, int samples, hipStream_t st) {
+    std::lock_guard<std::mutex> g(mu_);
     if (idx < 0 || idx >= (int)recs_.size()) return;
     Rec& r = recs_[idx];
     r.name = name;
@@ -44,16 +46,19 @@ void Profiler::end(int idx, const char* name, double bytes_per_sample, int sampl
 }
 
 void Profiler::set_samples(int idx, int samples) {
+    std::lock_guard<std::mutex> g(mu_);
     if (idx >= 0 && idx < (int)recs_.size()) recs_[idx].samples = samples;
 }
 
 void Profiler::enable(bool on) {
+    std::lock_guard<std::mutex> g(mu_);
     on_ = on;
     recs_.clear();
     used_ = 0;
 }
 
 int Profiler::read(std::vector<Entry>& out) {
+    std::lock_guard<std::mutex> g(mu_);
     out.clear();
     std::map<std::string, Entry> agg;
     for (const Rec& r : recs_) {

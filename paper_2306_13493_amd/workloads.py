@@ -13,6 +13,11 @@ C2  single-level MC, Matern nu=1, lambda=0.1, 257^2 vertices, embedding
 C3  MLMC with smoothing, Matern nu=1/2, lambda=0.03, levels h = 1/16 ..
     1/256 with N = 20000/5000/1200/300/80; level 0 single, levels 1..4
     pairs; tau = n on smoothed fields, the finest fine field unsmoothed.
+C4  served requests: Poisson arrivals (rate 200/s), mesh m uniform on
+    {32, ..., 1024}, count uniform on 1..256, Matern nu uniform on
+    {1/2, 1, 3/2}, lambda uniform on [0.02, 0.3], sigma2=1, pair levels
+    (m, m/2) except single at m=32, tau=0, embedding grown up to 4x, mixed;
+    request r uses seed r+1 and samples 0..count-1.
 C5  large fine level, Matern nu=3/2, sigma2=2, lambda=0.01, 2049^2
     vertices, embedding grown up to 4x, flow cell, outflow QoI, mixed.
 """
@@ -38,6 +43,30 @@ def c3_level(l):
     if l == len(C3_M) - 1:
         return dict(base, level="pair", tau_fine=0, tau_coarse=-1)
     return dict(base, level="pair", tau_fine=-1, tau_coarse=-1)
+
+
+def c4_trace(duration_s=30.0, rate=200.0, seed=0, m_values=(32, 64, 128, 256, 512, 1024)):
+    """Arrival trace of the serving workload: list of dicts with keys t
+    (arrival time, s), w (level descriptor arguments), seed, first, count.
+    Drawn from numpy.random.default_rng(seed)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t > duration_s:
+            break
+        m = int(m_values[int(rng.integers(0, len(m_values)))])
+        count = int(rng.integers(1, 257))
+        nu = (0.5, 1.0, 1.5)[int(rng.integers(0, 3))]
+        lam = float(rng.uniform(0.02, 0.3))
+        r = len(out)
+        w = dict(cov="matern", nu=nu, lam=lam, sigma2=1.0, m=m, level="single" if m == 32 else "pair",
+                 tau_fine=0, tau_coarse=0, psd="grow", max_pad=4, precision="mixed", qoi="integral",
+                 bc="dirichlet0")
+        out.append(dict(t=t, w=w, seed=r + 1, first=0, count=count))
+    return out
 
 
 C5 = dict(cov="matern", nu=1.5, lam=0.01, sigma2=2.0, m=2048, level="single", psd="grow",

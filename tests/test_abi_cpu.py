@@ -72,3 +72,16 @@ def test_batch_entry_points_reject_bad_arguments(lib):
     assert lib.ces_schedule_set(None, None) == -1
     assert lib.ces_autotune(None, reqs, 1, None, None, None) == -1
     assert b"NULL" in lib.ces_last_error()
+
+
+def test_server_entry_points_reject_bad_arguments(lib):
+    from paper_2306_13493_amd import _lib
+    assert ctypes.sizeof(_lib.ServerStats) == 72
+    rid = ctypes.c_int64()
+    st = ctypes.c_int32()
+    assert lib.ces_server_create(None, 0, 0, None) == -1
+    assert lib.ces_server_submit(None, None, 0, 0, 1, None, None, ctypes.byref(rid)) == -1
+    assert lib.ces_server_poll(None, 1, ctypes.byref(st), None) == -1
+    assert lib.ces_server_drain(None) == -1
+    assert lib.ces_server_get_stats(None, None) == -1
+    assert lib.ces_server_destroy(None) == 0
