@@ -652,12 +652,31 @@ __global__ __launch_bounds__(NT) void k_bottom(BottomArgs<T> a) {
     }
 }
 
-// Coarse operators: each coarse edge conductance is the harmonic mean of
-// the two fine edge conductances it spans (the two fine edges in series,
-// 2ab/(a+b)), computed from level 0's nodal k or from a stored level.
+// Coarse operators from the fine edge conductances: along the coarse edge
+// the two fine edges it spans act in series (harmonic mean 2ab/(a+b)); the
+// coarse control volume also covers half of each parallel fine line beside
+// it, so the series means of the three fine lines are averaged with weights
+// 1/2 (the line itself) and 1/4 (each neighbour).  Exact for constant k
+// (also on boundary lines, whose missing neighbour counts as zero where the
+// fine boundary edge has half the interior conductance).  Computed from
+// level 0's nodal k or from a stored level.
 __device__ __forceinline__ double hmean2(double a, double b) {
     const double s = a + b;
     return s > 0.0 ? 2.0 * a * b / s : 0.0;
+}
+
+// E(x, y), N(x, y): fine east / north edge conductances, zero outside the mesh
+template <typename EF>
+__device__ __forceinline__ double coarse_e(int I, int J, const EF& E) {
+    const int x = 2 * I, y = 2 * J;
+    return 0.5 * hmean2(E(x, y), E(x + 1, y)) +
+           0.25 * (hmean2(E(x, y - 1), E(x + 1, y - 1)) + hmean2(E(x, y + 1), E(x + 1, y + 1)));
+}
+template <typename NF>
+__device__ __forceinline__ double coarse_n(int I, int J, const NF& N) {
+    const int x = 2 * I, y = 2 * J;
+    return 0.5 * hmean2(N(x, y), N(x, y + 1)) +
+           0.25 * (hmean2(N(x - 1, y), N(x - 1, y + 1)) + hmean2(N(x + 1, y), N(x + 1, y + 1)));
 }
 
 template <typename T>
@@ -670,8 +689,10 @@ __global__ __launch_bounds__(kBlock) void k_coarsen_k(const T* __restrict__ kf, 
     const T* k = kf + (size_t)s * kfss;
     const int m = F.m, w = F.w;
     auto K = [&](int gx, int gy) -> double { return (double)k[(size_t)gy * w + gx]; };
-    const double e = hmean2(cond_e<double>(2 * I, 2 * J, m, K), cond_e<double>(2 * I + 1, 2 * J, m, K));
-    const double n = hmean2(cond_n<double>(2 * I, 2 * J, m, K), cond_n<double>(2 * I, 2 * J + 1, m, K));
+    auto E = [&](int x, int y) -> double { return cond_e<double>(x, y, m, K); };
+    auto N = [&](int x, int y) -> double { return cond_n<double>(x, y, m, K); };
+    const double e = coarse_e(I, J, E);
+    const double n = coarse_n(I, J, N);
     cec[(size_t)s * C.ss + t] = (T)e;
     cnc[(size_t)s * C.ss + t] = (T)n;
 }
@@ -686,10 +707,14 @@ __global__ __launch_bounds__(kBlock) void k_coarsen_c(const T* __restrict__ cef,
     const T* ce = cef + (size_t)s * F.ss;
     const T* cn = cnf + (size_t)s * F.ss;
     const int m = F.m, w = F.w;
-    auto E = [&](int x, int y) -> double { return (x <= m && y <= m) ? (double)ce[(size_t)y * w + x] : 0.0; };
-    auto N = [&](int x, int y) -> double { return (x <= m && y <= m) ? (double)cn[(size_t)y * w + x] : 0.0; };
-    cec[(size_t)s * C.ss + t] = (T)hmean2(E(2 * I, 2 * J), E(2 * I + 1, 2 * J));
-    cnc[(size_t)s * C.ss + t] = (T)hmean2(N(2 * I, 2 * J), N(2 * I, 2 * J + 1));
+    auto E = [&](int x, int y) -> double {
+        return (x >= 0 && y >= 0 && x <= m && y <= m) ? (double)ce[(size_t)y * w + x] : 0.0;
+    };
+    auto N = [&](int x, int y) -> double {
+        return (x >= 0 && y >= 0 && x <= m && y <= m) ? (double)cn[(size_t)y * w + x] : 0.0;
+    };
+    cec[(size_t)s * C.ss + t] = (T)coarse_e(I, J, E);
+    cnc[(size_t)s * C.ss + t] = (T)coarse_n(I, J, N);
 }
 
 // ------------------------------------------- whole solve of a small mesh
@@ -763,8 +788,10 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
             const int cw = g.w(1), o = g.off[1];
             for (int t = threadIdx.x; t < cw * cw; t += NT) {
                 const int J = t / cw, I = t - J * cw;
-                g.ce[o + t] = (T)hmean2(cond_e<double>(2 * I, 2 * J, m, KD), cond_e<double>(2 * I + 1, 2 * J, m, KD));
-                g.cn[o + t] = (T)hmean2(cond_n<double>(2 * I, 2 * J, m, KD), cond_n<double>(2 * I, 2 * J + 1, m, KD));
+                auto E = [&](int x, int y) -> double { return cond_e<double>(x, y, m, KD); };
+                auto N = [&](int x, int y) -> double { return cond_n<double>(x, y, m, KD); };
+                g.ce[o + t] = (T)coarse_e(I, J, E);
+                g.cn[o + t] = (T)coarse_n(I, J, N);
             }
         }
         __syncthreads();
@@ -772,12 +799,16 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
     for (int l = 2; l < a.nl; ++l) {
         const int fm = g.m(l - 1), fw = g.w(l - 1), fo = g.off[l - 1];
         const int cw = g.w(l), o = g.off[l];
-        auto E = [&](int x, int y) -> double { return (x <= fm && y <= fm) ? (double)g.ce[fo + y * fw + x] : 0.0; };
-        auto N = [&](int x, int y) -> double { return (x <= fm && y <= fm) ? (double)g.cn[fo + y * fw + x] : 0.0; };
+        auto E = [&](int x, int y) -> double {
+            return (x >= 0 && y >= 0 && x <= fm && y <= fm) ? (double)g.ce[fo + y * fw + x] : 0.0;
+        };
+        auto N = [&](int x, int y) -> double {
+            return (x >= 0 && y >= 0 && x <= fm && y <= fm) ? (double)g.cn[fo + y * fw + x] : 0.0;
+        };
         for (int t = threadIdx.x; t < cw * cw; t += NT) {
             const int J = t / cw, I = t - J * cw;
-            g.ce[o + t] = (T)hmean2(E(2 * I, 2 * J), E(2 * I + 1, 2 * J));
-            g.cn[o + t] = (T)hmean2(N(2 * I, 2 * J), N(2 * I, 2 * J + 1));
+            g.ce[o + t] = (T)coarse_e(I, J, E);
+            g.cn[o + t] = (T)coarse_n(I, J, N);
         }
         __syncthreads();
     }
