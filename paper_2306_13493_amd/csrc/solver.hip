@@ -949,8 +949,11 @@ __device__ void load_ktile(KTile<T>& K, const T* __restrict__ k, int x0, int y0,
     }
 }
 
-// init over the full (m+1)^2 grid: x = Dirichlet lifting, r = b - A x
-// at unknowns, all other vectors zero; partial ||r||^2.
+// init over the full (m+1)^2 grid: x = Dirichlet lifting, r = b - A x at
+// unknowns (zero elsewhere); partial ||r||^2.  p, q and z need no reset:
+// off the unknowns (boundary nodes, stride padding) they are zero from the
+// workspace's allocation and never written, z is written before it is
+// read, and the first direction does not read p_old.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs<T> a) {
     __shared__ KTile<T> K;
@@ -984,10 +987,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs<T> a) {
         }
         a.X[o] = xv;
         a.R[o] = rv;
-        a.Pold[o] = 0.0;
-        a.Pnew[o] = 0.0;
-        a.Q[o] = 0.0;
-        a.Z[o] = T(0);
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
@@ -1037,7 +1036,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
         const int gx = x0 - 1 + x, gy = y0 - 1 + y;
         const bool in = gx >= 0 && gx <= m && gy >= 0 && gy <= m;
         K[t] = in ? kv[i] : 0.0;
-        P[t] = is_unknown(gx, gy, m, bc) ? zv[i] + beta * pv[i] : 0.0;
+        P[t] = is_unknown(gx, gy, m, bc) ? (first ? zv[i] : zv[i] + beta * pv[i]) : 0.0;
     }
     __syncthreads();
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1085,46 +1084,53 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
     if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
 }
 
-// x += alpha p; r -= alpha q; partial ||r||^2
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(PcgArgs<T> a) {
-    constexpr int NR = PTY / (kBlock / 64);
+// x += alpha p; r -= alpha q; partial ||r||^2.  Elementwise over each
+// sample's whole padded node range, two nodes per lane per access (16 bytes):
+// off the unknowns p, q and r are zero (x keeps its boundary values), so no
+// masks are needed.  Every access is non-temporal: a chunk's vectors are far
+// larger than the caches and are next read by another kernel, so caching
+// them only evicts useful lines.  Block b of a sample covers nodes
+// [b * kUpdChunk, (b+1) * kUpdChunk); its partial sum goes to part[b].
+constexpr int kUpdChunk = 4 * 2 * kBlock;   // nodes per workgroup
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(kBlock) void k_pcg_update(double* __restrict__ X, double* __restrict__ R,
+                                                       const double* __restrict__ P, const double* __restrict__ Q,
+                                                       long long ss, int nb, double* __restrict__ part,
+                                                       const Scal* __restrict__ scal) {
     __shared__ double red[kBlock / 64];
-    const int wi = xcd_remap(blockIdx.x, gridDim.x);
-    const int s = wi / a.ntiles, tile = wi - s * a.ntiles;
-    const Scal sc = a.scal[s];
+    const int s = blockIdx.y, b = blockIdx.x;
+    const Scal sc = scal[s];
     if (!sc.active) return;
     const double alpha = sc.rz / sc.pq;
-    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
-    const int x0 = 1 + tx * PTX, y0 = a.L.ylo + ty * PTY;
-    const int m = a.L.m, w = a.L.w;
-    const size_t base = (size_t)s * a.L.ss;
-    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int gx = x0 + l, gxc = min(gx, m);
-    double xv[NR], pv[NR], rv[NR], qv[NR];
+    const size_t base = (size_t)s * ss;
+    constexpr int V = kUpdChunk / (2 * kBlock);
+    dvec2 xv[V], rv[V], pv[V], qv[V];
+    long long o[V];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const size_t o = base + (size_t)min(y0 + NR * wv + r, m) * w + gxc;
-        xv[r] = a.X[o];
-        pv[r] = a.Pnew[o];
-        rv[r] = a.R[o];
-        qv[r] = a.Q[o];
+    for (int i = 0; i < V; ++i) {
+        o[i] = (long long)b * kUpdChunk + 2LL * (i * kBlock + threadIdx.x);
+        const long long oc = o[i] < ss ? o[i] : 0;   // ss is even: pairs never straddle the end
+        xv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(X + base + oc));
+        rv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(R + base + oc));
+        pv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(P + base + oc));
+        qv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(Q + base + oc));
     }
     double acc = 0.0;
-    const bool unkc = gx <= m - 1;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int gy = y0 + NR * wv + r;
-        if (unkc && gy <= a.L.yhi) {
-            const size_t o = base + (size_t)gy * w + gx;
-            a.X[o] = xv[r] + alpha * pv[r];
-            const double rn = rv[r] - alpha * qv[r];
-            a.R[o] = rn;
-            acc += rn * rn;
-        }
+    for (int i = 0; i < V; ++i) {
+        if (o[i] >= ss) continue;
+        dvec2 xn, rn;
+        xn.x = xv[i].x + alpha * pv[i].x;
+        xn.y = xv[i].y + alpha * pv[i].y;
+        rn.x = rv[i].x - alpha * qv[i].x;
+        rn.y = rv[i].y - alpha * qv[i].y;
+        __builtin_nontemporal_store(xn, reinterpret_cast<dvec2*>(X + base + o[i]));
+        __builtin_nontemporal_store(rn, reinterpret_cast<dvec2*>(R + base + o[i]));
+        acc += rn.x * rn.x + rn.y * rn.y;
     }
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
+    if (threadIdx.x == 0) part[(size_t)s * nb + b] = acc;
 }
 
 enum { RED_BB = 0, RED_RZ = 1, RED_PQ = 2, RED_RR = 3 };
@@ -1309,7 +1315,8 @@ public:
         stx_ = cdiv(L0.m - 1, POST_TX);
         sty_ = cdiv(L0.yhi - L0.ylo + 1, POST_TY);
         rz_parts_ = stx_ * sty_;
-        max_parts_ = std::max(std::max(ptiles_, itiles_), rz_parts_);
+        ublocks_ = (int)cdiv(L0.ss, kUpdChunk);
+        max_parts_ = std::max(std::max(std::max(ptiles_, itiles_), rz_parts_), ublocks_);
         o_X_ = take(n0 * 8); o_R_ = take(n0 * 8); o_P0_ = take(n0 * 8); o_P1_ = take(n0 * 8);
         o_Q_ = take(n0 * 8); o_Z_ = take(n0 * sizeof(T));
         o_za0_ = take(n0 * sizeof(T));
@@ -1525,9 +1532,10 @@ private:
         });
         hipLaunchKernelGGL(k_reduce<RED_PQ>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
         launch("pcg_update", nu(0) * 48.0, S, it, st, [&] {
-            hipLaunchKernelGGL(k_pcg_update<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL(k_pcg_update, dim3(ublocks_, S), dim3(kBlock), 0, st, a.X, a.R, a.Pnew, a.Q,
+                               lv_[0].ss, ublocks_, part, scal);
         });
-        hipLaunchKernelGGL(k_reduce<RED_RR>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
+        hipLaunchKernelGGL(k_reduce<RED_RR>, dim3(S), dim3(kBlock), 0, st, part, part, ublocks_, scal, rtol2, cfg_.maxit, cnt);
         if (Profiler::get().on())
             hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, ptr<int>(o_hist_) + it + 1);
         return hipGetLastError();
@@ -1640,7 +1648,7 @@ private:
     int nlev_ = 0, lb_ = 0;
     bool small_ = false;
     int ptx_ = 0, pty_ = 0, ptiles_ = 0, itx_ = 0, ity_ = 0, itiles_ = 0, stx_ = 0, sty_ = 0;
-    int rz_parts_ = 0, max_parts_ = 0;
+    int rz_parts_ = 0, ublocks_ = 0, max_parts_ = 0;
     size_t o_X_ = 0, o_R_ = 0, o_P0_ = 0, o_P1_ = 0, o_Q_ = 0, o_Z_ = 0, o_za0_ = 0;
     std::vector<size_t> o_ce_, o_cn_, o_rhs_, o_za_, o_zb_;
     size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0, o_hist_ = 0;
