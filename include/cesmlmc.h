@@ -173,11 +173,16 @@ typedef struct {
  *                  convergence read-back, 1..4 (default 2)
  *   max_lanes      plans worked on concurrently, 0 = all (default 0)
  *   chunk_samples  samples per solver launch, 0 = the plan's workspace
- *                  capacity (default 0) */
+ *                  capacity (default 0)
+ *   graphs         1: each CG iteration of a tiled solve is replayed from a
+ *                  captured HIP graph (one launch instead of about twelve);
+ *                  0: launched kernel by kernel (default 0) */
 typedef struct {
     int32_t depth;
     int32_t max_lanes;
     int64_t chunk_samples;
+    int32_t graphs;
+    int32_t reserved;
 } ces_schedule;
 
 /* Samples of every request, in one scheduled pass (the levels of an MLMC

@@ -93,14 +93,15 @@ class Context:
 
     @property
     def schedule(self):
-        """(depth, max_lanes, chunk_samples) of ces_sample / ces_sample_batch."""
+        """(depth, max_lanes, chunk_samples, graphs) of ces_sample / ces_sample_batch."""
         s = Schedule()
         check(self.lib.ces_schedule_get(self.handle, ctypes.byref(s)))
-        return (s.depth, s.max_lanes, s.chunk_samples)
+        return (s.depth, s.max_lanes, s.chunk_samples, s.graphs)
 
     @schedule.setter
     def schedule(self, v):
-        s = Schedule(int(v[0]), int(v[1]), int(v[2]))
+        v = tuple(v) + (0,) * (4 - len(v))
+        s = Schedule(int(v[0]), int(v[1]), int(v[2]), int(v[3]), 0)
         check(self.lib.ces_schedule_set(self.handle, ctypes.byref(s)))
 
     def _requests(self, reqs, outs):
@@ -133,13 +134,13 @@ class Context:
         return res
 
     def autotune(self, reqs, stream=None, outs=None):
-        """ces_autotune over the requests: ((depth, max_lanes, chunk), best_ms, outputs)."""
+        """ces_autotune over the requests: ((depth, max_lanes, chunk, graphs), best_ms, outputs)."""
         arr, res = self._requests(reqs, outs)
         s = Schedule()
         ms = ctypes.c_double()
         check(self.lib.ces_autotune(self.handle, arr, len(reqs), _stream_ptr(stream), ctypes.byref(s),
                                     ctypes.byref(ms)))
-        return (s.depth, s.max_lanes, s.chunk_samples), ms.value, res
+        return (s.depth, s.max_lanes, s.chunk_samples, s.graphs), ms.value, res
 
     def close(self):
         if self.handle:

@@ -52,7 +52,8 @@ class Request(ctypes.Structure):
 
 
 class Schedule(ctypes.Structure):
-    _fields_ = [("depth", c_int32), ("max_lanes", c_int32), ("chunk_samples", c_int64)]
+    _fields_ = [("depth", c_int32), ("max_lanes", c_int32), ("chunk_samples", c_int64), ("graphs", c_int32),
+                ("reserved", c_int32)]
 
 
 class ServerStats(ctypes.Structure):

@@ -536,8 +536,9 @@ int Scheduler::step(bool* progressed) {
             continue;
         }
         bool pf = false, pc = false;
-        if (!L.fdone) CES_HIP(L.p->sf->advance(L.sa, s_.depth, &L.fdone, &pf), "fine solve");
-        if (L.p->sc && !L.cdone) CES_HIP(L.p->sc->advance(L.sb, s_.depth, &L.cdone, &pc), "coarse solve");
+        const bool g = s_.graphs != 0;
+        if (!L.fdone) CES_HIP(L.p->sf->advance(L.sa, s_.depth, g, &L.fdone, &pf), "fine solve");
+        if (L.p->sc && !L.cdone) CES_HIP(L.p->sc->advance(L.sb, s_.depth, g, &L.cdone, &pc), "coarse solve");
         if (pf || pc) *progressed = true;
         if (L.fdone && (L.cdone || !L.p->sc)) {
             int rc = finish(L);
@@ -685,6 +686,7 @@ int ces_schedule_get(ces_context ctx, ces_schedule* out) {
 int ces_schedule_set(ces_context ctx, const ces_schedule* s) {
     if (!ctx || !s) return fail(CES_ERR_ARG, "context or schedule is NULL");
     if (s->depth < 0 || s->depth > 4) return fail(CES_ERR_ARG, "depth must be in 0..4");
+    if (s->graphs != 0 && s->graphs != 1) return fail(CES_ERR_ARG, "graphs must be 0 or 1");
     if (s->max_lanes < 0 || s->chunk_samples < 0) return fail(CES_ERR_ARG, "max_lanes / chunk_samples < 0");
     ctx->sched = *s;
     if (ctx->sched.depth == 0) ctx->sched.depth = 2;
@@ -751,6 +753,11 @@ int ces_autotune(ces_context ctx, const ces_request* reqs, int32_t nreq, void* s
             c.chunk_samples = ch;
             if ((rc = consider(c)) != CES_OK) return rc;
         }
+    {
+        ces_schedule c = best;
+        c.graphs = best.graphs ? 0 : 1;
+        if ((rc = consider(c)) != CES_OK) return rc;
+    }
     ctx->sched = best;
     if (chosen) *chosen = best;
     if (best_ms) *best_ms = tbest;

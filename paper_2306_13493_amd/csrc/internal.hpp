@@ -128,8 +128,10 @@ public:
     // [0, S) are solved.
     virtual hipError_t begin(const void* k, long long kstride, int S, hipStream_t st) = 0;
     // depth: iterations allowed in flight before their convergence count
-    // has been read back (1..4).  *progressed: an iteration was enqueued.
-    virtual hipError_t advance(hipStream_t st, int depth, bool* done, bool* progressed) = 0;
+    // has been read back (1..4).  graphs: replay iterations from captured
+    // HIP graphs (same kernels and arguments).  *progressed: an iteration
+    // was enqueued.
+    virtual hipError_t advance(hipStream_t st, int depth, bool graphs, bool* done, bool* progressed) = 0;
     // block until the oldest unconfirmed iteration has finished
     virtual hipError_t wait() = 0;
     // bookkeeping after the solve (launch profiler only; may synchronise)
@@ -139,7 +141,7 @@ public:
         hipError_t e = begin(k, kstride, S, st);
         bool done = false, prog = false;
         while (e == hipSuccess && !done) {
-            e = advance(st, depth, &done, &prog);
+            e = advance(st, depth, false, &done, &prog);
             if (e == hipSuccess && !done && !prog) e = wait();
         }
         return e == hipSuccess ? finish(st) : e;

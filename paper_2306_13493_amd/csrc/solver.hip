@@ -1338,6 +1338,10 @@ public:
         bytes_ = off;
     }
     ~SolverImpl() override {
+        for (auto& G : graphs_)
+            for (auto& x : G.exec)
+                if (x) (void)hipGraphExecDestroy(x);
+        if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
         if (base_) alloc_->release(base_);
         if (hcnt_) pinned_slot_release(hcnt_);
         for (auto& e : ev_)
@@ -1436,7 +1440,7 @@ public:
         return hipGetLastError();
     }
 
-    hipError_t advance(hipStream_t st, int depth, bool* done, bool* progressed) override {
+    hipError_t advance(hipStream_t st, int depth, bool graphs, bool* done, bool* progressed) override {
         *progressed = false;
         depth = std::max(1, std::min(depth, RING));
         // confirm finished iterations in order: the active-sample count
@@ -1454,7 +1458,14 @@ public:
         }
         if (!done_ && confirmed_ == it_next_ && it_next_ >= cfg_.maxit) done_ = true;
         if (!done_ && it_next_ < cfg_.maxit && it_next_ - confirmed_ < depth) {
-            hipError_t e = iteration(it_next_, st);
+            hipError_t e;
+            if (graphs && it_next_ >= 1 && !Profiler::get().on()) {
+                hipGraphExec_t g = nullptr;
+                e = iteration_graph(it_next_ & 1, &g);
+                if (e == hipSuccess) e = hipGraphLaunch(g, st);
+            } else {
+                e = iteration(it_next_, st);
+            }
             if (e != hipSuccess) return e;
             const int slot = it_next_ % RING;
             if ((e = hipMemcpyAsync(&hcnt_[slot], ptr<int>(o_cnt_), sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
@@ -1539,6 +1550,41 @@ private:
         if (Profiler::get().on())
             hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, ptr<int>(o_hist_) + it + 1);
         return hipGetLastError();
+    }
+
+    // Executable graph of one iteration (it >= 1) of a solve of S_ samples
+    // with coefficients at k0_: the kernels of iteration(it, .) depend on it
+    // only through its parity (which direction buffer is old).  Captured on
+    // a private stream on first use; two batch sizes are kept (a plan's full
+    // chunks and its last one).
+    hipError_t iteration_graph(int parity, hipGraphExec_t* out) {
+        ItGraph* G = nullptr;
+        for (auto& g : graphs_)
+            if (g.S == S_ && g.k == k0_) G = &g;
+        if (!G) {
+            G = &graphs_[graph_victim_];
+            graph_victim_ ^= 1;
+            for (auto& x : G->exec)
+                if (x) (void)hipGraphExecDestroy(x);
+            G->exec[0] = G->exec[1] = nullptr;
+            G->S = S_;
+            G->k = k0_;
+        }
+        if (!G->exec[parity]) {
+            hipError_t e = hipSuccess;
+            if (!cap_stream_) e = hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+            if ((e = hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+            const hipError_t ei = iteration(parity == 0 ? 2 : 1, cap_stream_);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(cap_stream_, &g);
+            if (ei != hipSuccess) e = ei;
+            if (e == hipSuccess) e = hipGraphInstantiate(&G->exec[parity], g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return e;
+        }
+        *out = G->exec[parity];
+        return hipSuccess;
     }
 
     PcgArgs<T> pcg_args(int it) {
@@ -1658,6 +1704,14 @@ private:
     void* base_ = nullptr;
     int* hcnt_ = nullptr;
     hipEvent_t ev_[RING] = {nullptr, nullptr, nullptr, nullptr};
+    struct ItGraph {
+        int S = -1;
+        const T* k = nullptr;
+        hipGraphExec_t exec[2] = {nullptr, nullptr};
+    };
+    ItGraph graphs_[2];
+    int graph_victim_ = 0;
+    hipStream_t cap_stream_ = nullptr;
     // state of the solve in progress
     const T* k0_ = nullptr;
     long long kss_ = 0;

@@ -65,7 +65,7 @@ def test_argument_errors_without_device(lib):
 def test_batch_entry_points_reject_bad_arguments(lib):
     from paper_2306_13493_amd import _lib
     assert ctypes.sizeof(_lib.Request) == 72
-    assert ctypes.sizeof(_lib.Schedule) == 16
+    assert ctypes.sizeof(_lib.Schedule) == 24
     reqs = (_lib.Request * 1)()
     assert lib.ces_sample_batch(None, reqs, 1, None) == -1
     assert lib.ces_schedule_get(None, None) == -1

@@ -87,15 +87,19 @@ def test_mixed_requests_same_plan_and_zero_count(ctx, c3_plans):
     assert np.array_equal(y.view(np.uint64), bits(whole["y"]))
 
 
-@pytest.mark.parametrize("sched", [(1, 0, 0), (3, 1, 0), (4, 2, 64), (2, 0, 30)])
+@pytest.mark.parametrize("sched", [(1, 0, 0, 0), (3, 1, 0, 0), (4, 2, 64, 0), (2, 0, 30, 0),
+                                   (2, 0, 0, 1), (3, 0, 45, 1), (1, 1, 0, 1)])
 def test_schedules_do_not_change_results(ctx, c3_plans, sched):
+    # graphs = 1 replays captured iterations many times per solve and across
+    # chunks of different sizes (45, 45, 30 at level 2), with eager work in
+    # between; every replay must match the eagerly launched iterations
     reqs = [(p, 0, 0, c) for p, c in zip(c3_plans, C3_SMALL_N)]
     ref = ctx.sample_batch(reqs)
     torch.cuda.synchronize()
     old = ctx.schedule
     try:
         ctx.schedule = sched
-        assert ctx.schedule[:2] == sched[:2]
+        assert ctx.schedule[:2] == sched[:2] and ctx.schedule[3] == sched[3]
         got = ctx.sample_batch(reqs)
         torch.cuda.synchronize()
     finally:
@@ -110,10 +114,10 @@ def test_autotune_picks_valid_schedule(ctx, c3_plans):
     torch.cuda.synchronize()
     old = ctx.schedule
     try:
-        (depth, lanes, chunk), ms, outs = ctx.autotune(reqs)
+        (depth, lanes, chunk, graphs), ms, outs = ctx.autotune(reqs)
         torch.cuda.synchronize()
-        assert 1 <= depth <= 4 and lanes >= 0 and chunk >= 0 and ms > 0
-        assert ctx.schedule == (depth, lanes, chunk)
+        assert 1 <= depth <= 4 and lanes >= 0 and chunk >= 0 and graphs in (0, 1) and ms > 0
+        assert ctx.schedule == (depth, lanes, chunk, graphs)
     finally:
         ctx.schedule = old
     for a, b in zip(ref, outs):
