@@ -208,6 +208,70 @@ int ces_schedule_set(ces_context ctx, const ces_schedule* sched);
 int ces_autotune(ces_context ctx, const ces_request* reqs, int32_t nreq, void* hip_stream,
                  ces_schedule* chosen, double* best_ms);
 
+/* ---- adaptive MLMC estimator on top of the sampler -------------------- */
+
+/* Options of ces_mlmc_run.  Initialise with ces_mlmc_opts_default(). */
+typedef struct {
+    int32_t struct_size;   /* sizeof(ces_mlmc_opts) */
+    double eps;            /* target root mean squared error */
+    int32_t l_start;       /* levels 0..l_start are used from the start (>= 0) */
+    int32_t reserved0;
+    int64_t n_pilot;       /* first samples of a level newly added (>= 2) */
+    double theta;          /* share of eps^2 for the estimator variance; the
+                              paper's sample-size rule uses 1/2 */
+    double alpha;          /* weak order for the bias estimate; <= 0: fitted */
+    int32_t cost_model;    /* 0: cost of a level sample = unknowns of its
+                              meshes; 1: measured device time per sample */
+    int32_t max_rounds;    /* bound on sampling rounds */
+    uint64_t seed;
+} ces_mlmc_opts;
+
+#define CES_MLMC_MAX_LEVELS 16
+
+typedef struct {
+    double estimate;       /* sum over levels of the sample mean of Y_l */
+    double variance;       /* sum of V_l / N_l (estimator variance) */
+    double bias;           /* |E[Y_L]| / (2^alpha - 1) (Richardson) */
+    double alpha, beta, gamma;  /* fitted rates of |E[Y_l]|, V_l, C_l in h_l */
+    int32_t levels;        /* L + 1 */
+    int32_t converged;     /* 1: variance <= theta eps^2 and bias^2 <= (1-theta) eps^2 */
+    int32_t rounds;
+    int32_t reserved;
+    int64_t n[CES_MLMC_MAX_LEVELS];      /* samples per level */
+    double mean[CES_MLMC_MAX_LEVELS];    /* sample mean of Y_l */
+    double var[CES_MLMC_MAX_LEVELS];     /* sample variance of Y_l */
+    double cost[CES_MLMC_MAX_LEVELS];    /* cost per sample (model or seconds) */
+} ces_mlmc_result;
+
+void ces_mlmc_opts_default(ces_mlmc_opts* o);
+
+/* Adaptive MLMC (Section 3.3, eq. (mlmc-estimator); smoothed form eq.
+ * (mlmc-estimator-smoothed)).  levels[l] is the plan of level l: level 0 a
+ * SINGLE plan on mesh h_0, level l >= 1 a PAIR plan on mesh h_0 / 2^l (its
+ * coarse mesh is level l-1's).  finest (may be NULL) gives, per level, the
+ * plan to use while that level is the finest one (the smoothed estimator
+ * keeps the finest fine field unsmoothed); when a level stops being the
+ * finest its samples are discarded and it is sampled again with
+ * levels[l].  Each round samples, for every level in use,
+ * the missing samples (sample indices continue per level, seed opts.seed)
+ * in one ces_sample_batch call, updates the level means and variances, and
+ * sets N_l = ceil(eps^-2 / theta * sqrt(V_l / C_l) * sum_k sqrt(V_k C_k))
+ * (eq. (optimal-nl) with theta = 1/2).  When no level needs samples, the
+ * bias |E[Q_h - Q]| is estimated by Richardson extrapolation with
+ * extrapolant Q_2h, |E[Y_L]| / (2^alpha - 1) (Section 4); if its square
+ * exceeds (1 - theta) eps^2 the next level is added (up to nlevels), else
+ * the run has converged.  alpha, beta, gamma are least-squares slopes of
+ * log2 |mean_l|, log2 V_l, log2 C_l against l over levels 1..L.
+ * Synchronous; hip_stream orders the sampling. */
+int ces_mlmc_run(ces_context ctx, const ces_plan* levels, const ces_plan* finest, int32_t nlevels,
+                 const ces_mlmc_opts* opts, void* hip_stream, ces_mlmc_result* out);
+
+/* Coarsest mesh rule of Section 3.5, eq. (mlmc-h0-bound-matern-covariance)
+ * and eq. (mlmc-h0-bound-exp-covariance): the largest h_0 = 2^-k with
+ * h_0 <= sqrt(8 nu) lambda (Matern) or h_0 <= lambda (separable
+ * exponential); returns m_0 = 1/h_0 in *m0. */
+int ces_mlmc_coarsest_mesh(const ces_level_desc* desc, int32_t* m0);
+
 /* ---- serving: continuous batching with memory admission -------------- */
 
 /* A server owns a host thread that plans, admits and runs requests as they

@@ -28,8 +28,10 @@ fem         P1 finite elements with nodal quadrature, boundary
             conditions, direct solve (Section 3.1-3.2)
 qoi         quantities of interest (Sections 3.1 and 4)
 sampler     one MLMC level sample Y = Q_f - Q_c (Sections 3.4-3.5)
+mlmc        adaptive MLMC estimator over level samples (Sections 3.3,
+            3.5, 4)
 
 Parity status per function is listed in each module header.
 """
 
-from . import covariance, embedding, normals, field, fem, qoi, sampler  # noqa: F401
+from . import covariance, embedding, normals, field, fem, qoi, sampler, mlmc  # noqa: F401

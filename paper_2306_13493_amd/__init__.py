@@ -15,7 +15,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import CesError, LevelDesc, PlanInfo, Request, Schedule, ServerStats, check, load
+from ._lib import CesError, LevelDesc, MlmcOpts, MlmcResult, PlanInfo, Request, Schedule, ServerStats, check, load
 
 COV = {"matern": 0, "sepexp": 1}
 LEVEL = {"single": 0, "pair": 1}
@@ -302,6 +302,34 @@ class Server:
             pass
 
 
+def mlmc_run(ctx, levels, finest=None, eps=1e-3, l_start=2, n_pilot=100, theta=0.5, alpha=0.0, cost_model=0,
+             max_rounds=50, seed=0, stream=None):
+    """ces_mlmc_run: adaptive MLMC over the given level plans (level 0
+    single, levels >= 1 pairs); returns a dict of the result fields."""
+    lib = load()
+    o = MlmcOpts()
+    lib.ces_mlmc_opts_default(ctypes.byref(o))
+    o.eps, o.l_start, o.n_pilot, o.theta = float(eps), int(l_start), int(n_pilot), float(theta)
+    o.alpha, o.cost_model, o.max_rounds, o.seed = float(alpha), int(cost_model), int(max_rounds), int(seed)
+    n = len(levels)
+    lv = (ctypes.c_void_p * n)(*[p.handle.value for p in levels])
+    fv = None if finest is None else (ctypes.c_void_p * n)(*[p.handle.value for p in finest])
+    r = MlmcResult()
+    check(lib.ces_mlmc_run(ctx.handle, lv, fv, n, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(r)))
+    L = r.levels
+    return {"estimate": r.estimate, "variance": r.variance, "bias": r.bias, "alpha": r.alpha, "beta": r.beta,
+            "gamma": r.gamma, "levels": L, "converged": bool(r.converged), "rounds": r.rounds,
+            "n": [r.n[i] for i in range(L)], "mean": [r.mean[i] for i in range(L)],
+            "var": [r.var[i] for i in range(L)], "cost": [r.cost[i] for i in range(L)]}
+
+
+def coarsest_mesh(desc):
+    """ces_mlmc_coarsest_mesh: m_0 of the coarsest-mesh rule for a descriptor."""
+    m0 = ctypes.c_int32()
+    check(load().ces_mlmc_coarsest_mesh(ctypes.byref(desc), ctypes.byref(m0)))
+    return m0.value
+
+
 def normals(seed, q, stream_tag, first_e, count, device=0, stream=None):
     """(count, 2) float64 device tensor of Box-Muller pairs (parity hook)."""
     torch = _torch()
@@ -327,5 +355,5 @@ def profile_read(max_entries=64):
             for i in range(min(n.value, max_entries))}
 
 
-__all__ = ["Context", "Plan", "Server", "level_desc", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc",
+__all__ = ["Context", "Plan", "Server", "level_desc", "mlmc_run", "coarsest_mesh", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc",
            "PlanInfo", "Request", "Schedule", "load"]

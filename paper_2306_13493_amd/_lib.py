@@ -62,6 +62,23 @@ class ServerStats(ctypes.Structure):
                 ("mem_peak", c_size_t), ("plans_cached", c_int32), ("reserved", c_int32)]
 
 
+MLMC_MAX_LEVELS = 16
+
+
+class MlmcOpts(ctypes.Structure):
+    _fields_ = [("struct_size", c_int32), ("eps", c_double), ("l_start", c_int32), ("reserved0", c_int32),
+                ("n_pilot", c_int64), ("theta", c_double), ("alpha", c_double), ("cost_model", c_int32),
+                ("max_rounds", c_int32), ("seed", c_uint64)]
+
+
+class MlmcResult(ctypes.Structure):
+    _fields_ = [("estimate", c_double), ("variance", c_double), ("bias", c_double), ("alpha", c_double),
+                ("beta", c_double), ("gamma", c_double), ("levels", c_int32), ("converged", c_int32),
+                ("rounds", c_int32), ("reserved", c_int32), ("n", c_int64 * MLMC_MAX_LEVELS),
+                ("mean", c_double * MLMC_MAX_LEVELS), ("var", c_double * MLMC_MAX_LEVELS),
+                ("cost", c_double * MLMC_MAX_LEVELS)]
+
+
 # name -> (restype, argtypes); every function declared in include/cesmlmc.h
 SIGNATURES = {
     "ces_level_desc_default": (None, [ctypes.POINTER(LevelDesc)]),
@@ -84,6 +101,10 @@ SIGNATURES = {
     "ces_server_drain": (c_int32, [c_void_p]),
     "ces_server_get_stats": (c_int32, [c_void_p, ctypes.POINTER(ServerStats)]),
     "ces_server_destroy": (c_int32, [c_void_p]),
+    "ces_mlmc_opts_default": (None, [ctypes.POINTER(MlmcOpts)]),
+    "ces_mlmc_run": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int32,
+                               ctypes.POINTER(MlmcOpts), c_void_p, ctypes.POINTER(MlmcResult)]),
+    "ces_mlmc_coarsest_mesh": (c_int32, [ctypes.POINTER(LevelDesc), ctypes.POINTER(c_int32)]),
     "ces_normals": (c_int32, [c_uint64, c_uint64, c_uint32, c_uint64, c_int64, c_dptr, c_void_p]),
     "ces_plan_eigenvalues": (c_int32, [c_void_p, c_void_p]),
     "ces_plan_mask": (c_int32, [c_void_p, c_void_p, c_void_p]),

@@ -85,3 +85,17 @@ def test_server_entry_points_reject_bad_arguments(lib):
     assert lib.ces_server_drain(None) == -1
     assert lib.ces_server_get_stats(None, None) == -1
     assert lib.ces_server_destroy(None) == 0
+
+
+def test_mlmc_entry_points(lib):
+    from paper_2306_13493_amd import _lib
+    o = _lib.MlmcOpts()
+    lib.ces_mlmc_opts_default(ctypes.byref(o))
+    assert o.struct_size == ctypes.sizeof(_lib.MlmcOpts) and o.theta == 0.5 and o.n_pilot >= 2
+    r = _lib.MlmcResult()
+    assert lib.ces_mlmc_run(None, None, None, 1, ctypes.byref(o), None, ctypes.byref(r)) == -1
+    d = _lib.LevelDesc()
+    lib.ces_level_desc_default(ctypes.byref(d))
+    d.nu, d.lambda_ = 0.5, 0.03
+    m0 = ctypes.c_int32()
+    assert lib.ces_mlmc_coarsest_mesh(ctypes.byref(d), ctypes.byref(m0)) == 0 and m0.value == 32

@@ -1,0 +1,93 @@
+"""GPU tests of the adaptive MLMC estimator (ces_mlmc_run) against the
+oracle's estimator (oracle/mlmc.py) run on the oracle's level samples.
+
+Bar: the same decisions (levels used, samples per level) and estimates
+equal to the level-sample bar (1e-6 relative for mixed precision); runs
+are deterministic bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import mlmc as omlmc
+from oracle import sampler as osm
+from paper_2306_13493_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ces():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_13493_amd as ces
+    ces.load()
+    return ces
+
+
+@pytest.fixture(scope="module")
+def ctx(ces):
+    return ces.Context(0)
+
+
+def level_desc(l, m0, smoothed, finest=False, **kw):
+    m = m0 * 2 ** l
+    w = dict(cov="matern", nu=0.5, lam=0.1, m=m, level="single" if l == 0 else "pair", stream=l, **kw)
+    if smoothed:
+        w["tau_coarse"] = -1
+        w["tau_fine"] = 0 if finest else -1
+    return w
+
+
+def oracle_run(descs, finest_descs, seed, **opts):
+    plans = [osm.Plan(W.to_oracle(d)) for d in descs]
+    fplans = [osm.Plan(W.to_oracle(d)) for d in finest_descs] if finest_descs else None
+
+    def sample(l, finest, first, count):
+        p = fplans[l] if finest else plans[l]
+        return [p.sample(seed, first + t)[0] for t in range(count)]
+
+    cost = [omlmc.unknowns(d["m"]) + (omlmc.unknowns(d["m"] // 2) if l > 0 else 0) for l, d in enumerate(descs)]
+    return omlmc.run(sample, cost, len(descs), finest_differs=fplans is not None, **opts)
+
+
+@pytest.mark.parametrize("smoothed", [False, True])
+def test_estimator_matches_oracle(ctx, ces, smoothed):
+    n = 4
+    descs = [level_desc(l, 8, smoothed) for l in range(n)]
+    fdescs = [level_desc(l, 8, smoothed, finest=True) for l in range(n)] if smoothed else None
+    opts = dict(eps=2e-3, l_start=1, n_pilot=40, theta=0.5, max_rounds=20)
+    plans = [ctx.plan(ces.level_desc(**d)) for d in descs]
+    fplans = [ctx.plan(ces.level_desc(**d)) for d in fdescs] if smoothed else None
+    g = ces.mlmc_run(ctx, plans, finest=fplans, seed=7, **opts)
+    o = oracle_run(descs, fdescs, 7, **opts)
+    assert g["levels"] == o["levels"] and g["converged"] == o["converged"]
+    assert g["n"] == o["n"]
+    for a, b in zip(g["mean"], o["mean"]):
+        assert abs(a - b) <= 1e-6 * max(abs(b), 1e-4)
+    assert abs(g["estimate"] - o["estimate"]) <= 1e-6 * abs(o["estimate"])
+    assert abs(g["variance"] - o["variance"]) <= 1e-5 * o["variance"]
+
+
+def test_estimator_is_deterministic_and_meets_its_budget(ctx, ces):
+    # C3's levels (m = 16 .. 256, smoothed below the finest) at a loose eps
+    descs = [W.c3_level(l) for l in range(5)]
+    levels = [ctx.plan(ces.level_desc(**dict(d, tau_fine=-1, tau_coarse=-1) if l > 0 else d))
+              for l, d in enumerate(descs)]
+    finest = [ctx.plan(ces.level_desc(**dict(d, tau_fine=0, tau_coarse=-1))) if l > 0 else levels[0]
+              for l, d in enumerate(descs)]
+    r1 = ces.mlmc_run(ctx, levels, finest=finest, eps=1e-3, l_start=1, n_pilot=64, seed=3)
+    r2 = ces.mlmc_run(ctx, levels, finest=finest, eps=1e-3, l_start=1, n_pilot=64, seed=3)
+    assert r1 == r2
+    assert r1["variance"] <= 0.5 * 1e-6 * (1 + 1e-9)
+    if r1["converged"]:
+        assert r1["bias"] ** 2 <= 0.5 * 1e-6
+    assert r1["gamma"] == pytest.approx(2.0, abs=0.1)   # unknowns grow like h^-2
+
+
+def test_coarsest_mesh_rule(ces):
+    for w in (dict(cov="matern", nu=0.5, lam=0.03), dict(cov="sepexp", lam=0.1),
+              dict(cov="matern", nu=1.5, lam=0.1)):
+        assert ces.coarsest_mesh(ces.level_desc(**w)) == omlmc.coarsest_mesh(w["cov"], w.get("nu", 0.5), w["lam"])
