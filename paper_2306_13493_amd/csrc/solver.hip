@@ -152,10 +152,13 @@ __device__ __forceinline__ void mg_half_sweep(T (&z)[SH][2], const T (&rhs)[SH][
     __syncthreads();
 }
 
-template <typename T, int SH, bool POST, bool L0>
+// WHOLE: the level's unknowns fit in one region (Dirichlet boundary, m - 1
+// <= 64 columns and rows), so one workgroup per sample takes the level with
+// no halo: every sweep is exact on the region and nothing is recomputed.
+template <typename T, int SH, bool POST, bool L0, bool WHOLE>
 __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
     constexpr int RX = 64, NH = kBlock / 32, RY = NH * SH;
-    constexpr int H = POST ? 4 : 6;
+    constexpr int H = WHOLE ? 0 : (POST ? 4 : 6);
     constexpr int TX = RX - 2 * H, TY = RY - 2 * H;
     constexpr int PX = RX + 2, PY = RY + 2;   // padded: one-node ring on every side
     __shared__ T sz[PY * PX];
@@ -1314,7 +1317,7 @@ public:
         itiles_ = itx_ * ity_;
         stx_ = cdiv(L0.m - 1, POST_TX);
         sty_ = cdiv(L0.yhi - L0.ylo + 1, POST_TY);
-        rz_parts_ = stx_ * sty_;
+        rz_parts_ = whole(0) ? 1 : stx_ * sty_;
         ublocks_ = (int)cdiv(L0.ss, kUpdChunk);
         max_parts_ = std::max(std::max(std::max(ptiles_, itiles_), rz_parts_), ublocks_);
         o_X_ = take(n0 * 8); o_R_ = take(n0 * 8); o_P0_ = take(n0 * 8); o_P1_ = take(n0 * 8);
@@ -1627,22 +1630,29 @@ private:
         return a;
     }
 
+    // a level whose unknowns fit one multigrid region (see k_mg's WHOLE)
+    bool whole(int l) const {
+        return cfg_.bc == BC_DIRICHLET0 && lv_[l].m - 1 <= 64 && lv_[l].m - 1 <= RYT;
+    }
+
     void vcycle(int it, hipStream_t st) {
         const int S = S_;
         const double sT = sizeof(T);
         for (int l = 0; l < lb_; ++l) {
             const Lvl& L = lv_[l];
-            const int tx = cdiv(L.m - 1, PRE_TX), ty = cdiv(L.yhi - L.ylo + 1, PRE_TY);
+            const bool wh = whole(l);
+            const int tx = wh ? 1 : cdiv(L.m - 1, PRE_TX), ty = wh ? 1 : cdiv(L.yhi - L.ylo + 1, PRE_TY);
             MgArgs<T> a = mg_args(l, tx, tx * ty);
             a.rhs_c = ptr<T>(o_rhs_[l]);
             // k, rhs in; z_pre and the coarse rhs out
             const double rb = l == 0 ? 8.0 : sT;
             const double coef = (l == 0 ? 1.0 : 2.0) * nv(l) * sT;   // k, or two conductance arrays
             launch(l == 0 ? "mg_pre_l0" : "mg_pre", coef + nu(l) * (rb + sT) + nu(l + 1) * sT, S, it, st, [&] {
-                if (l == 0)
-                    hipLaunchKernelGGL((k_mg<T, SH, false, true>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
-                else
-                    hipLaunchKernelGGL((k_mg<T, SH, false, false>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
+                const dim3 g(tx * ty * S), b(kBlock);
+                if (l == 0 && wh) hipLaunchKernelGGL((k_mg<T, SH, false, true, true>), g, b, 0, st, a);
+                else if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, false, true, false>), g, b, 0, st, a);
+                else if (wh) hipLaunchKernelGGL((k_mg<T, SH, false, false, true>), g, b, 0, st, a);
+                else hipLaunchKernelGGL((k_mg<T, SH, false, false, false>), g, b, 0, st, a);
             });
         }
         {
@@ -1671,7 +1681,8 @@ private:
         }
         for (int l = lb_ - 1; l >= 0; --l) {
             const Lvl& L = lv_[l];
-            const int tx = cdiv(L.m - 1, POST_TX), ty = cdiv(L.yhi - L.ylo + 1, POST_TY);
+            const bool wh = whole(l);
+            const int tx = wh ? 1 : cdiv(L.m - 1, POST_TX), ty = wh ? 1 : cdiv(L.yhi - L.ylo + 1, POST_TY);
             MgArgs<T> a = mg_args(l, tx, tx * ty);
             a.zc = ptr<T>(o_zb_[l]);
             a.zout = l == 0 ? ptr<T>(o_Z_) : ptr<T>(o_zb_[l - 1]);
@@ -1682,10 +1693,11 @@ private:
             const double post = l == 0 ? nv(0) * sT + nu(0) * (sT + 8.0 + 8.0 + sT) + nu(1) * sT
                                        : 2.0 * nv(l) * sT + nu(l) * 3.0 * sT + nu(l + 1) * sT;
             launch(l == 0 ? "mg_post_l0" : "mg_post", post, S, it, st, [&] {
-                if (l == 0)
-                    hipLaunchKernelGGL((k_mg<T, SH, true, true>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
-                else
-                    hipLaunchKernelGGL((k_mg<T, SH, true, false>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
+                const dim3 g(tx * ty * S), b(kBlock);
+                if (l == 0 && wh) hipLaunchKernelGGL((k_mg<T, SH, true, true, true>), g, b, 0, st, a);
+                else if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, true, true, false>), g, b, 0, st, a);
+                else if (wh) hipLaunchKernelGGL((k_mg<T, SH, true, false, true>), g, b, 0, st, a);
+                else hipLaunchKernelGGL((k_mg<T, SH, true, false, false>), g, b, 0, st, a);
             });
         }
     }
