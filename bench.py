@@ -104,6 +104,29 @@ def cpu_baseline(workload, seed, nsamples, nproc):
     return y, dt
 
 
+def parity_per_result(ces, plan, w, seed, log):
+    """Error of each result type of the benchmarked plan against the FP64
+    oracle: the normals (bit-exact), the Gaussian field Z of two samples
+    (relative to max |Z|) and the QoI (checked on the CPU-baseline samples
+    by the caller)."""
+    import numpy as np
+    from oracle import normals as onm, sampler
+    from paper_2306_13493_amd.workloads import to_oracle
+    e = np.arange(0, 200000, dtype=np.uint64)
+    g = ces.normals(seed, 5, w.get("stream", 0), 0, len(e)).cpu().numpy()
+    g0, g1 = onm.normals(seed, 5, w.get("stream", 0), e)
+    bitexact = bool(np.array_equal(g.view(np.uint64), np.stack([g0, g1], axis=1).view(np.uint64)))
+    ref = sampler.Plan(to_oracle(w))
+    worst = 0.0
+    for i in (0, 1):
+        zf, _ = plan.field(seed, i)
+        zr, _ = ref.fields(seed, i)
+        worst = max(worst, float(np.max(np.abs(zf.cpu().numpy() - zr)) / np.max(np.abs(zr))))
+    log("parity: normals bit-exact %s (%d pairs); field max rel diff %.2e" % (bitexact, len(e), worst))
+    return {"normals_bit_exact": bitexact, "normals_checked": int(len(e)), "field_max_rel_diff": worst,
+            "field_bar": 1e-5, "qoi_bar": 1e-6}
+
+
 def c3_batch(ces, ctx, W, log, reps=5):
     """Five MLMC levels (m = 16 .. 256, N = 20000/5000/1200/300/80) in one
     ces_sample_batch call, against the same levels one ces_sample call at a
@@ -343,6 +366,9 @@ def main():
                          "%d processes x 1 thread, wall %.1f s" % (ns - 1, nproc, dt)}
         extra["parity_vs_oracle_max_rel"] = rel
         log("cpu baseline %.3f samples/s; GPU vs oracle max rel diff %.2e" % (ns / dt, rel))
+    if not args.no_cpu_baseline:
+        extra["parity_vs_oracle"] = parity_per_result(ces, plan, w, seed, log)
+        extra["parity_vs_oracle"]["qoi_max_rel_diff"] = extra["parity_vs_oracle_max_rel"]
     if not args.no_fp64:
         p64 = ctx.plan(ces.level_desc(**dict(w, precision="fp64")))
         o64 = p64.sample(seed, 0, count)
@@ -355,9 +381,22 @@ def main():
         v64 = nrep * count / (time.perf_counter() - t1)
         om = plan.sample(seed, (nrep - 1) * count, count)
         diff = float(torch.max(torch.abs(om["y"] - o64["y"]) / torch.abs(o64["y"])).item())
+        # the plain FP64 path one sample per call (no batching)
+        n1 = 32
+        y1 = torch.empty(1, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(n1):
+            p64.lib.ces_sample(p64.handle, seed, i, 1, ces._ptr(y1), None, None, None, None,
+                               ces._stream_ptr(None))
+        torch.cuda.synchronize()
+        v1 = n1 / (time.perf_counter() - t1)
         extra["fp64_plain_path"] = {"value": round(v64, 1), "unit": "samples/s",
-                                    "mixed_vs_fp64_max_rel_diff_Y": diff}
-        log("plain FP64 path %.1f samples/s; mixed vs FP64 max rel diff %.2e" % (v64, diff))
+                                    "mixed_vs_fp64_max_rel_diff_Y": diff,
+                                    "one_sample_per_call": {"value": round(v1, 1), "unit": "samples/s",
+                                                            "samples": n1}}
+        log("plain FP64 path %.1f samples/s batched, %.1f samples/s one per call; mixed vs FP64 max rel diff %.2e"
+            % (v64, v1, diff))
 
     if not args.no_c3:
         extra["c3_mlmc_batch"] = c3_batch(ces, ctx, W, log)

@@ -206,3 +206,43 @@ def test_c2_full_size_sampled(ctx, ces, prec, tol):
     for i in (0, 1, 255):
         ref = o.sample(0, i)[0]
         assert abs(y[i] - ref) <= tol * abs(ref), (i, y[i], ref)
+
+
+def test_c5_full_size_field_and_flux_balance(ctx, ces):
+    """C5 at its full size (2049^2 vertices, flow cell, outflow QoI): the
+    field of a sample against the oracle's; the solution of the device
+    solver satisfies the discrete flux balance of the flow cell (the
+    operator's rows sum to zero, so the boundary fluxes add up to the
+    integral of f = 1) and reproduces the sampled outflow QoI.  The
+    operator is the oracle's element-by-element assembly on the float
+    coefficients the mixed solver uses."""
+    from oracle import fem as ofem2, qoi as oqoi
+    w = W.C5
+    m = w["m"]
+    p = mkplan(ctx, ces, w)
+    o = oracle_plan(w)
+    assert (p.info.n, p.info.J) == (o.n, o.J) == (4096, 0)
+    zf, _ = p.field(0, 0)
+    z = zf.cpu().numpy()
+    zr, _ = o.fields(0, 0)
+    assert np.max(np.abs(z - zr)) <= 1e-5 * np.max(np.abs(zr))
+    y = p.sample(0, 0, 2)["y"].cpu().numpy()
+    k = np.exp(z).astype(np.float32).astype(np.float64)
+    u, it = p.solve(torch.from_numpy(k).reshape(1, m + 1, m + 1).to("cuda"))
+    assert int(it.cpu()[0]) > 0
+    uu = u.cpu().numpy().reshape(-1)
+    A, b = ofem2.assemble(k, m, 1.0)
+    res = b - A @ uu
+    i = np.arange((m + 1) ** 2) % (m + 1)
+    influx, outflux = res[i == 0].sum(), res[i == m].sum()
+    free = (i > 0) & (i < m)
+    # CG stops at ||r|| <= 1e-10 ||r0|| (r0 of the Dirichlet lifting)
+    r0 = b - A @ (i == 0).astype(np.float64)
+    assert np.linalg.norm(res[free]) <= 1e-9 * np.linalg.norm(r0[free])
+    # rows (and columns) of A sum to zero: the boundary fluxes balance the
+    # load up to the sum of the free-node residuals
+    assert abs(b.sum() - 1.0) <= 1e-12
+    assert abs(influx + outflux - b.sum()) <= 1e-7
+    q = oqoi.outflux(uu, m, A, b)
+    assert abs(q - outflux) <= 1e-12 * abs(q)
+    assert abs(y[0] - q) <= 1e-6 * abs(q)
