@@ -33,7 +33,7 @@ KERNEL_SYMBOL = {
     "mg_pre": "k_mg<float, 8, false, false, false>",
     "mg_bottom": "k_bottom<float, 32, 256>",
     "pcg_dir": "k_pcg_dir<float>",
-    "pcg_update": "k_pcg_update",
+    "pcg_update": "k_pcg_update<false>",
     "pcg_init": "k_pcg_init<float>",
     "small_pcg": "k_small_pcg<float, 256>",
     "field_rows": "k_field_rows<float, 16, 0, 1>",

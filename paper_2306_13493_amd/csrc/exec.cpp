@@ -457,11 +457,11 @@ int Scheduler::start_t(Lane& L, const Job& j) {
     const int nslots = j.units * per_unit;
     FieldBatch<T> b = field_batch<T>(p, j.seed, j.u0, j.units);
     CES_HIP(launch_field<T>(b, L.sa), "field kernels");
-    CES_HIP(p->sf->begin(p->kf.p, p->kf_ss, nslots, L.sa), "fine solve");
+    CES_HIP(p->sf->begin(p->kf.p, p->kf_ss, nslots, L.sa, false), "fine solve");
     if (p->sc) {
         CES_HIP(hipEventRecord(L.ev_f, L.sa), "lane event");
         CES_HIP(hipStreamWaitEvent(L.sb, L.ev_f, 0), "lane event");
-        CES_HIP(p->sc->begin(p->kc.p, p->kc_ss, nslots, L.sb), "coarse solve");
+        CES_HIP(p->sc->begin(p->kc.p, p->kc_ss, nslots, L.sb, false), "coarse solve");
     }
     L.solving = true;
     L.fdone = L.cdone = false;

@@ -125,8 +125,9 @@ public:
     virtual size_t bytes() const = 0;
     virtual int mg_levels() const = 0;
     // k: capacity x kstride values of T (slot s at k + s*kstride); slots
-    // [0, S) are solved.
-    virtual hipError_t begin(const void* k, long long kstride, int S, hipStream_t st) = 0;
+    // [0, S) are solved.  keep_x = false lets a solve whose QoI is linear
+    // in u skip the iterate (x() then holds only the Dirichlet lifting).
+    virtual hipError_t begin(const void* k, long long kstride, int S, hipStream_t st, bool keep_x) = 0;
     // depth: iterations allowed in flight before their convergence count
     // has been read back (1..4).  graphs: replay iterations from captured
     // HIP graphs (same kernels and arguments).  *progressed: an iteration
@@ -138,7 +139,7 @@ public:
     virtual hipError_t finish(hipStream_t st) = 0;
     // begin + advance to the end + finish
     hipError_t solve(const void* k, long long kstride, int S, hipStream_t st, int depth = 2) {
-        hipError_t e = begin(k, kstride, S, st);
+        hipError_t e = begin(k, kstride, S, st, true);
         bool done = false, prog = false;
         while (e == hipSuccess && !done) {
             e = advance(st, depth, false, &done, &prog);
@@ -150,7 +151,8 @@ public:
     // converged); either may be null.
     virtual hipError_t qoi(const void* k, long long kstride, int S, double* q, int* iters,
                            hipStream_t st) = 0;
-    // Nodal solution (double, (m+1)^2 per slot, dense).
+    // Nodal solution (double, (m+1)^2 per slot, dense) of a solve begun
+    // with keep_x.
     virtual const double* x() const = 0;
     virtual long long xstride() const = 0;
 };

@@ -25,6 +25,8 @@
 // per-tile partial sums reduced in a fixed order, so every result is
 // independent of the batch composition.  Converged samples switch their
 // workgroups off (per-sample active flag).
+#include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "internal.hpp"
@@ -35,6 +37,8 @@ namespace {
 
 struct Scal {
     double bb, rz, rz_old, pq, rr, zq;
+    double wp;     // w.p of the current direction (linear QoI)
+    double qacc;   // sum over iterations of alpha w.p = w.(x - x0)
     int it, active, status, pad;
 };
 
@@ -925,6 +929,19 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
 // ----------------------------------------------------------- PCG (double)
 constexpr int PTX = 64, PTY = 16;
 
+// A QoI that is linear in u, Q(x) = Q(x0) + w.(x - x0), needs no iterate:
+// with x0 the Dirichlet lifting and x - x0 = sum_k alpha_k p_k, the solve
+// accumulates alpha_k w.p_k per sample and never stores x.  Weights w:
+// integral, the load weights tri_count h^2 / 6; point value, the three P1
+// barycentric weights of the triangle holding the point; outflux through
+// x1 = 1, the conductance of the edge from (m-1, j) to the boundary node
+// (m, j) (there b - A x is linear in the neighbouring unknown).
+struct QoiLin {
+    int on, kind;
+    int pi, pj;                     // point: lower-left node of its square
+    double w00, w10, w11, w01;      // point: weights of (pi,pj), (pi+1,pj), (pi+1,pj+1), (pi,pj+1)
+};
+
 template <typename T>
 struct PcgArgs {
     Lvl L;
@@ -935,8 +952,21 @@ struct PcgArgs {
     double *X, *R, *Pold, *Pnew, *Q;
     T* Z;   // preconditioned residual (precision of the multigrid)
     double* part;
+    double* part2;   // partial w.p (linear QoI)
     Scal* scal;
+    QoiLin ql;
 };
+
+// weight of unknown (gx, gy) in a linear QoI; ce is the conductance of the
+// east edge of the node
+__device__ __forceinline__ double qoi_weight(const QoiLin& q, int gx, int gy, int m, double h2, double ce) {
+    if (q.kind == Q_INTEGRAL) return (double)tri_count(gx, gy, m) * h2 * (1.0 / 6.0);
+    if (q.kind == Q_OUTFLUX) return gx == m - 1 ? ce : 0.0;
+    double w = 0.0;
+    if (gy == q.pj) w = gx == q.pi ? q.w00 : (gx == q.pi + 1 ? q.w10 : 0.0);
+    else if (gy == q.pj + 1) w = gx == q.pi + 1 ? q.w11 : (gx == q.pi ? q.w01 : 0.0);
+    return w;
+}
 
 template <typename T>
 struct KTile {
@@ -1003,7 +1033,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
     constexpr int KX = PTX + 2, KY = PTY + 2, NR = PTY / (kBlock / 64);
     __shared__ double K[KY * KX];
     __shared__ double P[KY * KX];
-    __shared__ double red[kBlock / 64];
+    __shared__ double red[2 * (kBlock / 64)];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     const int s = wi / a.ntiles, tile = wi - s * a.ntiles;
     const Scal sc = a.scal[s];
@@ -1060,6 +1090,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
     }
     const double sixth = 1.0 / 6.0;
     double cS = (s2a_p + s1m_p) * sixth;
+    double accw = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const int yy = NR * wv + r, gy = y0 + yy;
@@ -1079,11 +1110,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
             a.Pnew[o] = pc;
             a.Q[o] = q;
             acc += pc * q;
+            if (a.ql.on) accw += qoi_weight(a.ql, gx, gy, m, a.h2, cE) * pc;
         }
         s1m_p = s1m; s2m_p = s2m; s2a_p = s2a;
         cS = cN;
     }
-    acc = block_sum(acc, red);
+    if (a.ql.on) {
+        block_sum2(acc, accw, red);
+        if (threadIdx.x == 0) a.part2[(size_t)s * a.ntiles + tile] = accw;
+    } else {
+        acc = block_sum(acc, red);
+    }
     if (threadIdx.x == 0) a.part[(size_t)s * a.ntiles + tile] = acc;
 }
 
@@ -1097,6 +1134,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
 constexpr int kUpdChunk = 4 * 2 * kBlock;   // nodes per workgroup
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
+// KEEPX = false (a linear QoI accumulated per iteration) skips x and p.
+template <bool KEEPX>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(double* __restrict__ X, double* __restrict__ R,
                                                        const double* __restrict__ P, const double* __restrict__ Q,
                                                        long long ss, int nb, double* __restrict__ part,
@@ -1114,21 +1153,26 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(double* __restrict__ X, d
     for (int i = 0; i < V; ++i) {
         o[i] = (long long)b * kUpdChunk + 2LL * (i * kBlock + threadIdx.x);
         const long long oc = o[i] < ss ? o[i] : 0;   // ss is even: pairs never straddle the end
-        xv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(X + base + oc));
+        if (KEEPX) {
+            xv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(X + base + oc));
+            pv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(P + base + oc));
+        }
         rv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(R + base + oc));
-        pv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(P + base + oc));
         qv[i] = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(Q + base + oc));
     }
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         if (o[i] >= ss) continue;
-        dvec2 xn, rn;
-        xn.x = xv[i].x + alpha * pv[i].x;
-        xn.y = xv[i].y + alpha * pv[i].y;
+        dvec2 rn;
+        if (KEEPX) {
+            dvec2 xn;
+            xn.x = xv[i].x + alpha * pv[i].x;
+            xn.y = xv[i].y + alpha * pv[i].y;
+            __builtin_nontemporal_store(xn, reinterpret_cast<dvec2*>(X + base + o[i]));
+        }
         rn.x = rv[i].x - alpha * qv[i].x;
         rn.y = rv[i].y - alpha * qv[i].y;
-        __builtin_nontemporal_store(xn, reinterpret_cast<dvec2*>(X + base + o[i]));
         __builtin_nontemporal_store(rn, reinterpret_cast<dvec2*>(R + base + o[i]));
         acc += rn.x * rn.x + rn.y * rn.y;
     }
@@ -1147,7 +1191,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
     double acc = 0.0, acc2 = 0.0;
     for (int t = threadIdx.x; t < np; t += blockDim.x) acc += part[(size_t)s * np + t];
     acc = block_sum(acc, red);
-    if (WHAT == RED_RZ) {
+    if (WHAT == RED_RZ || (WHAT == RED_PQ && part2)) {
         for (int t = threadIdx.x; t < np; t += blockDim.x) acc2 += part2[(size_t)s * np + t];
         acc2 = block_sum(acc2, red);
     }
@@ -1156,7 +1200,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
     if (WHAT == RED_BB) {
         sc.bb = acc;
         sc.it = 0;
-        sc.rz = sc.rz_old = sc.pq = sc.zq = 0.0;
+        sc.rz = sc.rz_old = sc.pq = sc.zq = sc.wp = sc.qacc = 0.0;
         sc.rr = acc;
         sc.status = 0;
         sc.active = acc > 0.0 ? 1 : 0;
@@ -1166,6 +1210,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
         sc.zq = acc2;
     } else if (WHAT == RED_PQ) {
         sc.pq = acc;
+        if (part2) {
+            // the step alpha = rz / pq of this iteration, as the update takes it
+            sc.wp = acc2;
+            sc.qacc += (sc.rz / sc.pq) * acc2;
+        }
     } else {
         sc.rr = acc;
         sc.it += 1;
@@ -1186,7 +1235,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ X, Lvl L, int bc, double f, int qoi,
                                                 double qx, double qy, const T* __restrict__ k, long long kss,
-                                                const Scal* scal, double* q, int* iters) {
+                                                const Scal* scal, int lin, double* q, int* iters) {
     __shared__ double red[kBlock / 64];
     const int s = blockIdx.x;
     const int m = L.m, w = L.w;
@@ -1229,6 +1278,8 @@ __global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ X, Lv
         acc = block_sum(acc, red);
     }
     if (threadIdx.x == 0) {
+        // linear QoI: x holds the lifting x0, the solve accumulated w.(x - x0)
+        if (lin) acc += scal[s].qacc;
         if (q) q[s] = acc;
         if (iters) iters[s] = scal[s].status == 0 ? scal[s].it : -scal[s].it;
     }
@@ -1381,8 +1432,9 @@ public:
     const double* x() const override { return ptr<double>(o_X_); }
     long long xstride() const override { return lv_[0].ss; }
 
-    hipError_t begin(const void* kv, long long kss, int S, hipStream_t st) override {
+    hipError_t begin(const void* kv, long long kss, int S, hipStream_t st, bool keep_x) override {
         k0_ = reinterpret_cast<const T*>(kv);
+        lin_ = !small_ && !keep_x && cfg_.qoi != Q_L2;
         kss_ = kss;
         S_ = S;
         it_next_ = confirmed_ = 0;
@@ -1503,7 +1555,7 @@ public:
         launch("qoi", nv(0) * 8.0, S, -1, st, [&] {
             hipLaunchKernelGGL(k_qoi<T>, dim3(S), dim3(kBlock), 0, st, ptr<double>(o_X_), lv_[0], cfg_.bc, cfg_.f,
                                cfg_.qoi, cfg_.qx, cfg_.qy, reinterpret_cast<const T*>(kv), kss, ptr<Scal>(o_scal_),
-                               q ? q : ptr<double>(o_q_), iters ? iters : ptr<int>(o_it_));
+                               lin_ ? 1 : 0, q ? q : ptr<double>(o_q_), iters ? iters : ptr<int>(o_it_));
         });
         return hipGetLastError();
     }
@@ -1544,10 +1596,15 @@ private:
         launch("pcg_dir", nu(0) * (24.0 + sT) + nv(0) * sT, S, it, st, [&] {
             hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
         });
-        hipLaunchKernelGGL(k_reduce<RED_PQ>, dim3(S), dim3(kBlock), 0, st, part, part, ptiles_, scal, rtol2, cfg_.maxit, cnt);
-        launch("pcg_update", nu(0) * 48.0, S, it, st, [&] {
-            hipLaunchKernelGGL(k_pcg_update, dim3(ublocks_, S), dim3(kBlock), 0, st, a.X, a.R, a.Pnew, a.Q,
-                               lv_[0].ss, ublocks_, part, scal);
+        hipLaunchKernelGGL(k_reduce<RED_PQ>, dim3(S), dim3(kBlock), 0, st, part, lin_ ? part2 : nullptr, ptiles_,
+                           scal, rtol2, cfg_.maxit, cnt);
+        launch("pcg_update", nu(0) * (lin_ ? 24.0 : 48.0), S, it, st, [&] {
+            if (lin_)
+                hipLaunchKernelGGL(k_pcg_update<false>, dim3(ublocks_, S), dim3(kBlock), 0, st, a.X, a.R, a.Pnew,
+                                   a.Q, lv_[0].ss, ublocks_, part, scal);
+            else
+                hipLaunchKernelGGL(k_pcg_update<true>, dim3(ublocks_, S), dim3(kBlock), 0, st, a.X, a.R, a.Pnew,
+                                   a.Q, lv_[0].ss, ublocks_, part, scal);
         });
         hipLaunchKernelGGL(k_reduce<RED_RR>, dim3(S), dim3(kBlock), 0, st, part, part, ublocks_, scal, rtol2, cfg_.maxit, cnt);
         if (Profiler::get().on())
@@ -1563,7 +1620,7 @@ private:
     hipError_t iteration_graph(int parity, hipGraphExec_t* out) {
         ItGraph* G = nullptr;
         for (auto& g : graphs_)
-            if (g.S == S_ && g.k == k0_) G = &g;
+            if (g.S == S_ && g.k == k0_ && g.lin == lin_) G = &g;
         if (!G) {
             G = &graphs_[graph_victim_];
             graph_victim_ ^= 1;
@@ -1572,6 +1629,7 @@ private:
             G->exec[0] = G->exec[1] = nullptr;
             G->S = S_;
             G->k = k0_;
+            G->lin = lin_;
         }
         if (!G->exec[parity]) {
             hipError_t e = hipSuccess;
@@ -1607,8 +1665,37 @@ private:
         a.Q = ptr<double>(o_Q_);
         a.Z = ptr<T>(o_Z_);
         a.part = ptr<double>(o_part_);
+        a.part2 = ptr<double>(o_part2_);
         a.scal = ptr<Scal>(o_scal_);
+        a.ql = qoi_lin();
         return a;
+    }
+
+    // weights of the linear QoI of this mesh (off when the solve keeps x)
+    QoiLin qoi_lin() const {
+        QoiLin q{};
+        q.on = lin_ ? 1 : 0;
+        q.kind = cfg_.qoi;
+        q.pi = q.pj = -2;
+        if (cfg_.qoi == Q_POINT) {
+            // the triangle of the diagonal split that holds the point
+            const int m = cfg_.m;
+            const double h = 1.0 / m;
+            const int i = std::min((int)std::floor(cfg_.qx / h), m - 1), j = std::min((int)std::floor(cfg_.qy / h), m - 1);
+            const double sx = cfg_.qx / h - i, sy = cfg_.qy / h - j;
+            q.pi = i;
+            q.pj = j;
+            if (sx >= sy) {
+                q.w00 = 1 - sx;
+                q.w10 = sx - sy;
+                q.w11 = sy;
+            } else {
+                q.w00 = 1 - sy;
+                q.w11 = sx;
+                q.w01 = sy - sx;
+            }
+        }
+        return q;
     }
 
     MgArgs<T> mg_args(int l, int tiles_x, int ntiles) {
@@ -1719,6 +1806,7 @@ private:
     struct ItGraph {
         int S = -1;
         const T* k = nullptr;
+        bool lin = false;
         hipGraphExec_t exec[2] = {nullptr, nullptr};
     };
     ItGraph graphs_[2];
@@ -1726,6 +1814,7 @@ private:
     hipStream_t cap_stream_ = nullptr;
     // state of the solve in progress
     const T* k0_ = nullptr;
+    bool lin_ = false;   // the solve accumulates a linear QoI instead of x
     long long kss_ = 0;
     int S_ = 0, it_next_ = 0, confirmed_ = 0;
     bool done_ = true;

@@ -158,6 +158,13 @@ SAMPLE_CASES = {
                               qoi="outflux"), 8),
     "point_qoi_pair": (dict(cov="sepexp", lam=0.3, m=32, level="pair", qoi="point"), 8),
     "l2_qoi": (dict(cov="matern", nu=1.5, lam=0.03, m=64, qoi="l2"), 6),
+    # tiled solves of QoIs that are linear in u accumulate the QoI over the
+    # CG steps instead of keeping the iterate
+    "outflux_tiled_pair": (dict(cov="matern", nu=1.5, lam=0.05, sigma2=2.0, m=128, level="pair",
+                                bc="flowcell", qoi="outflux"), 4),
+    "point_tiled_upper_triangle": (dict(cov="sepexp", lam=0.3, m=128, level="pair", qoi="point",
+                                        qoi_x=0.3, qoi_y=0.71), 4),
+    "integral_flowcell_tiled": (dict(cov="matern", nu=1.0, lam=0.1, m=64, bc="flowcell"), 6),
 }
 
 
