@@ -159,9 +159,12 @@ SAMPLE_CASES = {
     "point_qoi_pair": (dict(cov="sepexp", lam=0.3, m=32, level="pair", qoi="point"), 8),
     "l2_qoi": (dict(cov="matern", nu=1.5, lam=0.03, m=64, qoi="l2"), 6),
     # tiled solves of QoIs that are linear in u accumulate the QoI over the
-    # CG steps instead of keeping the iterate
+    # CG steps instead of keeping the iterate.  The outflux is a boundary
+    # functional of A u: a residual of 1e-10 of r0 (the flow cell's r0 is
+    # large next to x1 = 0) bounds it only to a few 1e-9, so this case
+    # solves to 1e-12 and checks the accumulation at the 1e-9 bar.
     "outflux_tiled_pair": (dict(cov="matern", nu=1.5, lam=0.05, sigma2=2.0, m=128, level="pair",
-                                bc="flowcell", qoi="outflux"), 4),
+                                bc="flowcell", qoi="outflux", cg_rtol=1e-12), 4),
     "point_tiled_upper_triangle": (dict(cov="sepexp", lam=0.3, m=128, level="pair", qoi="point",
                                         qoi_x=0.3, qoi_y=0.71), 4),
     "integral_flowcell_tiled": (dict(cov="matern", nu=1.0, lam=0.1, m=64, bc="flowcell"), 6),
