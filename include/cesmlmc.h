@@ -272,6 +272,46 @@ int ces_mlmc_run(ces_context ctx, const ces_plan* levels, const ces_plan* finest
  * exponential); returns m_0 = 1/h_0 in *m0. */
 int ces_mlmc_coarsest_mesh(const ces_level_desc* desc, int32_t* m0);
 
+/* ---- smoothing parameter and smoothing error -------------------------- */
+
+/* Number of eigenvalues to drop on a mesh h = 1/m (Section 3.5): the
+ * smoothing error bound of the covariance's corollary (separable
+ * exponential: C_s tau / (s - tau + 1); Matern: eq. (tau-values-matern))
+ * set equal to the discretisation error C_alpha h^alpha, with s = n^2 =
+ * 4 (m + J)^2.  Separable exponential: closed form, eq.
+ * (k-values-p-norm-cov) (needs J = 0: its classical embedding is
+ * nonnegative).  Matern: the root of eq. (tau-values-matern) in [0, s] by
+ * bisection (the left side increases strictly in tau); s when the right
+ * side is at least s.  cs_over_calpha = C_s / C_alpha > 0 (constants of the
+ * two bounds, from pilot runs), alpha > 0.  *tau = the root rounded to the
+ * nearest integer; *tau_real (may be NULL) = the root.  Host only;
+ * CES_ERR_ARG on invalid arguments. */
+int ces_tau_rule(int32_t cov_kind, double nu, int32_t m, int32_t J, double alpha, double cs_over_calpha,
+                 int64_t* tau, double* tau_real);
+
+typedef struct {
+    int32_t struct_size;   /* sizeof(ces_smoothing_stats), set by the caller */
+    int32_t reserved;
+    int64_t n;             /* samples */
+    double mean;           /* sample mean of Q_h - Q~_h */
+    double mean_abs;       /* sample mean of |Q_h - Q~_h| */
+    double var;            /* sample variance of Q_h - Q~_h (n - 1 denominator) */
+    double mean_q;         /* sample mean of Q_h */
+    double mean_q_smoothed;/* sample mean of Q~_h */
+} ces_smoothing_stats;
+
+/* Smoothing error of one mesh (Section 4.1, the quantities E[Q_h - Q~_h]
+ * and V[Q_h - Q~_h]; Corollaries (error-1-norm-cov), (error-matern-cov)):
+ * `full` and `smoothed` are SINGLE plans that differ only in tau_fine
+ * (same mesh, covariance, field mode, precision, PDE data and stream), so
+ * sample i of `seed` draws the same normals in both and Q_h^(i) - Q~_h^(i)
+ * is taken on one realisation of the field.  Samples first .. first+count-1
+ * (count >= 2) of both plans run in one ces_sample_batch call; the
+ * statistics are accumulated on the host in sample order.  Synchronous;
+ * hip_stream orders the sampling. */
+int ces_smoothing_error(ces_context ctx, ces_plan full, ces_plan smoothed, uint64_t seed, uint64_t first,
+                        int64_t count, void* hip_stream, ces_smoothing_stats* out);
+
 /* ---- serving: continuous batching with memory admission -------------- */
 
 /* A server owns a host thread that plans, admits and runs requests as they

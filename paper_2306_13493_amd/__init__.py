@@ -15,7 +15,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import CesError, LevelDesc, MlmcOpts, MlmcResult, PlanInfo, Request, Schedule, ServerStats, check, load
+from ._lib import (CesError, LevelDesc, MlmcOpts, MlmcResult, PlanInfo, Request, Schedule, ServerStats,
+                   SmoothingStats, check, load)
 
 COV = {"matern": 0, "sepexp": 1}
 LEVEL = {"single": 0, "pair": 1}
@@ -328,6 +329,27 @@ def coarsest_mesh(desc):
     m0 = ctypes.c_int32()
     check(load().ces_mlmc_coarsest_mesh(ctypes.byref(desc), ctypes.byref(m0)))
     return m0.value
+
+
+def tau_rule(cov, m, alpha, cs_over_calpha, nu=0.5, J=0):
+    """ces_tau_rule: eigenvalues to drop on mesh 1/m from the balance of
+    discretisation and smoothing error; returns (tau, real root)."""
+    t = ctypes.c_int64()
+    tr = ctypes.c_double()
+    check(load().ces_tau_rule(_enum(COV, cov), float(nu), int(m), int(J), float(alpha), float(cs_over_calpha),
+                              ctypes.byref(t), ctypes.byref(tr)))
+    return t.value, tr.value
+
+
+def smoothing_error(ctx, full, smoothed, seed, first, count, stream=None):
+    """ces_smoothing_error: statistics of Q_h - Q~_h over samples
+    first..first+count-1 of two single plans that differ only in tau."""
+    r = SmoothingStats()
+    r.struct_size = ctypes.sizeof(SmoothingStats)
+    check(load().ces_smoothing_error(ctx.handle, full.handle, smoothed.handle, int(seed), int(first), int(count),
+                                     _stream_ptr(stream), ctypes.byref(r)))
+    return {"n": r.n, "mean": r.mean, "mean_abs": r.mean_abs, "var": r.var, "mean_q": r.mean_q,
+            "mean_q_smoothed": r.mean_q_smoothed}
 
 
 def normals(seed, q, stream_tag, first_e, count, device=0, stream=None):

@@ -79,6 +79,11 @@ class MlmcResult(ctypes.Structure):
                 ("cost", c_double * MLMC_MAX_LEVELS)]
 
 
+class SmoothingStats(ctypes.Structure):
+    _fields_ = [("struct_size", c_int32), ("reserved", c_int32), ("n", c_int64), ("mean", c_double),
+                ("mean_abs", c_double), ("var", c_double), ("mean_q", c_double), ("mean_q_smoothed", c_double)]
+
+
 # name -> (restype, argtypes); every function declared in include/cesmlmc.h
 SIGNATURES = {
     "ces_level_desc_default": (None, [ctypes.POINTER(LevelDesc)]),
@@ -105,6 +110,10 @@ SIGNATURES = {
     "ces_mlmc_run": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int32,
                                ctypes.POINTER(MlmcOpts), c_void_p, ctypes.POINTER(MlmcResult)]),
     "ces_mlmc_coarsest_mesh": (c_int32, [ctypes.POINTER(LevelDesc), ctypes.POINTER(c_int32)]),
+    "ces_tau_rule": (c_int32, [c_int32, c_double, c_int32, c_int32, c_double, c_double, ctypes.POINTER(c_int64),
+                               ctypes.POINTER(c_double)]),
+    "ces_smoothing_error": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_uint64, c_int64, c_void_p,
+                                      ctypes.POINTER(SmoothingStats)]),
     "ces_normals": (c_int32, [c_uint64, c_uint64, c_uint32, c_uint64, c_int64, c_dptr, c_void_p]),
     "ces_plan_eigenvalues": (c_int32, [c_void_p, c_void_p]),
     "ces_plan_mask": (c_int32, [c_void_p, c_void_p, c_void_p]),

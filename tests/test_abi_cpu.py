@@ -99,3 +99,14 @@ def test_mlmc_entry_points(lib):
     d.nu, d.lambda_ = 0.5, 0.03
     m0 = ctypes.c_int32()
     assert lib.ces_mlmc_coarsest_mesh(ctypes.byref(d), ctypes.byref(m0)) == 0 and m0.value == 32
+
+
+def test_smoothing_study_entry_points(lib):
+    from paper_2306_13493_amd import _lib
+    assert ctypes.sizeof(_lib.SmoothingStats) == 56
+    r = _lib.SmoothingStats()
+    r.struct_size = ctypes.sizeof(r)
+    assert lib.ces_smoothing_error(None, None, None, 0, 0, 4, None, ctypes.byref(r)) == -1
+    t = ctypes.c_int64()
+    assert lib.ces_tau_rule(0, 1.5, 64, 0, 1.0, 1.0, ctypes.byref(t), None) == 0 and 0 <= t.value <= 128 * 128
+    assert lib.ces_tau_rule(7, 1.5, 64, 0, 1.0, 1.0, ctypes.byref(t), None) == -1
