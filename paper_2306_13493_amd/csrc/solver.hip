@@ -159,17 +159,22 @@ __device__ __forceinline__ void mg_half_sweep(T (&z)[SH][2], const T (&rhs)[SH][
 // WHOLE: the level's unknowns fit in one region (Dirichlet boundary, m - 1
 // <= 64 columns and rows), so one workgroup per sample takes the level with
 // no halo: every sweep is exact on the region and nothing is recomputed.
-template <typename T, int SH, bool POST, bool L0, bool WHOLE>
-__global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
-    constexpr int RX = 64, NH = kBlock / 32, RY = NH * SH;
+// RXW = 128 (float, levels >= 1 only): the same with 128 x 128 regions, a
+// workgroup of 16 waves of 64 lanes (lane k owns columns 2k, 2k+1 of its
+// wave's SH rows), for levels with m - 1 <= 128.
+template <typename T, int SH, bool POST, bool L0, bool WHOLE, int RXW = 64>
+__global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
+    static_assert(RXW == 64 || (RXW == 128 && WHOLE && !L0), "128-wide regions: whole coarse levels only");
+    constexpr int NT = RXW == 64 ? kBlock : 1024, LW = RXW / 2;
+    constexpr int RX = RXW, NH = NT / LW, RY = NH * SH;
     constexpr int H = WHOLE ? 0 : (POST ? 4 : 6);
     constexpr int TX = RX - 2 * H, TY = RY - 2 * H;
     constexpr int PX = RX + 2, PY = RY + 2;   // padded: one-node ring on every side
     __shared__ T sz[PY * PX];
-    __shared__ T sk[PY * PX];    // level 0: k; PRE reuses it for the residual
+    __shared__ T sk[(L0 || !POST) ? PY * PX : 1];    // level 0: k; PRE reuses it for the residual
     constexpr int CX = RX / 2 + 3, CY = RY / 2 + 3;
     __shared__ T szc[POST ? CY * CX : 1];
-    __shared__ double red[kBlock / 64];
+    __shared__ double red[NT / 64];
     const int wi = xcd_remap(blockIdx.x, gridDim.x);
     const int s = wi / a.ntiles;
     const int tile = wi - s * a.ntiles;
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_mg(MgArgs<T> a) {
         }
     }
     __syncthreads();
-    const int lane = threadIdx.x & 31, hw = threadIdx.x >> 5;
+    const int lane = threadIdx.x % LW, hw = threadIdx.x / LW;
     const int lx0 = 2 * lane, ly0 = hw * SH;
     const int gx0 = ox + lx0;
     // column masks of this lane
@@ -1721,13 +1726,18 @@ private:
     bool whole(int l) const {
         return cfg_.bc == BC_DIRICHLET0 && lv_[l].m - 1 <= 64 && lv_[l].m - 1 <= RYT;
     }
+    // a coarse level that fits one 128 x 128 region (float multigrid)
+    bool whole128(int l) const {
+        return sizeof(T) == 4 && l >= 1 && cfg_.bc == BC_DIRICHLET0 && lv_[l].m - 1 > 64 && lv_[l].m - 1 <= 128;
+    }
 
     void vcycle(int it, hipStream_t st) {
         const int S = S_;
         const double sT = sizeof(T);
         for (int l = 0; l < lb_; ++l) {
             const Lvl& L = lv_[l];
-            const bool wh = whole(l);
+            const bool w128 = whole128(l);
+            const bool wh = whole(l) || w128;
             const int tx = wh ? 1 : cdiv(L.m - 1, PRE_TX), ty = wh ? 1 : cdiv(L.yhi - L.ylo + 1, PRE_TY);
             MgArgs<T> a = mg_args(l, tx, tx * ty);
             a.rhs_c = ptr<T>(o_rhs_[l]);
@@ -1736,6 +1746,12 @@ private:
             const double coef = (l == 0 ? 1.0 : 2.0) * nv(l) * sT;   // k, or two conductance arrays
             launch(l == 0 ? "mg_pre_l0" : "mg_pre", coef + nu(l) * (rb + sT) + nu(l + 1) * sT, S, it, st, [&] {
                 const dim3 g(tx * ty * S), b(kBlock);
+                if constexpr (sizeof(T) == 4) {
+                    if (w128) {
+                        hipLaunchKernelGGL((k_mg<T, SH, false, false, true, 128>), g, dim3(1024), 0, st, a);
+                        return;
+                    }
+                }
                 if (l == 0 && wh) hipLaunchKernelGGL((k_mg<T, SH, false, true, true>), g, b, 0, st, a);
                 else if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, false, true, false>), g, b, 0, st, a);
                 else if (wh) hipLaunchKernelGGL((k_mg<T, SH, false, false, true>), g, b, 0, st, a);
@@ -1768,7 +1784,8 @@ private:
         }
         for (int l = lb_ - 1; l >= 0; --l) {
             const Lvl& L = lv_[l];
-            const bool wh = whole(l);
+            const bool w128 = whole128(l);
+            const bool wh = whole(l) || w128;
             const int tx = wh ? 1 : cdiv(L.m - 1, POST_TX), ty = wh ? 1 : cdiv(L.yhi - L.ylo + 1, POST_TY);
             MgArgs<T> a = mg_args(l, tx, tx * ty);
             a.zc = ptr<T>(o_zb_[l]);
@@ -1781,6 +1798,12 @@ private:
                                        : 2.0 * nv(l) * sT + nu(l) * 3.0 * sT + nu(l + 1) * sT;
             launch(l == 0 ? "mg_post_l0" : "mg_post", post, S, it, st, [&] {
                 const dim3 g(tx * ty * S), b(kBlock);
+                if constexpr (sizeof(T) == 4) {
+                    if (w128) {
+                        hipLaunchKernelGGL((k_mg<T, SH, true, false, true, 128>), g, dim3(1024), 0, st, a);
+                        return;
+                    }
+                }
                 if (l == 0 && wh) hipLaunchKernelGGL((k_mg<T, SH, true, true, true>), g, b, 0, st, a);
                 else if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, true, true, false>), g, b, 0, st, a);
                 else if (wh) hipLaunchKernelGGL((k_mg<T, SH, true, false, true>), g, b, 0, st, a);
