@@ -8,20 +8,22 @@
 // ([T ...] = the adjacent triangle exists), (A u)_p = sum_q c_pq (u_p - u_q)
 // and load b_p = f (#triangles at p) h^2/6.
 //
-// Method: conjugate gradients in double, preconditioned by one geometric
-// multigrid V(2,2) cycle in T (float on the mixed path, double on the
-// plain path): red-black Gauss-Seidel (red, black, red, black before the
-// coarse correction, the reverse after, so the preconditioner is
-// symmetric), restriction = transpose of bilinear prolongation, coarse
-// operators rediscretised from the geometric mean of k over the
-// full-weighting stencil, exact solve on the 2 x 2 mesh.
+// Method: conjugate gradients in double (beta = r.z / r_old.z_old),
+// preconditioned by one geometric multigrid V(2,2) cycle in T (float on
+// the mixed path, double on the plain path): red-black Gauss-Seidel (red,
+// black, red, black before the coarse correction, the reverse after, so
+// the preconditioner is symmetric), restriction = transpose of bilinear
+// prolongation, coarse edge conductances from the series (harmonic) means
+// of the fine edges they span (exact for constant k), exact solve on the
+// 2 x 2 mesh.
 //
-// Work layout: one launch handles a whole batch of samples (blockIdx.y =
-// sample); fine levels are tiled (64 x 16 or 64 x 8 nodes per workgroup)
-// and the four half-sweeps of a smoothing step run in LDS on the tile plus
-// a 4-node halo (temporal blocking: one HBM read of z, rhs and k and one
-// write of z per smoothing step); all levels with m <= 32 (16 in double)
-// run in one workgroup per sample entirely in LDS.  Dot products are
+// Work layout: one launch handles a whole batch of samples; fine levels
+// are tiled (64 x 64 or 64 x 32 node regions per workgroup) and the four
+// half-sweeps of a smoothing step run in LDS on the tile plus a 4-node
+// halo (temporal blocking: one HBM read of z, rhs and k and one write of z
+// per smoothing step); a level that fits one region is smoothed by one
+// workgroup per sample without halo; all levels with m <= 32 (16 in
+// double) run in one workgroup per sample entirely in LDS.  Dot products are
 // per-tile partial sums reduced in a fixed order, so every result is
 // independent of the batch composition.  Converged samples switch their
 // workgroups off (per-sample active flag).
@@ -36,7 +38,7 @@ namespace ces {
 namespace {
 
 struct Scal {
-    double bb, rz, rz_old, pq, rr, zq;
+    double bb, rz, rz_old, pq, rr;
     double wp;     // w.p of the current direction (linear QoI)
     double qacc;   // sum over iterations of alpha w.p = w.(x - x0)
     int it, active, status, pad;
@@ -105,7 +107,7 @@ __device__ __forceinline__ int tri_count(int i, int j, int m) {
 // the tile, then the residual r - A z on the tile plus one ring and its
 // restriction P^T to the coarse nodes whose fine centre lies in the tile.
 // POST (H = 4): z_pre + P z_coarse, two sweeps (black, red, black, red),
-// z written on the tile; on level 0 also the partial sums r.z and z.q_old.
+// z written on the tile; on level 0 also the partial sum r.z.
 template <typename T>
 struct MgArgs {
     Lvl L, C;            // this level, the next coarser level
@@ -120,8 +122,6 @@ struct MgArgs {
     const T* zc;         // POST: coarse correction
     T* zout;             // POST: smoothed z
     double* dot;         // POST level 0: partial r.z per tile
-    double* dot2;        // POST level 0: partial z.q_old per tile
-    const double* q;     // POST level 0: q_old
     const Scal* scal;
 };
 
@@ -351,18 +351,8 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
             mg_half_sweep<T, SH, 1, PX>(z, rhs, id, ce, cw0, cn, sz0);
     }
     // outputs on the tile (margin >= H); id != 0 marks unknown nodes
-    double acc = 0.0, acc2 = 0.0;
+    double acc = 0.0;
     T* out = POST ? a.zout + sbase : a.za + sbase;
-    double qv[POST && L0 ? SH : 1][2];
-    if constexpr (POST && L0) {
-        const int gxc0 = min(max(gx0, 0), m), gxc1 = min(max(gx0 + 1, 0), m);
-#pragma unroll
-        for (int r = 0; r < SH; ++r) {
-            const int gyc = min(max(oy + ly0 + r, 0), m);
-            qv[r][0] = a.q[sbase + gyc * w + gxc0];
-            qv[r][1] = a.q[sbase + gyc * w + gxc1];
-        }
-    }
 #pragma unroll
     for (int r = 0; r < SH; ++r) {
         const int ly = ly0 + r, gy = oy + ly;
@@ -373,21 +363,14 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
             const bool in = iny && lx >= H && lx < H + TX && id[r][q] != T(0);
             if (in) out[gy * w + gx0 + q] = z[r][q];
             if constexpr (POST && L0) {
-                if (in) {
-                    acc += (double)rhs[r][q] * (double)z[r][q];
-                    acc2 += qv[r][q] * (double)z[r][q];
-                }
+                if (in) acc += (double)rhs[r][q] * (double)z[r][q];
             }
         }
     }
     if constexpr (POST) {
         if constexpr (L0) {
             acc = block_sum(acc, red);
-            acc2 = block_sum(acc2, red);
-            if (threadIdx.x == 0) {
-                a.dot[(size_t)s * a.ntiles + tile] = acc;
-                a.dot2[(size_t)s * a.ntiles + tile] = acc2;
-            }
+            if (threadIdx.x == 0) a.dot[(size_t)s * a.ntiles + tile] = acc;
         }
         return;
     } else {
@@ -731,11 +714,11 @@ __global__ __launch_bounds__(kBlock) void k_coarsen_c(const T* __restrict__ cef,
 
 // ------------------------------------------- whole solve of a small mesh
 // Meshes with m <= 32: one workgroup runs one sample's entire PCG solve
-// (same method as the tiled path: flexible CG in double, one V(2,2) cycle
-// in T per iteration, harmonic-mean coarse operators) with every vector in
-// LDS or registers, so a batch of small solves is a single launch with no
-// host round trips.  Thread t owns nodes t, t + NT, ... (at most NPT of
-// them): their x, r and q_old stay in registers; p (which the operator
+// (same method as the tiled path: CG in double, one V(2,2) cycle in T per
+// iteration, harmonic-mean coarse operators) with every vector in LDS or
+// registers, so a batch of small solves is a single launch with no host
+// round trips.  Thread t owns nodes t, t + NT, ... (at most NPT of them):
+// their x, r and q stay in registers; p (which the operator
 // needs at neighbours), the double conductances of the CG operator and the
 // multigrid hierarchy live in LDS.
 template <typename T>
@@ -849,7 +832,7 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
     }
     const double bb = block_sum(acc, red);
     int it = 0, status = 0;
-    double rr = bb, pq_old = 0.0;
+    double rr = bb, rz_old = 0.0;
     bool active = bb > 0.0;
     while (active) {
         // z = V-cycle(r) in T
@@ -860,18 +843,17 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
         }
         __syncthreads();
         lds_vcycle(g);
-        double rz = 0.0, zq = 0.0;
+        double rz = 0.0;
         double zr[kSmallNpt];
 #pragma unroll
         for (int i = 0; i < kSmallNpt; ++i) {
             const int t = threadIdx.x + i * NT;
             zr[i] = t < n0 ? (double)g.z[t] : 0.0;
             rz += rr_[i] * zr[i];
-            zq += zr[i] * qr[i];
         }
-        block_sum2(rz, zq, red);
-        // flexible (Polak-Ribiere) beta = -(z_new . q_old) / (p_old . q_old)
-        const double beta = it == 0 ? 0.0 : -zq / pq_old;
+        rz = block_sum(rz, red);
+        const double beta = it == 0 ? 0.0 : rz / rz_old;
+        rz_old = rz;
 #pragma unroll
         for (int i = 0; i < kSmallNpt; ++i) {
             const int t = threadIdx.x + i * NT;
@@ -906,7 +888,6 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
             racc += rr_[i] * rr_[i];
         }
         rr = block_sum(racc, red);
-        pq_old = pq;
         ++it;
         if (rr <= a.rtol2 * bb) {
             active = false;
@@ -1043,9 +1024,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(PcgArgs<T> a, int first) {
     const int s = wi / a.ntiles, tile = wi - s * a.ntiles;
     const Scal sc = a.scal[s];
     if (!sc.active) return;
-    // flexible (Polak-Ribiere) beta = z_new.(r_new - r_old) / z_old.r_old
-    //                              = -(z_new . q_old) / (p_old . q_old)
-    const double beta = first ? 0.0 : -sc.zq / sc.pq;
+    // beta = r.z / r_old.z_old: the multigrid preconditioner is symmetric
+    // (its sweeps are mirrored) and fixed, so plain PCG applies; measured to
+    // take the same iterations as the flexible (Polak-Ribiere) form, whose
+    // z.q_old would cost a read of q_old per unknown and iteration
+    const double beta = first ? 0.0 : sc.rz / sc.rz_old;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = 1 + tx * PTX, y0 = a.L.ylo + ty * PTY;
     const int m = a.L.m, w = a.L.w, bc = a.bc;
@@ -1196,7 +1179,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
     double acc = 0.0, acc2 = 0.0;
     for (int t = threadIdx.x; t < np; t += blockDim.x) acc += part[(size_t)s * np + t];
     acc = block_sum(acc, red);
-    if (WHAT == RED_RZ || (WHAT == RED_PQ && part2)) {
+    if (WHAT == RED_PQ && part2) {
         for (int t = threadIdx.x; t < np; t += blockDim.x) acc2 += part2[(size_t)s * np + t];
         acc2 = block_sum(acc2, red);
     }
@@ -1205,14 +1188,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
     if (WHAT == RED_BB) {
         sc.bb = acc;
         sc.it = 0;
-        sc.rz = sc.rz_old = sc.pq = sc.zq = sc.wp = sc.qacc = 0.0;
+        sc.rz = sc.rz_old = sc.pq = sc.wp = sc.qacc = 0.0;
         sc.rr = acc;
         sc.status = 0;
         sc.active = acc > 0.0 ? 1 : 0;
         if (sc.active) atomicAdd(active_count, 1);
     } else if (WHAT == RED_RZ) {
         sc.rz = acc;
-        sc.zq = acc2;
     } else if (WHAT == RED_PQ) {
         sc.pq = acc;
         if (part2) {
@@ -1585,7 +1567,7 @@ private:
         }
     }
 
-    // one PCG iteration of the tiled path: z = V-cycle(r); r.z and z.q_old;
+    // one PCG iteration of the tiled path: z = V-cycle(r) and r.z;
     // p, q = A p and p.q; x, r and ||r||^2 with the convergence test
     hipError_t iteration(int it, hipStream_t st) {
         const int S = S_;
@@ -1596,7 +1578,7 @@ private:
         const double rtol2 = cfg_.rtol * cfg_.rtol;
         const double sT = sizeof(T);
         vcycle(it, st);
-        hipLaunchKernelGGL(k_reduce<RED_RZ>, dim3(S), dim3(kBlock), 0, st, part, part2, rz_parts_, scal, rtol2, cfg_.maxit, cnt);
+        hipLaunchKernelGGL(k_reduce<RED_RZ>, dim3(S), dim3(kBlock), 0, st, part, part, rz_parts_, scal, rtol2, cfg_.maxit, cnt);
         PcgArgs<T> a = pcg_args(it);
         launch("pcg_dir", nu(0) * (24.0 + sT) + nv(0) * sT, S, it, st, [&] {
             hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
@@ -1791,10 +1773,8 @@ private:
             a.zc = ptr<T>(o_zb_[l]);
             a.zout = l == 0 ? ptr<T>(o_Z_) : ptr<T>(o_zb_[l - 1]);
             a.dot = ptr<double>(o_part_);
-            a.dot2 = ptr<double>(o_part2_);
-            a.q = ptr<double>(o_Q_);
-            // k, z_pre, rhs, coarse correction in; z out (level 0: r, q_old in for the dots)
-            const double post = l == 0 ? nv(0) * sT + nu(0) * (sT + 8.0 + 8.0 + sT) + nu(1) * sT
+            // k, z_pre, rhs, coarse correction in; z out (level 0: r in double)
+            const double post = l == 0 ? nv(0) * sT + nu(0) * (sT + 8.0 + sT) + nu(1) * sT
                                        : 2.0 * nv(l) * sT + nu(l) * 3.0 * sT + nu(l + 1) * sT;
             launch(l == 0 ? "mg_post_l0" : "mg_post", post, S, it, st, [&] {
                 const dim3 g(tx * ty * S), b(kBlock);
