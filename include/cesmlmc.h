@@ -93,7 +93,9 @@ typedef struct {
     int32_t m_fine;        /* intervals per side, h = 1/m_fine; power of two, 4..4096 */
     int32_t level_kind;    /* CES_LEVEL_*; PAIR needs m_fine >= 8 */
     int64_t tau_fine;      /* eigenvalues dropped for the fine-mesh field; -1 = n (sqrt(s)) */
-    int64_t tau_coarse;    /* eigenvalues dropped for the coarse-mesh field; -1 = n */
+    int64_t tau_coarse;    /* eigenvalues dropped for the coarse-mesh field; -1 = n.  A PAIR
+                              level with tau_fine != tau_coarse draws two fields from one xi
+                              and needs n <= 4096 (CES_ERR_ARG otherwise) */
     int32_t psd_policy;    /* CES_PSD_* */
     int32_t periodization; /* CES_PERIOD_* */
     int32_t max_pad_factor;/* cap on n / m_fine for GROW (2..4) */

@@ -203,6 +203,11 @@ int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* A,
     if (p->tau_f > s || p->tau_c > s) return fail(CES_ERR_ARG, "tau exceeds the number of eigenvalues");
     p->is_double = desc->precision == CES_PREC_FP64;
     p->nf = (desc->level_kind == CES_LEVEL_PAIR && p->tau_f != p->tau_c) ? 2 : 1;
+    // two DFTs of one xi share a workgroup's LDS: 2 n complex values fit
+    // up to n = 4096
+    if (p->nf == 2 && n > 4096)
+        return fail(CES_ERR_ARG, "a pair level whose fine and coarse drop counts differ needs an embedding of at "
+                                 "most 4096 per axis (this one has " + std::to_string(n) + ")");
     p->fp = make_fft_plan(n);
     DevBuf kf_d, kc_d;
     if (p->tau_f > 0 || p->tau_c > 0) {

@@ -256,3 +256,38 @@ def test_c5_full_size_field_and_flux_balance(ctx, ces):
     q = oqoi.outflux(uu, m, A, b)
     assert abs(q - outflux) <= 1e-12 * abs(q)
     assert abs(y[0] - q) <= 1e-6 * abs(q)
+
+
+@pytest.mark.timeout(400)   # the oracle's normals and DFT at 8192^2 take about a minute of CPU
+def test_largest_mesh(ctx, ces):
+    """The largest mesh a descriptor allows (4097^2 vertices, embedding
+    8192^2, separable exponential: no padding): the field of a sample
+    against the oracle's, and converged solves whose QoI agrees between
+    the mixed and the FP64 path to the mixed bar.  Every kernel runs at
+    its largest index range."""
+    w = dict(cov="sepexp", lam=0.05, m=4096)
+    p = mkplan(ctx, ces, w)
+    o = oracle_plan(w)
+    assert (p.info.n, p.info.J) == (o.n, o.J) == (8192, 0)
+    zf, _ = p.field(0, 1)
+    z = zf.cpu().numpy()
+    zr, _ = o.fields(0, 1)
+    assert np.max(np.abs(z - zr)) <= 1e-5 * np.max(np.abs(zr))
+    del zf, z, zr, o
+    out = p.sample(0, 0, 2)
+    p64 = mkplan(ctx, ces, dict(w, precision="fp64"))
+    out64 = p64.sample(0, 0, 2)
+    torch.cuda.synchronize()
+    for r in (out, out64):
+        assert np.all(r["status"].cpu().numpy() == 0)
+        it = r["iters"].cpu().numpy()
+        assert np.all((it > 0) & (it < 60)), it
+    y, y64 = out["y"].cpu().numpy(), out64["y"].cpu().numpy()
+    assert np.max(np.abs(y - y64)) <= 1e-6 * np.max(np.abs(y64))
+
+
+def test_two_field_pair_level_beyond_4096_is_rejected(ctx, ces):
+    # the finest level of the smoothed estimator at m = 4096 draws two fields
+    w = dict(cov="sepexp", lam=0.05, m=4096, level="pair", tau_fine=0, tau_coarse=-1)
+    with pytest.raises(ces.CesError):
+        mkplan(ctx, ces, w)
