@@ -78,6 +78,19 @@ enum { CES_BC_DIRICHLET0 = 0, CES_BC_FLOWCELL = 1 };
 /* QoIs of Sections 3.1 and 4 on the P1 solution: integral of u,
  * u(qoi_x, qoi_y), L2 norm, outward flux through x1 = 1. */
 enum { CES_QOI_INTEGRAL = 0, CES_QOI_POINT = 1, CES_QOI_L2 = 2, CES_QOI_OUTFLUX = 3 };
+/* Coarse field of a PAIR level.  RESTRICT: the fine embedding's field (with
+ * tau_coarse) at the even nodes (Algorithm 1 step 4(e)).  EMBED: the
+ * coarse mesh's own embedding, as a SINGLE plan of mesh 2h with tau_fine =
+ * tau_coarse would set it up, driven by the fine normals of the nearest
+ * signed frequencies: per axis, coarse index j (signed k = j or j - n_c,
+ * period n_c 2h) takes the fine xi at round(k n_f / (2 n_c)) mod n_f (fine
+ * period n_f h; ties upwards; the identity on signed frequencies when
+ * n_f = 2 n_c).  The selection is injective when n_f >= 2 n_c, so the
+ * coarse term has exactly the law of the next coarser level's fine term
+ * and the smoothed estimator (eq. (mlmc-estimator-smoothed)) telescopes
+ * exactly; plan creation fails with CES_ERR_ARG when n_f < 2 n_c (the
+ * coarse mesh padded relatively more than the fine one). */
+enum { CES_COUPLE_RESTRICT = 0, CES_COUPLE_EMBED = 1 };
 
 typedef struct ces_context_s* ces_context;
 typedef struct ces_plan_s* ces_plan;
@@ -103,6 +116,7 @@ typedef struct {
     int32_t precision;     /* CES_PREC_* */
     int32_t bc;            /* CES_BC_* */
     int32_t qoi;           /* CES_QOI_* */
+    int32_t coupling;      /* CES_COUPLE_* (PAIR levels; 0 otherwise) */
     double qoi_x, qoi_y;   /* point of CES_QOI_POINT */
     double f_value;        /* constant source term f */
     double cg_rtol;        /* stop when ||r||_2 <= cg_rtol ||r_0||_2 */
@@ -121,7 +135,7 @@ typedef struct {
     double boundary_gap;   /* relative gap between the last kept and the first
                               dropped eigenvalue of the coarse mask (0 if tie) */
     int32_t mg_levels;     /* multigrid levels of the fine solve */
-    int32_t reserved;
+    int32_t n_coarse;      /* embedding size per axis of the coarse field (n unless EMBED) */
     size_t bytes_per_sample; /* device workspace per in-flight sample */
 } ces_plan_info;
 

@@ -14,6 +14,12 @@ Restriction (step 4(e)): the fine field is v[p1, p2] for 0 <= p1, p2 <= m
 of the mesh with spacing 2h takes the even nodes (2 i1, 2 i2).  Step 4(f):
 k = exp(Z).
 
+EMBED coupling (the coarse term drawn from the coarse mesh's own
+embedding, so that the smoothed estimator telescopes): the coarse
+embedding's xi takes the fine xi at the nearest signed frequencies
+(embedded_xi); the selection is injective when n_f >= 2 n_c, so its law is
+that of an independent draw.
+
 Pins (tests/test_oracle_field.py): the linear map xi -> Z satisfies
 A A^T = R exactly (covariance identity of Section 2.1); tau = 0 gives the
 unsmoothed field bitwise; tau = s gives zero; empirical covariance of many
@@ -51,6 +57,24 @@ def fields(a, xi_, m, mode):
     if mode == PAIR:
         return [v.real.copy(), v.imag.copy()]
     return [v.real + v.imag]
+
+
+def embedded_index(n_c, n_f):
+    """Fine embedding index (per axis) of each coarse embedding index of
+    the EMBED coupling: the fine signed frequency nearest to the coarse one
+    (coarse period n_c * 2h, fine period n_f * h), ties upwards, mod n_f."""
+    j = np.arange(n_c, dtype=np.int64)
+    k = np.where(j < n_c // 2, j, j - n_c)
+    # round(k * n_f / (2 n_c)) with ties upwards, in integers
+    f = np.floor_divide(2 * k * n_f + 2 * n_c, 4 * n_c)
+    return np.where(f >= 0, f, f + n_f)
+
+
+def embedded_xi(xi_f, n_c):
+    """Normals of the coarse embedding taken from the fine embedding's xi
+    (indexed [j2, j1]) at the same signed frequencies."""
+    idx = embedded_index(n_c, xi_f.shape[0])
+    return xi_f[np.ix_(idx, idx)]
 
 
 def restrict_coarse(z):

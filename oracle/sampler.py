@@ -13,13 +13,18 @@ field solved on the coarse mesh.  Reading of eq. (mlmc-estimator-smoothed)
 (listed in the design doc): on levels l < L both use tau_l; on the finest level
 L the fine term is unsmoothed (tau_f = 0) and the coarse term keeps tau_L;
 when tau_f != tau_c the two fields come from two DFTs of the same xi.
+With coupling EMBED the coarse field instead comes from the coarse mesh's
+own embedding (as a single level of mesh 2h with drop count tau_c) driven
+by the fine xi at the same signed frequencies, so that the coarse term of
+level l has the law of the fine term of level l-1 and the smoothed sum
+telescopes exactly.
 
 Sample index i maps to pair q = floor(i/2), component i mod 2 in PAIR field
 mode, and to q = i in HARTLEY field mode.
 
 desc keys: cov, nu, lam, sigma2, m, level (0 SINGLE / 1 PAIR), tau_f,
 tau_c (-1 = default n), psd, period, max_pad, field_mode, bc, qoi, qx, qy,
-f, stream.
+f, stream, coupling (0 RESTRICT / 1 EMBED).
 """
 
 import numpy as np
@@ -28,6 +33,8 @@ from . import embedding, field, fem, qoi
 
 SINGLE = 0
 PAIR_LEVEL = 1
+RESTRICT = 0
+EMBED = 1
 
 
 class Plan:
@@ -45,8 +52,18 @@ class Plan:
         tc = self.desc.get("tau_c", 0)
         self.tau_f = embedding.tau_default(n) if tf < 0 else int(tf)
         self.tau_c = embedding.tau_default(n) if tc < 0 else int(tc)
+        self.coarse_plan = None
+        if self.desc.get("coupling", 0) == EMBED and self.desc.get("level", SINGLE) == PAIR_LEVEL:
+            # the coarse term from the coarse mesh's own embedding (a single
+            # level of mesh 2h with the coarse drop count)
+            cd = dict(self.desc, m=self.desc["m"] // 2, level=SINGLE, tau_f=tc, tau_c=tc, coupling=0)
+            self.coarse_plan = Plan(cd)
+            if n < 2 * self.coarse_plan.n:
+                raise ValueError("EMBED coupling needs a fine embedding period at least the coarse one's")
+            self.tau_c = self.coarse_plan.tau_f
         self.keep_f = embedding.mask(self.lam, self.tau_f)
-        self.keep_c = embedding.mask(self.lam, self.tau_c)
+        # the fine embedding's coarse-mesh field (RESTRICT only)
+        self.keep_c = self.keep_f if self.coarse_plan is not None else embedding.mask(self.lam, self.tau_c)
         self.a_f = embedding.amplitudes(self.lam, self.keep_f)
         self.a_c = embedding.amplitudes(self.lam, self.keep_c)
 
@@ -63,6 +80,9 @@ class Plan:
         zf = field.fields(self.a_f, xi, m, mode)[comp]
         if d.get("level", SINGLE) == SINGLE:
             return zf, None
+        if self.coarse_plan is not None:
+            cp = self.coarse_plan
+            return zf, field.fields(cp.a_f, field.embedded_xi(xi, cp.n), m // 2, mode)[comp]
         if self.tau_c == self.tau_f:
             zc_full = zf
         else:

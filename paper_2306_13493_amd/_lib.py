@@ -30,7 +30,7 @@ class LevelDesc(ctypes.Structure):
         ("sigma2", c_double), ("m_fine", c_int32), ("level_kind", c_int32), ("tau_fine", c_int64),
         ("tau_coarse", c_int64), ("psd_policy", c_int32), ("periodization", c_int32),
         ("max_pad_factor", c_int32), ("field_mode", c_int32), ("precision", c_int32), ("bc", c_int32),
-        ("qoi", c_int32), ("qoi_x", c_double), ("qoi_y", c_double), ("f_value", c_double),
+        ("qoi", c_int32), ("coupling", c_int32), ("qoi_x", c_double), ("qoi_y", c_double), ("f_value", c_double),
         ("cg_rtol", c_double), ("cg_max_iter", c_int32), ("stream", c_uint32)]
 
 
@@ -38,7 +38,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("n", c_int32), ("J", c_int32), ("lam_min", c_double), ("lam_max", c_double),
         ("n_clamped", c_int64), ("tau_fine", c_int64), ("tau_coarse", c_int64),
-        ("boundary_gap", c_double), ("mg_levels", c_int32), ("reserved", c_int32),
+        ("boundary_gap", c_double), ("mg_levels", c_int32), ("n_coarse", c_int32),
         ("bytes_per_sample", c_size_t)]
 
 

@@ -142,6 +142,9 @@ int validate_desc(const ces_level_desc* d) {
         return fail(CES_ERR_ARG, "qoi point outside the unit square");
     if (!(d->cg_rtol > 0.0) || d->cg_max_iter < 1) return fail(CES_ERR_ARG, "cg_rtol / cg_max_iter");
     if (d->tau_fine < -1 || d->tau_coarse < -1) return fail(CES_ERR_ARG, "tau must be >= -1");
+    if (d->coupling != CES_COUPLE_RESTRICT && d->coupling != CES_COUPLE_EMBED) return fail(CES_ERR_ARG, "coupling");
+    if (d->coupling == CES_COUPLE_EMBED && d->level_kind != CES_LEVEL_PAIR)
+        return fail(CES_ERR_ARG, "coupling EMBED applies to PAIR levels");
     return CES_OK;
 }
 
@@ -197,12 +200,32 @@ int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* A,
     p->n_clamped = nneg;
     const int n = p->n;
     const int64_t s = (int64_t)n * n;
+    const bool embed = desc->coupling == CES_COUPLE_EMBED;
     p->tau_f = desc->tau_fine < 0 ? n : desc->tau_fine;
     p->tau_c = desc->tau_coarse < 0 ? n : desc->tau_coarse;
     if (desc->level_kind == CES_LEVEL_SINGLE) p->tau_c = p->tau_f;
-    if (p->tau_f > s || p->tau_c > s) return fail(CES_ERR_ARG, "tau exceeds the number of eigenvalues");
+    if (embed) {
+        // the coarse field comes from the coarse mesh's own embedding: a
+        // SINGLE plan of mesh 2h with the coarse drop count
+        ces_level_desc cd = *desc;
+        cd.m_fine = m / 2;
+        cd.level_kind = CES_LEVEL_SINGLE;
+        cd.tau_fine = cd.tau_coarse = desc->tau_coarse;
+        cd.coupling = CES_COUPLE_RESTRICT;
+        ces_plan child = nullptr;
+        rc = plan_create(ctx, &cd, A, st, &child, false);
+        if (rc != CES_OK) return rc;
+        p->cpl.reset(child);
+        if (n < 2 * child->n)
+            return fail(CES_ERR_ARG, "coupling EMBED needs a fine embedding period at least the coarse one's (fine "
+                                     "n = " + std::to_string(n) + ", coarse n = " + std::to_string(child->n) + ")");
+        p->tau_c = child->tau_f;
+    }
+    // drop count of a second fine-embedding field (RESTRICT pairs only)
+    const int64_t tau_c2 = embed ? p->tau_f : p->tau_c;
+    if (p->tau_f > s || tau_c2 > s) return fail(CES_ERR_ARG, "tau exceeds the number of eigenvalues");
     p->is_double = desc->precision == CES_PREC_FP64;
-    p->nf = (desc->level_kind == CES_LEVEL_PAIR && p->tau_f != p->tau_c) ? 2 : 1;
+    p->nf = (desc->level_kind == CES_LEVEL_PAIR && p->tau_f != tau_c2) ? 2 : 1;
     // two DFTs of one xi share a workgroup's LDS: 2 n complex values fit
     // up to n = 4096
     if (p->nf == 2 && n > 4096)
@@ -210,29 +233,30 @@ int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* A,
                                  "most 4096 per axis (this one has " + std::to_string(n) + ")");
     p->fp = make_fft_plan(n);
     DevBuf kf_d, kc_d;
-    if (p->tau_f > 0 || p->tau_c > 0) {
+    if (p->tau_f > 0 || tau_c2 > 0) {
         // masks: the host orders the clamped eigenvalues
         std::vector<double> lam(s);
         CES_HIP(hipMemcpyAsync(lam.data(), p->lam.p, (size_t)s * 8, hipMemcpyDeviceToHost, st), "eigenvalues");
         CES_HIP(hipStreamSynchronize(st), "plan set-up");
         for (double& v : lam) v = std::max(v, 0.0);
         std::vector<int64_t> order;
-        smallest_order(lam, std::max(p->tau_f, p->tau_c), order);
+        smallest_order(lam, std::max(p->tau_f, tau_c2), order);
         p->keep_f.assign(s, 1);
         p->keep_c.assign(s, 1);
         for (int64_t i = 0; i < p->tau_f; ++i) p->keep_f[order[i]] = 0;
-        for (int64_t i = 0; i < p->tau_c; ++i) p->keep_c[order[i]] = 0;
-        if (p->tau_c > 0 && p->tau_c < s) {
+        for (int64_t i = 0; i < tau_c2; ++i) p->keep_c[order[i]] = 0;
+        if (tau_c2 > 0 && tau_c2 < s) {
             double kept_min = 1e308;
             for (int64_t i = 0; i < s; ++i)
                 if (p->keep_c[i]) kept_min = std::min(kept_min, lam[i]);
-            p->gap = (kept_min - lam[order[p->tau_c - 1]]) / std::max(p->lam_max, 1e-300);
+            p->gap = (kept_min - lam[order[tau_c2 - 1]]) / std::max(p->lam_max, 1e-300);
         }
         CES_HIP(kf_d.alloc((size_t)s, A), "mask buffers");
         CES_HIP(kc_d.alloc((size_t)s, A), "mask buffers");
         CES_HIP(hipMemcpyAsync(kf_d.p, p->keep_f.data(), (size_t)s, hipMemcpyHostToDevice, st), "masks");
         CES_HIP(hipMemcpyAsync(kc_d.p, p->keep_c.data(), (size_t)s, hipMemcpyHostToDevice, st), "masks");
     }
+    if (embed) p->gap = p->cpl->gap;   // the coarse field's mask is the coarse plan's
     const size_t tb = p->is_double ? 8 : 4;
     CES_HIP(p->af.alloc((size_t)s * tb, A), "amplitude buffers");
     if (p->nf == 2) CES_HIP(p->ac.alloc((size_t)s * tb, A), "amplitude buffers");
@@ -361,6 +385,7 @@ int ces_plan_info_get(ces_plan p, ces_plan_info* info) {
     int lv = 0;
     for (int mm = p->d.m_fine; mm >= 2; mm /= 2) ++lv;
     info->mg_levels = lv;
+    info->n_coarse = p->cpl ? p->cpl->n : p->n;
     info->bytes_per_sample = slot_bytes(p);
     return CES_OK;
 }

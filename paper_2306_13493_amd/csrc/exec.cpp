@@ -248,7 +248,8 @@ FieldBatch<T> field_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
     b.m = p->d.m_fine;
     b.mode = p->d.field_mode == CES_FIELD_PAIR ? MODE_PAIR : MODE_HARTLEY;
     b.nf = p->nf;
-    b.coarse = p->d.level_kind == CES_LEVEL_PAIR;
+    // EMBED pairs draw the coarse field in a second batch (embedded_batch)
+    b.coarse = p->d.level_kind == CES_LEVEL_PAIR && !p->cpl;
     b.af = p->af.as<T>();
     b.ac = p->nf == 2 ? p->ac.as<T>() : p->af.as<T>();
     b.tw = p->tw.as<cplx<T>>();
@@ -265,6 +266,35 @@ FieldBatch<T> field_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
     return b;
 }
 
+// CES_COUPLE_EMBED: the coarse field of the same units from the coarse
+// plan's amplitudes, its normals taken from the fine embedding's counters;
+// written as that plan's fine field into the pair's coarse coefficients.
+// It reuses the fine batch's intermediate buffer, so it must be enqueued
+// after the fine batch on the same stream.
+template <typename T>
+FieldBatch<T> embedded_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
+    const ces_plan c = p->cpl.get();
+    FieldBatch<T> b;
+    b.n = c->n;
+    b.m = c->d.m_fine;
+    b.mode = p->d.field_mode == CES_FIELD_PAIR ? MODE_PAIR : MODE_HARTLEY;
+    b.nf = 1;
+    b.coarse = false;
+    b.af = c->af.as<T>();
+    b.ac = b.af;
+    b.tw = c->tw.as<cplx<T>>();
+    b.fp = c->fp;
+    b.seed = seed;
+    b.q0 = q0;
+    b.stream = p->d.stream;
+    b.units = units;
+    b.work = p->work.as<cplx<T>>();
+    b.kf = p->kc.as<T>();
+    b.kf_stride = p->kc_ss;
+    b.n_src = p->n;
+    return b;
+}
+
 template <typename T>
 int field_t(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, hipStream_t st) {
     const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
@@ -278,6 +308,11 @@ int field_t(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, 
     b.zf = p->zf.as<double>();
     b.zc = p->zc.as<double>();
     CES_HIP(launch_field<T>(b, st), "field kernels");
+    if (p->cpl) {
+        FieldBatch<T> c = embedded_batch<T>(p, seed, pair_field ? sample / 2 : sample, 1);
+        c.zf = p->zc.as<double>();
+        CES_HIP(launch_field<T>(c, st), "coarse field kernels");
+    }
     const int comp = pair_field ? (int)(sample % 2) : 0;
     CES_HIP(hipMemcpyAsync(zf, p->zf.as<double>() + comp * nf, nf * 8, hipMemcpyDeviceToDevice, st), "copy field");
     if (zc && p->d.level_kind == CES_LEVEL_PAIR)
@@ -457,6 +492,7 @@ int Scheduler::start_t(Lane& L, const Job& j) {
     const int nslots = j.units * per_unit;
     FieldBatch<T> b = field_batch<T>(p, j.seed, j.u0, j.units);
     CES_HIP(launch_field<T>(b, L.sa), "field kernels");
+    if (p->cpl) CES_HIP(launch_field<T>(embedded_batch<T>(p, j.seed, j.u0, j.units), L.sa), "coarse field kernels");
     CES_HIP(p->sf->begin(p->kf.p, p->kf_ss, nslots, L.sa, false), "fine solve");
     if (p->sc) {
         CES_HIP(hipEventRecord(L.ev_f, L.sa), "lane event");

@@ -32,6 +32,17 @@ __device__ __forceinline__ float dev_exp<float>(float z) { return expf(z); }
 template <>
 __device__ __forceinline__ double dev_exp<double>(double z) { return exp(z); }
 
+// Index of the source embedding (size ns, period ns h_s) whose signed
+// frequency is nearest to that of index j of an embedding of size n on the
+// mesh of twice the spacing (period 2 n h_s): round(k * ns / (2 n)) with
+// k = j or j - n, ties upwards, taken mod ns.  Injective for ns >= 2 n.
+__device__ __forceinline__ int src_index(int j, int n, int ns) {
+    const long long k = j < n / 2 ? j : j - n;
+    const long long num = 2 * k * ns + 2LL * n, den = 4LL * n;
+    const long long f = num >= 0 ? num / den : -((-num + den - 1) / den);
+    return (int)(f >= 0 ? f : f + ns);
+}
+
 template <typename T, int E, int MODE, int NF>
 __global__ __launch_bounds__(kBlock) void k_field_rows(FieldBatch<T> b, int L) {
     extern __shared__ unsigned char smem_raw[];
@@ -43,15 +54,18 @@ __global__ __launch_bounds__(kBlock) void k_field_rows(FieldBatch<T> b, int L) {
     for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
         const int line = t / n;
         const int j1 = t - line * n;
-        const uint32_t e = (uint32_t)j1 + (uint32_t)n * (uint32_t)(j2_0 + line);
+        const int j2 = j2_0 + line;
+        const uint32_t ia = (uint32_t)j1 + (uint32_t)n * (uint32_t)j2;   // amplitude index
+        uint32_t e = ia;                                                  // normal counter
+        if (b.n_src > 0) e = (uint32_t)src_index(j1, n, b.n_src) + (uint32_t)b.n_src * (uint32_t)src_index(j2, n, b.n_src);
         double g0, g1;
         normal_pair(b.seed, q, b.stream, e, g0, g1);
         const double xr = g0;
         const double xi = (MODE == MODE_PAIR) ? g1 : 0.0;
-        const double a = (double)b.af[e];
+        const double a = (double)b.af[ia];
         buf[line * n + j1] = cplx<T>{(T)(a * xr), (T)(a * xi)};
         if constexpr (NF == 2) {
-            const double c = (double)b.ac[e];
+            const double c = (double)b.ac[ia];
             buf[(L + line) * n + j1] = cplx<T>{(T)(c * xr), (T)(c * xi)};
         }
     }

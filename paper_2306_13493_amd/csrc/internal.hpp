@@ -85,6 +85,9 @@ struct FieldBatch {
     T* kc = nullptr; long long kc_stride = 0;   // exp(Z) on (m/2+1)^2 nodes
     double* zf = nullptr;    // if set: Z (not exp) as double, stride (m+1)^2
     double* zc = nullptr;    // if set: Z coarse as double, stride (m/2+1)^2
+    // > 0: draw the normals of the embedding of size n_src of the mesh with
+    // half this one's spacing, at the nearest signed frequencies
+    int n_src = 0;
 };
 template <typename T>
 hipError_t launch_field(const FieldBatch<T>& b, hipStream_t st);

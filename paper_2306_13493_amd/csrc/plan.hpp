@@ -120,6 +120,10 @@ struct ces_plan_s {
     long long kf_ss = 0, kc_ss = 0;
     std::unique_ptr<ces::Solver> sf, sc;
     size_t ws_bytes = 0;
+    // CES_COUPLE_EMBED: the coarse mesh's own embedding (a SINGLE plan of
+    // mesh 2h with the coarse drop count); its amplitudes drive the coarse
+    // field, its workspace is never used
+    std::unique_ptr<ces_plan_s> cpl;
     std::atomic<int> busy{0};           // a scheduler is using the workspace
     // recorded after the last work that used the workspace; the next lane
     // of this plan waits for it (lanes of successive calls may run on

@@ -81,6 +81,7 @@ _ENUMS = {
     "field": {"pair": 0, "hartley": 1},
     "bc": {"dirichlet0": 0, "flowcell": 1},
     "qoi": {"integral": 0, "point": 1, "l2": 2, "outflux": 3},
+    "coupling": {"restrict": 0, "embed": 1},
 }
 
 
@@ -94,4 +95,4 @@ def to_oracle(w):
                 tau_c=w.get("tau_coarse", 0), psd=e("psd", "grow"), period=e("period", "euclid"),
                 max_pad=w.get("max_pad", 4), field_mode=e("field", "pair"), bc=e("bc", "dirichlet0"),
                 qoi=e("qoi", "integral"), qx=w.get("qoi_x", 7.0 / 15.0), qy=w.get("qoi_y", 7.0 / 15.0),
-                f=w.get("f", 1.0), stream=w.get("stream", 0))
+                f=w.get("f", 1.0), stream=w.get("stream", 0), coupling=e("coupling", "restrict"))

@@ -109,6 +109,12 @@ FIELD_CASES = {
     "hartley_pair_level": dict(cov="matern", nu=1.5, lam=0.2, m=16, level="pair", field="hartley"),
     "padded_n96": dict(cov="matern", nu=0.5, lam=0.3, m=32, level="pair", stream=3),
     "c2_size": dict(W.C2),
+    # coarse field from the coarse mesh's own embedding (EMBED coupling)
+    "embed_smoothed": dict(cov="matern", nu=1.5, lam=0.2, m=16, level="pair", tau_fine=-1, tau_coarse=-1,
+                           coupling="embed"),
+    "embed_finest_form_hartley": dict(cov="matern", nu=1.0, lam=0.1, m=64, level="pair", tau_fine=0,
+                                      tau_coarse=-1, coupling="embed", field="hartley", stream=2),
+    "embed_padded": dict(cov="matern", nu=0.5, lam=0.3, m=32, level="pair", coupling="embed", stream=3),
 }
 
 
@@ -167,6 +173,12 @@ SAMPLE_CASES = {
                                 bc="flowcell", qoi="outflux", cg_rtol=1e-12), 4),
     "point_tiled_upper_triangle": (dict(cov="sepexp", lam=0.3, m=128, level="pair", qoi="point",
                                         qoi_x=0.3, qoi_y=0.71), 4),
+    # EMBED coupling: smoothed level (small meshes) and the finest-level
+    # form on a tiled mesh
+    "embed_smoothed_small": (dict(cov="matern", nu=1.5, lam=0.2, m=16, level="pair", tau_fine=-1,
+                                  tau_coarse=-1, coupling="embed"), 12),
+    "embed_finest_tiled": (dict(cov="matern", nu=1.0, lam=0.1, m=128, level="pair", tau_fine=0,
+                                tau_coarse=-1, coupling="embed"), 4),
     "integral_flowcell_tiled": (dict(cov="matern", nu=1.0, lam=0.1, m=64, bc="flowcell"), 6),
 }
 
@@ -291,3 +303,16 @@ def test_two_field_pair_level_beyond_4096_is_rejected(ctx, ces):
     w = dict(cov="sepexp", lam=0.05, m=4096, level="pair", tau_fine=0, tau_coarse=-1)
     with pytest.raises(ces.CesError):
         mkplan(ctx, ces, w)
+
+
+def test_embed_plan_info_and_coarse_embedding(ctx, ces):
+    w = dict(cov="matern", nu=0.5, lam=0.3, m=32, level="pair", coupling="embed", tau_coarse=-1)
+    p = mkplan(ctx, ces, w)
+    o = oracle_plan(w)
+    # 32^2 needs padding (n = 96), the 16^2 coarse mesh does not (n = 32)
+    assert (p.info.n, p.info.n_coarse) == (o.n, o.coarse_plan.n) == (96, 32)
+    assert p.info.tau_coarse == o.coarse_plan.tau_f == o.coarse_plan.n
+    r = mkplan(ctx, ces, dict(w, coupling="restrict"))
+    assert r.info.n_coarse == r.info.n
+    with pytest.raises(ces.CesError):
+        mkplan(ctx, ces, dict(w, level="single"))
