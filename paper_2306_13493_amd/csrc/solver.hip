@@ -159,12 +159,12 @@ __device__ __forceinline__ void mg_half_sweep(T (&z)[SH][2], const T (&rhs)[SH][
 // WHOLE: the level's unknowns fit in one region (Dirichlet boundary, m - 1
 // <= 64 columns and rows), so one workgroup per sample takes the level with
 // no halo: every sweep is exact on the region and nothing is recomputed.
-// RXW = 128 (float, levels >= 1 only): the same with 128 x 128 regions, a
-// workgroup of 16 waves of 64 lanes (lane k owns columns 2k, 2k+1 of its
-// wave's SH rows), for levels with m - 1 <= 128.
+// RXW = 128 (float only): the same with 128 x 128 regions, a workgroup of
+// 16 waves of 64 lanes (lane k owns columns 2k, 2k+1 of its wave's SH
+// rows), for Dirichlet levels with 64 < m - 1 <= 128.
 template <typename T, int SH, bool POST, bool L0, bool WHOLE, int RXW = 64>
 __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
-    static_assert(RXW == 64 || (RXW == 128 && WHOLE && !L0), "128-wide regions: whole coarse levels only");
+    static_assert(RXW == 64 || (RXW == 128 && WHOLE), "128-wide regions: whole levels only");
     constexpr int NT = RXW == 64 ? kBlock : 1024, LW = RXW / 2;
     constexpr int RX = RXW, NH = NT / LW, RY = NH * SH;
     constexpr int H = WHOLE ? 0 : (POST ? 4 : 6);
@@ -188,27 +188,36 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
     if constexpr (L0) {
         // all loads are issued before any is used (addresses clamped into
         // the mesh, values masked afterwards) so their latencies overlap
+        // lane l of wave wv takes padded columns l, l + 64, ... of rows
+        // wv, wv + NW, ... (the last chunk only where it is inside PX)
         const T* kk = a.k + (size_t)s * a.kss;
-        constexpr int NW = kBlock / 64, NIT = (PY + NW - 1) / NW;
+        constexpr int NW = NT / 64, NIT = (PY + NW - 1) / NW, NCW = (PX + 63) / 64;
         const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        const int col = l < PX - 64 ? 64 + l : l;   // lanes 0,1 also take the two last columns
-        const int gxa = ox - 1 + l, gxb = ox - 1 + col;
-        const int gxac = min(max(gxa, 0), m), gxbc = min(max(gxb, 0), m);
-        T ka[NIT], kb[NIT];
+        int gxc[NCW];
+        bool okx[NCW];
+#pragma unroll
+        for (int c = 0; c < NCW; ++c) {
+            const int gx = ox - 1 + 64 * c + l;
+            gxc[c] = min(max(gx, 0), m);
+            okx[c] = gx >= 0 && gx <= m;
+        }
+        T kv[NIT][NCW];
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int gyc = min(max(oy - 1 + wv + i * NW, 0), m);
-            ka[i] = kk[gyc * w + gxac];
-            kb[i] = kk[gyc * w + gxbc];
+#pragma unroll
+            for (int c = 0; c < NCW; ++c) kv[i][c] = kk[gyc * w + gxc[c]];
         }
-        const bool oka = gxa >= 0 && gxa <= m, okb = gxb >= 0 && gxb <= m;
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int y = wv + i * NW, gy = oy - 1 + y;
             const bool oky = gy >= 0 && gy <= m;
             if (y < PY) {
-                sk[y * PX + l] = (oka && oky) ? ka[i] : T(0);
-                if (l < PX - 64) sk[y * PX + col] = (okb && oky) ? kb[i] : T(0);
+#pragma unroll
+                for (int c = 0; c < NCW; ++c) {
+                    const int col = 64 * c + l;
+                    if (col < PX) sk[y * PX + col] = (okx[c] && oky) ? kv[i][c] : T(0);
+                }
             }
         }
     }
@@ -1355,7 +1364,7 @@ public:
         itiles_ = itx_ * ity_;
         stx_ = cdiv(L0.m - 1, POST_TX);
         sty_ = cdiv(L0.yhi - L0.ylo + 1, POST_TY);
-        rz_parts_ = whole(0) ? 1 : stx_ * sty_;
+        rz_parts_ = (whole(0) || whole128(0)) ? 1 : stx_ * sty_;
         ublocks_ = (int)cdiv(L0.ss, kUpdChunk);
         max_parts_ = std::max(std::max(std::max(ptiles_, itiles_), rz_parts_), ublocks_);
         o_X_ = take(n0 * 8); o_R_ = take(n0 * 8); o_P0_ = take(n0 * 8); o_P1_ = take(n0 * 8);
@@ -1708,9 +1717,9 @@ private:
     bool whole(int l) const {
         return cfg_.bc == BC_DIRICHLET0 && lv_[l].m - 1 <= 64 && lv_[l].m - 1 <= RYT;
     }
-    // a coarse level that fits one 128 x 128 region (float multigrid)
+    // a level that fits one 128 x 128 region (float multigrid)
     bool whole128(int l) const {
-        return sizeof(T) == 4 && l >= 1 && cfg_.bc == BC_DIRICHLET0 && lv_[l].m - 1 > 64 && lv_[l].m - 1 <= 128;
+        return sizeof(T) == 4 && cfg_.bc == BC_DIRICHLET0 && lv_[l].m - 1 > 64 && lv_[l].m - 1 <= 128;
     }
 
     void vcycle(int it, hipStream_t st) {
@@ -1730,7 +1739,8 @@ private:
                 const dim3 g(tx * ty * S), b(kBlock);
                 if constexpr (sizeof(T) == 4) {
                     if (w128) {
-                        hipLaunchKernelGGL((k_mg<T, SH, false, false, true, 128>), g, dim3(1024), 0, st, a);
+                        if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, false, true, true, 128>), g, dim3(1024), 0, st, a);
+                        else hipLaunchKernelGGL((k_mg<T, SH, false, false, true, 128>), g, dim3(1024), 0, st, a);
                         return;
                     }
                 }
@@ -1780,7 +1790,8 @@ private:
                 const dim3 g(tx * ty * S), b(kBlock);
                 if constexpr (sizeof(T) == 4) {
                     if (w128) {
-                        hipLaunchKernelGGL((k_mg<T, SH, true, false, true, 128>), g, dim3(1024), 0, st, a);
+                        if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, true, true, true, 128>), g, dim3(1024), 0, st, a);
+                        else hipLaunchKernelGGL((k_mg<T, SH, true, false, true, 128>), g, dim3(1024), 0, st, a);
                         return;
                     }
                 }

@@ -38,6 +38,9 @@ def level_desc(l, m0, smoothed, finest=False, **kw):
     if smoothed:
         w["tau_coarse"] = -1
         w["tau_fine"] = 0 if finest else -1
+        if smoothed == "embed" and l > 0:
+            # coarse terms from the next coarser level's own embedding
+            w["coupling"] = "embed"
     return w
 
 
@@ -53,7 +56,7 @@ def oracle_run(descs, finest_descs, seed, **opts):
     return omlmc.run(sample, cost, len(descs), finest_differs=fplans is not None, **opts)
 
 
-@pytest.mark.parametrize("smoothed", [False, True])
+@pytest.mark.parametrize("smoothed", [False, True, "embed"])
 def test_estimator_matches_oracle(ctx, ces, smoothed):
     n = 4
     descs = [level_desc(l, 8, smoothed) for l in range(n)]
