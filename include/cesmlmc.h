@@ -392,8 +392,9 @@ int ces_normals(uint64_t seed, uint64_t q, uint32_t stream, uint64_t first_e, in
 /* Symmetrised eigenvalues (n*n doubles, after clamping) into host memory. */
 int ces_plan_eigenvalues(ces_plan plan, double* host_out);
 
-/* Masks (n*n bytes, 1 = kept) of the fine and coarse fields; either may be
- * NULL. */
+/* Masks (1 = kept) of the fine field (n*n bytes) and of the coarse field
+ * (n*n bytes of the fine embedding; for EMBED pairs n_coarse*n_coarse bytes
+ * of the coarse embedding, see ces_plan_info); either may be NULL. */
 int ces_plan_mask(ces_plan plan, uint8_t* host_fine, uint8_t* host_coarse);
 
 /* Gaussian fields Z (before exp) of sample `sample`: z_fine_dev gets

@@ -204,9 +204,11 @@ class Plan:
         return a
 
     def masks(self):
-        n = self.n
+        """(fine, coarse) keep masks; the coarse one is on the coarse
+        embedding (n_coarse x n_coarse) for EMBED pairs."""
+        n, nc = self.n, self.info.n_coarse
         f = np.empty((n, n), dtype=np.uint8)
-        c = np.empty((n, n), dtype=np.uint8)
+        c = np.empty((nc, nc), dtype=np.uint8)
         check(self.lib.ces_plan_mask(self.handle, f.ctypes.data_as(ctypes.c_void_p),
                                      c.ctypes.data_as(ctypes.c_void_p)))
         return f, c

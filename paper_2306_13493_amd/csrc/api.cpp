@@ -423,8 +423,12 @@ int ces_plan_mask(ces_plan p, uint8_t* f, uint8_t* c) {
         else std::memcpy(f, p->keep_f.data(), s);
     }
     if (c) {
-        if (p->keep_c.empty()) std::memset(c, 1, s);
-        else std::memcpy(c, p->keep_c.data(), s);
+        // EMBED: the coarse field's mask lives on the coarse embedding
+        const ces_plan_s* q = p->cpl ? p->cpl.get() : p;
+        const std::vector<uint8_t>& kc = p->cpl ? q->keep_f : q->keep_c;
+        const size_t sc = (size_t)q->n * q->n;
+        if (kc.empty()) std::memset(c, 1, sc);
+        else std::memcpy(c, kc.data(), sc);
     }
     return CES_OK;
 }

@@ -312,6 +312,10 @@ def test_embed_plan_info_and_coarse_embedding(ctx, ces):
     # 32^2 needs padding (n = 96), the 16^2 coarse mesh does not (n = 32)
     assert (p.info.n, p.info.n_coarse) == (o.n, o.coarse_plan.n) == (96, 32)
     assert p.info.tau_coarse == o.coarse_plan.tau_f == o.coarse_plan.n
+    # the coarse mask hook returns the coarse embedding's mask
+    mf, mc = p.masks()
+    assert mf.shape == (96, 96) and mc.shape == (32, 32)
+    assert int((mc == 0).sum()) == o.coarse_plan.tau_f and int((mf == 0).sum()) == 0
     r = mkplan(ctx, ces, dict(w, coupling="restrict"))
     assert r.info.n_coarse == r.info.n
     with pytest.raises(ces.CesError):
