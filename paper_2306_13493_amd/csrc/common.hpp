@@ -1,6 +1,7 @@
 // Shared device/host helpers of the cesmlmc HIP library (gfx950).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>

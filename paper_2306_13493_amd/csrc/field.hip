@@ -219,22 +219,22 @@ hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2
     const double kout = slots * sT * ((double)(b.m + 1) * (b.m + 1) +
                                       (b.coarse ? (double)(b.m / 2 + 1) * (b.m / 2 + 1) : 0.0));
     Profiler& P = Profiler::get();
-    int idx = P.begin(st);
-    hipLaunchKernelGGL(kr, dim3(b.n / L1, b.units), dim3(kBlock), lds1, st, b, L1);
-    P.end(idx, "field_rows", (double)NF * b.n * b.n * sT + inter, 1, st);
+    Profiler::Slot ps = P.begin();
+    hipExtLaunchKernelGGL(kr, dim3(b.n / L1, b.units), dim3(kBlock), lds1, st, ps.a, ps.b, 0, b, L1);
+    P.end(ps, "field_rows", (double)NF * b.n * b.n * sT + inter, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     dim3 g2(cdiv(b.m + 1, L2), b.units, NF);
-    idx = P.begin(st);
+    ps = P.begin();
     if (b.zf) {
         auto kc = k_field_cols<T, E, MODE, NF, true>;
         if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
-        hipLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, b, L2);
+        hipExtLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, ps.a, ps.b, 0, b, L2);
     } else {
         auto kc = k_field_cols<T, E, MODE, NF, false>;
         if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
-        hipLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, b, L2);
+        hipExtLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, ps.a, ps.b, 0, b, L2);
     }
-    P.end(idx, "field_cols", inter + kout, 1, st);
+    P.end(ps, "field_cols", inter + kout, 1);
     return hipGetLastError();
 }
 

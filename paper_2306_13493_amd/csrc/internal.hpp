@@ -138,7 +138,7 @@ public:
     virtual hipError_t advance(hipStream_t st, int depth, bool graphs, bool* done, bool* progressed) = 0;
     // block until the oldest unconfirmed iteration has finished
     virtual hipError_t wait() = 0;
-    // bookkeeping after the solve (launch profiler only; may synchronise)
+    // bookkeeping after the solve (launch profiler only; host-side, no device wait)
     virtual hipError_t finish(hipStream_t st) = 0;
     // begin + advance to the end + finish
     hipError_t solve(const void* k, long long kstride, int S, hipStream_t st, int depth = 2) {
@@ -170,7 +170,7 @@ hipError_t launch_finalize(const double* qf, const double* qc, const int* itf, c
                            int* iters, int* status, hipStream_t st);
 
 // ------------------------------------------------------------- profiler
-// Process-wide; records HIP events around launches while enabled.
+// Process-wide; times launches with HIP events while enabled.
 // Thread-safe (a server's loop may launch while its owner reads).
 class Profiler {
 public:
@@ -180,11 +180,18 @@ public:
         double ms = 0.0;
         double bytes = 0.0;   // algorithmic bytes summed over launches
     };
+    // Events of one launch: passed to hipExtLaunchKernelGGL, which stamps
+    // them with the kernel's own start and end (no extra packets in the
+    // stream); both null and idx = -1 when the profiler is off.
+    struct Slot {
+        int idx = -1;
+        hipEvent_t a = nullptr, b = nullptr;
+    };
     static Profiler& get();
     bool on() const { return on_.load(std::memory_order_relaxed); }
     void enable(bool on);
-    int begin(hipStream_t st);   // -1 when off
-    void end(int idx, const char* name, double bytes_per_sample, int samples, hipStream_t st);
+    Slot begin();
+    void end(const Slot& s, const char* name, double bytes_per_sample, int samples);
     void set_samples(int idx, int samples);
     int read(std::vector<Entry>& out);   // synchronises; clears the records
 

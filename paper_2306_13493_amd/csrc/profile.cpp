@@ -1,5 +1,6 @@
-// Launch profiler: HIP events around kernel launches, aggregated by kernel
-// name with the algorithmic bytes each launch moves.  Off unless enabled.
+// Launch profiler: each timed launch stamps a pair of HIP events with the
+// kernel's start and end; durations are aggregated by kernel name with the
+// algorithmic bytes each launch moves.  Off unless enabled.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -23,26 +24,28 @@ hipEvent_t Profiler::event() {
     return e;
 }
 
-int Profiler::begin(hipStream_t st) {
-    if (!on_) return -1;
+Profiler::Slot Profiler::begin() {
+    Slot s;
+    if (!on_) return s;
     std::lock_guard<std::mutex> g(mu_);
     Rec r;
     r.a = event();
     r.b = event();
-    if (!r.a || !r.b) return -1;
-    if (hipEventRecord(r.a, st) != hipSuccess) return -1;
+    if (!r.a || !r.b) return s;
     recs_.push_back(r);
-    return (int)recs_.size() - 1;
+    s.idx = (int)recs_.size() - 1;
+    s.a = r.a;
+    s.b = r.b;
+    return s;
 }
 
-void Profiler::end(int idx, const char* name, double bytes_per_sample, int samples, hipStream_t st) {
+void Profiler::end(const Slot& s, const char* name, double bytes_per_sample, int samples) {
     std::lock_guard<std::mutex> g(mu_);
-    if (idx < 0 || idx >= (int)recs_.size()) return;
-    Rec& r = recs_[idx];
+    if (s.idx < 0 || s.idx >= (int)recs_.size()) return;
+    Rec& r = recs_[s.idx];
     r.name = name;
     r.bps = bytes_per_sample;
     r.samples = samples;
-    (void)hipEventRecord(r.b, st);
 }
 
 void Profiler::set_samples(int idx, int samples) {

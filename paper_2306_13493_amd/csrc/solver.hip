@@ -33,6 +33,11 @@
 
 #include "internal.hpp"
 
+// kernel launch inside a profiled launch(...) lambda: the slot's events (or
+// none) are stamped with the kernel's start and end
+#define PLAUNCH(kernel, grid, block, shmem, stream, ...) \
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ps.a, ps.b, 0, __VA_ARGS__)
+
 namespace ces {
 
 namespace {
@@ -1285,11 +1290,6 @@ __global__ void k_set_int(int* dst, int v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
 }
 
-// copy of the active-sample counter (launch profiler only)
-__global__ void k_snapshot(const int* cnt, int* dst) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *cnt;
-}
-
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* qf, const double* qc, const int* itf,
                                                      const int* itc, int slot0, int nslots, long long out0,
                                                      double* y, double* yf, double* yc, int* iters, int* status) {
@@ -1384,7 +1384,6 @@ public:
         o_q_ = take((size_t)cap * 8);
         o_it_ = take((size_t)cap * 4);
         o_cnt_ = take(64);
-        o_hist_ = take((size_t)(cfg.maxit + 2) * sizeof(int));
         bytes_ = off;
     }
     ~SolverImpl() override {
@@ -1453,11 +1452,11 @@ public:
             a.X = ptr<double>(o_X_);
             a.scal = ptr<Scal>(o_scal_);
             const size_t lds = small_lds_bytes<T>(cfg_.m);
-            launch("small_pcg", nv(0) * (sT + 8.0), S, -1, st, [&] {
+            launch("small_pcg", nv(0) * (sT + 8.0), S, -1, st, [&](const Profiler::Slot& ps) {
                 if (cfg_.m > 16)
-                    hipLaunchKernelGGL((k_small_pcg<T, small_threads(32)>), dim3(S), dim3(small_threads(32)), lds, st, a);
+                    PLAUNCH((k_small_pcg<T, small_threads(32)>), dim3(S), dim3(small_threads(32)), lds, st, a);
                 else
-                    hipLaunchKernelGGL((k_small_pcg<T, small_threads(16)>), dim3(S), dim3(small_threads(16)), lds, st, a);
+                    PLAUNCH((k_small_pcg<T, small_threads(16)>), dim3(S), dim3(small_threads(16)), lds, st, a);
             });
             done_ = true;
             return hipGetLastError();
@@ -1468,12 +1467,12 @@ public:
         // coefficient hierarchy
         for (int l = 0; l + 1 < nlev_; ++l) {
             const dim3 g(cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S);
-            launch("coarsen", (l == 0 ? nv(0) : 2.0 * nv(l)) * sT + 2.0 * nv(l + 1) * sT, S, -1, st, [&] {
+            launch("coarsen", (l == 0 ? nv(0) : 2.0 * nv(l)) * sT + 2.0 * nv(l + 1) * sT, S, -1, st, [&](const Profiler::Slot& ps) {
                 if (l == 0)
-                    hipLaunchKernelGGL(k_coarsen_k<T>, g, dim3(kBlock), 0, st, k0_, kss, lv_[0], ptr<T>(o_ce_[0]),
+                    PLAUNCH(k_coarsen_k<T>, g, dim3(kBlock), 0, st, k0_, kss, lv_[0], ptr<T>(o_ce_[0]),
                                        ptr<T>(o_cn_[0]), lv_[1]);
                 else
-                    hipLaunchKernelGGL(k_coarsen_c<T>, g, dim3(kBlock), 0, st, ptr<T>(o_ce_[l - 1]),
+                    PLAUNCH(k_coarsen_c<T>, g, dim3(kBlock), 0, st, ptr<T>(o_ce_[l - 1]),
                                        ptr<T>(o_cn_[l - 1]), lv_[l], ptr<T>(o_ce_[l]), ptr<T>(o_cn_[l]), lv_[l + 1]);
             });
         }
@@ -1481,13 +1480,16 @@ public:
         PcgArgs<T> pa = pcg_args(0);
         pa.tiles_x = itx_;
         pa.ntiles = itiles_;
-        launch("pcg_init", nv(0) * (2.0 * sT + 40.0), S, -1, st, [&] {
-            hipLaunchKernelGGL(k_pcg_init<T>, dim3(itiles_ * S), dim3(kBlock), 0, st, pa);
+        launch("pcg_init", nv(0) * (2.0 * sT + 40.0), S, -1, st, [&](const Profiler::Slot& ps) {
+            PLAUNCH(k_pcg_init<T>, dim3(itiles_ * S), dim3(kBlock), 0, st, pa);
         });
         hipLaunchKernelGGL(k_reduce<RED_BB>, dim3(S), dim3(kBlock), 0, st, part, part, itiles_, scal,
                            cfg_.rtol * cfg_.rtol, cfg_.maxit, cnt);
-        if (Profiler::get().on())
-            hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, ptr<int>(o_hist_));
+        // launch profiler: samples active in each iteration, from the counts
+        // read back for the convergence test (iteration 0: all S; a sample
+        // with a zero right-hand side, converged from the start, is counted)
+        hist_h_.assign(cfg_.maxit + 2, 0);
+        hist_h_[0] = S;
         return hipGetLastError();
     }
 
@@ -1504,6 +1506,7 @@ public:
             }
             if (q != hipSuccess) return q;
             const int c = hcnt_[confirmed_ % RING];
+            if (confirmed_ + 1 < (int)hist_h_.size()) hist_h_[confirmed_ + 1] = c;
             ++confirmed_;
             if (c == 0) done_ = true;
         }
@@ -1534,22 +1537,19 @@ public:
         return hipEventSynchronize(ev_[confirmed_ % RING]);
     }
 
-    hipError_t finish(hipStream_t st) override {
+    hipError_t finish(hipStream_t) override {
         if (!Profiler::get().on() || small_ || recs_.empty()) return hipSuccess;
-        // samples active in iteration it = counter after iteration it-1
-        std::vector<int> h(it_next_ + 1);
-        hipError_t e = hipMemcpyAsync(h.data(), ptr<int>(o_hist_), h.size() * sizeof(int), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return e;
+        // samples active in iteration it = count read back after iteration
+        // it-1 (iterations enqueued past the last confirmed one ran with none)
         for (auto& r : recs_)
-            if (r.second >= 0 && r.second < (int)h.size()) Profiler::get().set_samples(r.first, h[r.second]);
+            if (r.second >= 0 && r.second < (int)hist_h_.size()) Profiler::get().set_samples(r.first, hist_h_[r.second]);
         return hipSuccess;
     }
 
     hipError_t qoi(const void* kv, long long kss, int S, double* q, int* iters, hipStream_t st) override {
         if (S <= 0) return hipSuccess;
-        launch("qoi", nv(0) * 8.0, S, -1, st, [&] {
-            hipLaunchKernelGGL(k_qoi<T>, dim3(S), dim3(kBlock), 0, st, ptr<double>(o_X_), lv_[0], cfg_.bc, cfg_.f,
+        launch("qoi", nv(0) * 8.0, S, -1, st, [&](const Profiler::Slot& ps) {
+            PLAUNCH(k_qoi<T>, dim3(S), dim3(kBlock), 0, st, ptr<double>(o_X_), lv_[0], cfg_.bc, cfg_.f,
                                cfg_.qoi, cfg_.qx, cfg_.qy, reinterpret_cast<const T*>(kv), kss, ptr<Scal>(o_scal_),
                                lin_ ? 1 : 0, q ? q : ptr<double>(o_q_), iters ? iters : ptr<int>(o_it_));
         });
@@ -1565,14 +1565,16 @@ private:
 
     // launch with an optional profiler record; it >= 0 ties the record's
     // sample count to the samples active in CG iteration it
+    // f(ps) launches the kernel with PLAUNCH, which hands the slot's events
+    // to the launch
     template <typename F>
     void launch(const char* name, double bytes_per_sample, int S, int it, hipStream_t st, F&& f) {
         Profiler& P = Profiler::get();
-        const int idx = P.begin(st);
-        f();
-        if (idx >= 0) {
-            P.end(idx, name, bytes_per_sample, S, st);
-            if (it >= 0) recs_.emplace_back(idx, it);
+        const Profiler::Slot ps = P.begin();
+        f(ps);
+        if (ps.idx >= 0) {
+            P.end(ps, name, bytes_per_sample, S);
+            if (it >= 0) recs_.emplace_back(ps.idx, it);
         }
     }
 
@@ -1589,22 +1591,20 @@ private:
         vcycle(it, st);
         hipLaunchKernelGGL(k_reduce<RED_RZ>, dim3(S), dim3(kBlock), 0, st, part, part, rz_parts_, scal, rtol2, cfg_.maxit, cnt);
         PcgArgs<T> a = pcg_args(it);
-        launch("pcg_dir", nu(0) * (24.0 + sT) + nv(0) * sT, S, it, st, [&] {
-            hipLaunchKernelGGL(k_pcg_dir<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
+        launch("pcg_dir", nu(0) * (24.0 + sT) + nv(0) * sT, S, it, st, [&](const Profiler::Slot& ps) {
+            PLAUNCH(k_pcg_dir<T>, dim3(ptiles_ * S), dim3(kBlock), 0, st, a, it == 0 ? 1 : 0);
         });
         hipLaunchKernelGGL(k_reduce<RED_PQ>, dim3(S), dim3(kBlock), 0, st, part, lin_ ? part2 : nullptr, ptiles_,
                            scal, rtol2, cfg_.maxit, cnt);
-        launch("pcg_update", nu(0) * (lin_ ? 24.0 : 48.0), S, it, st, [&] {
+        launch("pcg_update", nu(0) * (lin_ ? 24.0 : 48.0), S, it, st, [&](const Profiler::Slot& ps) {
             if (lin_)
-                hipLaunchKernelGGL(k_pcg_update<false>, dim3(ublocks_, S), dim3(kBlock), 0, st, a.X, a.R, a.Pnew,
+                PLAUNCH(k_pcg_update<false>, dim3(ublocks_, S), dim3(kBlock), 0, st, a.X, a.R, a.Pnew,
                                    a.Q, lv_[0].ss, ublocks_, part, scal);
             else
-                hipLaunchKernelGGL(k_pcg_update<true>, dim3(ublocks_, S), dim3(kBlock), 0, st, a.X, a.R, a.Pnew,
+                PLAUNCH(k_pcg_update<true>, dim3(ublocks_, S), dim3(kBlock), 0, st, a.X, a.R, a.Pnew,
                                    a.Q, lv_[0].ss, ublocks_, part, scal);
         });
         hipLaunchKernelGGL(k_reduce<RED_RR>, dim3(S), dim3(kBlock), 0, st, part, part, ublocks_, scal, rtol2, cfg_.maxit, cnt);
-        if (Profiler::get().on())
-            hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, st, cnt, ptr<int>(o_hist_) + it + 1);
         return hipGetLastError();
     }
 
@@ -1735,19 +1735,19 @@ private:
             // k, rhs in; z_pre and the coarse rhs out
             const double rb = l == 0 ? 8.0 : sT;
             const double coef = (l == 0 ? 1.0 : 2.0) * nv(l) * sT;   // k, or two conductance arrays
-            launch(l == 0 ? "mg_pre_l0" : "mg_pre", coef + nu(l) * (rb + sT) + nu(l + 1) * sT, S, it, st, [&] {
+            launch(l == 0 ? "mg_pre_l0" : "mg_pre", coef + nu(l) * (rb + sT) + nu(l + 1) * sT, S, it, st, [&](const Profiler::Slot& ps) {
                 const dim3 g(tx * ty * S), b(kBlock);
                 if constexpr (sizeof(T) == 4) {
                     if (w128) {
-                        if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, false, true, true, 128>), g, dim3(1024), 0, st, a);
-                        else hipLaunchKernelGGL((k_mg<T, SH, false, false, true, 128>), g, dim3(1024), 0, st, a);
+                        if (l == 0) PLAUNCH((k_mg<T, SH, false, true, true, 128>), g, dim3(1024), 0, st, a);
+                        else PLAUNCH((k_mg<T, SH, false, false, true, 128>), g, dim3(1024), 0, st, a);
                         return;
                     }
                 }
-                if (l == 0 && wh) hipLaunchKernelGGL((k_mg<T, SH, false, true, true>), g, b, 0, st, a);
-                else if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, false, true, false>), g, b, 0, st, a);
-                else if (wh) hipLaunchKernelGGL((k_mg<T, SH, false, false, true>), g, b, 0, st, a);
-                else hipLaunchKernelGGL((k_mg<T, SH, false, false, false>), g, b, 0, st, a);
+                if (l == 0 && wh) PLAUNCH((k_mg<T, SH, false, true, true>), g, b, 0, st, a);
+                else if (l == 0) PLAUNCH((k_mg<T, SH, false, true, false>), g, b, 0, st, a);
+                else if (wh) PLAUNCH((k_mg<T, SH, false, false, true>), g, b, 0, st, a);
+                else PLAUNCH((k_mg<T, SH, false, false, false>), g, b, 0, st, a);
             });
         }
         {
@@ -1765,13 +1765,13 @@ private:
             b.scal = ptr<Scal>(o_scal_);
             double kb = 0.0;
             for (int l = lb_; l < nlev_; ++l) kb += 2.0 * nv(l) * sT;
-            launch("mg_bottom", kb + nu(lb_) * 2.0 * sT, S, it, st, [&] {
+            launch("mg_bottom", kb + nu(lb_) * 2.0 * sT, S, it, st, [&](const Profiler::Slot& ps) {
                 // few samples: more threads per sample shorten each phase;
                 // many: more workgroups per CU hide the latency instead
                 if (S >= 512)
-                    hipLaunchKernelGGL((k_bottom<T, MB, 256>), dim3(S), dim3(256), 0, st, b);
+                    PLAUNCH((k_bottom<T, MB, 256>), dim3(S), dim3(256), 0, st, b);
                 else
-                    hipLaunchKernelGGL((k_bottom<T, MB, 1024>), dim3(S), dim3(1024), 0, st, b);
+                    PLAUNCH((k_bottom<T, MB, 1024>), dim3(S), dim3(1024), 0, st, b);
             });
         }
         for (int l = lb_ - 1; l >= 0; --l) {
@@ -1786,19 +1786,19 @@ private:
             // k, z_pre, rhs, coarse correction in; z out (level 0: r in double)
             const double post = l == 0 ? nv(0) * sT + nu(0) * (sT + 8.0 + sT) + nu(1) * sT
                                        : 2.0 * nv(l) * sT + nu(l) * 3.0 * sT + nu(l + 1) * sT;
-            launch(l == 0 ? "mg_post_l0" : "mg_post", post, S, it, st, [&] {
+            launch(l == 0 ? "mg_post_l0" : "mg_post", post, S, it, st, [&](const Profiler::Slot& ps) {
                 const dim3 g(tx * ty * S), b(kBlock);
                 if constexpr (sizeof(T) == 4) {
                     if (w128) {
-                        if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, true, true, true, 128>), g, dim3(1024), 0, st, a);
-                        else hipLaunchKernelGGL((k_mg<T, SH, true, false, true, 128>), g, dim3(1024), 0, st, a);
+                        if (l == 0) PLAUNCH((k_mg<T, SH, true, true, true, 128>), g, dim3(1024), 0, st, a);
+                        else PLAUNCH((k_mg<T, SH, true, false, true, 128>), g, dim3(1024), 0, st, a);
                         return;
                     }
                 }
-                if (l == 0 && wh) hipLaunchKernelGGL((k_mg<T, SH, true, true, true>), g, b, 0, st, a);
-                else if (l == 0) hipLaunchKernelGGL((k_mg<T, SH, true, true, false>), g, b, 0, st, a);
-                else if (wh) hipLaunchKernelGGL((k_mg<T, SH, true, false, true>), g, b, 0, st, a);
-                else hipLaunchKernelGGL((k_mg<T, SH, true, false, false>), g, b, 0, st, a);
+                if (l == 0 && wh) PLAUNCH((k_mg<T, SH, true, true, true>), g, b, 0, st, a);
+                else if (l == 0) PLAUNCH((k_mg<T, SH, true, true, false>), g, b, 0, st, a);
+                else if (wh) PLAUNCH((k_mg<T, SH, true, false, true>), g, b, 0, st, a);
+                else PLAUNCH((k_mg<T, SH, true, false, false>), g, b, 0, st, a);
             });
         }
     }
@@ -1810,7 +1810,8 @@ private:
     int rz_parts_ = 0, ublocks_ = 0, max_parts_ = 0;
     size_t o_X_ = 0, o_R_ = 0, o_P0_ = 0, o_P1_ = 0, o_Q_ = 0, o_Z_ = 0, o_za0_ = 0;
     std::vector<size_t> o_ce_, o_cn_, o_rhs_, o_za_, o_zb_;
-    size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0, o_hist_ = 0;
+    size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0;
+    std::vector<int> hist_h_;   // active samples per iteration (launch profiler)
     std::vector<std::pair<int, int>> recs_;
     size_t bytes_ = 0;
     DeviceAllocator* alloc_ = nullptr;
