@@ -996,7 +996,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs<T> a) {
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = tx * PTX, y0 = ty * PTY;
     const int m = a.L.m, w = a.L.w;
-    load_ktile(K, a.k + (size_t)s * a.kss, x0, y0, m, w);
+    // only the flow cell carries nonzero Dirichlet data (u = 1 at x1 = 0),
+    // so only it needs k for the lifting's contribution to r
+    const bool lift = a.bc == BC_FLOWCELL;
+    if (lift) load_ktile(K, a.k + (size_t)s * a.kss, x0, y0, m, w);
     __syncthreads();
     auto KF = [&](int gx, int gy) -> double { return K.k[gy - y0 + 1][gx - x0 + 1]; };
     const size_t base = (size_t)s * a.L.ss;
@@ -1009,16 +1012,18 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs<T> a) {
         double xv = 0.0, rv = 0.0;
         if (is_unknown(gx, gy, m, a.bc)) {
             rv = a.f * (double)tri_count(gx, gy, m) * a.h2 * (1.0 / 6.0);
-            // neighbours carrying Dirichlet data
-            if (!is_unknown(gx + 1, gy, m, a.bc) && gx + 1 <= m) rv += cond_e<double>(gx, gy, m, KF) * dirichlet_value(gx + 1, a.bc);
-            if (!is_unknown(gx - 1, gy, m, a.bc) && gx - 1 >= 0) rv += cond_e<double>(gx - 1, gy, m, KF) * dirichlet_value(gx - 1, a.bc);
-            if (!is_unknown(gx, gy + 1, m, a.bc) && gy + 1 <= m) rv += cond_n<double>(gx, gy, m, KF) * dirichlet_value(gx, a.bc);
-            if (!is_unknown(gx, gy - 1, m, a.bc) && gy - 1 >= 0) rv += cond_n<double>(gx, gy - 1, m, KF) * dirichlet_value(gx, a.bc);
+            if (lift) {
+                // neighbours carrying Dirichlet data
+                if (!is_unknown(gx + 1, gy, m, a.bc) && gx + 1 <= m) rv += cond_e<double>(gx, gy, m, KF) * dirichlet_value(gx + 1, a.bc);
+                if (!is_unknown(gx - 1, gy, m, a.bc) && gx - 1 >= 0) rv += cond_e<double>(gx - 1, gy, m, KF) * dirichlet_value(gx - 1, a.bc);
+                if (!is_unknown(gx, gy + 1, m, a.bc) && gy + 1 <= m) rv += cond_n<double>(gx, gy, m, KF) * dirichlet_value(gx, a.bc);
+                if (!is_unknown(gx, gy - 1, m, a.bc) && gy - 1 >= 0) rv += cond_n<double>(gx, gy - 1, m, KF) * dirichlet_value(gx, a.bc);
+            }
             acc += rv * rv;
         } else {
             xv = dirichlet_value(gx, a.bc);
         }
-        a.X[o] = xv;
+        if (a.X) a.X[o] = xv;   // not kept by linear-QoI solves
         a.R[o] = rv;
     }
     acc = block_sum(acc, red);
@@ -1241,19 +1246,22 @@ __global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ X, Lv
     const int s = blockIdx.x;
     const int m = L.m, w = L.w;
     const double h = 1.0 / m, h2 = h * h;
-    const double* x = X + (size_t)s * L.ss;
+    // a linear-QoI solve keeps no iterate: x is the lifting x0 here, taken
+    // from its definition
+    const double* xs = X + (size_t)s * L.ss;
+    auto xat = [&](int t) -> double { return lin ? dirichlet_value(t % w, bc) : xs[t]; };
     double acc = 0.0;
     if (qoi == Q_INTEGRAL) {
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
             const int j = t / w, i = t - j * w;
-            acc += x[t] * (double)tri_count(i, j, m);
+            acc += xat(t) * (double)tri_count(i, j, m);
         }
         acc = block_sum(acc, red) * (h2 / 6.0);
     } else if (qoi == Q_L2) {
         for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
             const int j = t / m, i = t - j * m;
-            const double a00 = x[j * w + i], a10 = x[j * w + i + 1], a11 = x[(j + 1) * w + i + 1],
-                         a01 = x[(j + 1) * w + i];
+            const double a00 = xat(j * w + i), a10 = xat(j * w + i + 1), a11 = xat((j + 1) * w + i + 1),
+                         a01 = xat((j + 1) * w + i);
             const double s1 = a00 + a10 + a11, s2 = a00 + a11 + a01;
             acc += (a00 * a00 + a10 * a10 + a11 * a11 + s1 * s1) + (a00 * a00 + a11 * a11 + a01 * a01 + s2 * s2);
         }
@@ -1262,18 +1270,18 @@ __global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ X, Lv
         int i = min((int)floor(qx / h), m - 1), j = min((int)floor(qy / h), m - 1);
         const double sx = qx / h - i, sy = qy / h - j;
         if (sx >= sy)
-            acc = (1 - sx) * x[j * w + i] + (sx - sy) * x[j * w + i + 1] + sy * x[(j + 1) * w + i + 1];
+            acc = (1 - sx) * xat(j * w + i) + (sx - sy) * xat(j * w + i + 1) + sy * xat((j + 1) * w + i + 1);
         else
-            acc = (1 - sy) * x[j * w + i] + sx * x[(j + 1) * w + i + 1] + (sy - sx) * x[(j + 1) * w + i];
+            acc = (1 - sy) * xat(j * w + i) + sx * xat((j + 1) * w + i + 1) + (sy - sx) * xat((j + 1) * w + i);
     } else {  // outflux through x1 = 1: sum_j (b - A x) at (m, j)
         const T* kk = k + (size_t)s * kss;
         auto KF = [&](int gx, int gy) -> double { return (double)kk[(size_t)gy * w + gx]; };
         for (int j = threadIdx.x; j <= m; j += blockDim.x) {
             const int i = m;
-            const double xp = x[j * w + i];
-            double ax = cond_e<double>(i - 1, j, m, KF) * (xp - x[j * w + i - 1]);
-            if (j < m) ax += cond_n<double>(i, j, m, KF) * (xp - x[(j + 1) * w + i]);
-            if (j > 0) ax += cond_n<double>(i, j - 1, m, KF) * (xp - x[(j - 1) * w + i]);
+            const double xp = xat(j * w + i);
+            double ax = cond_e<double>(i - 1, j, m, KF) * (xp - xat(j * w + i - 1));
+            if (j < m) ax += cond_n<double>(i, j, m, KF) * (xp - xat((j + 1) * w + i));
+            if (j > 0) ax += cond_n<double>(i, j - 1, m, KF) * (xp - xat((j - 1) * w + i));
             acc += f * (double)tri_count(i, j, m) * h2 / 6.0 - ax;
         }
         acc = block_sum(acc, red);
@@ -1480,7 +1488,10 @@ public:
         PcgArgs<T> pa = pcg_args(0);
         pa.tiles_x = itx_;
         pa.ntiles = itiles_;
-        launch("pcg_init", nv(0) * (2.0 * sT + 40.0), S, -1, st, [&](const Profiler::Slot& ps) {
+        if (lin_) pa.X = nullptr;   // the iterate is not kept
+        // k for the flow cell's lifting; x (unless linear QoI) and r out
+        const double ib = nv(0) * ((cfg_.bc == BC_FLOWCELL ? sT : 0.0) + (lin_ ? 8.0 : 16.0));
+        launch("pcg_init", ib, S, -1, st, [&](const Profiler::Slot& ps) {
             PLAUNCH(k_pcg_init<T>, dim3(itiles_ * S), dim3(kBlock), 0, st, pa);
         });
         hipLaunchKernelGGL(k_reduce<RED_BB>, dim3(S), dim3(kBlock), 0, st, part, part, itiles_, scal,
@@ -1548,7 +1559,7 @@ public:
 
     hipError_t qoi(const void* kv, long long kss, int S, double* q, int* iters, hipStream_t st) override {
         if (S <= 0) return hipSuccess;
-        launch("qoi", nv(0) * 8.0, S, -1, st, [&](const Profiler::Slot& ps) {
+        launch("qoi", lin_ ? 8.0 : nv(0) * 8.0, S, -1, st, [&](const Profiler::Slot& ps) {
             PLAUNCH(k_qoi<T>, dim3(S), dim3(kBlock), 0, st, ptr<double>(o_X_), lv_[0], cfg_.bc, cfg_.f,
                                cfg_.qoi, cfg_.qx, cfg_.qy, reinterpret_cast<const T*>(kv), kss, ptr<Scal>(o_scal_),
                                lin_ ? 1 : 0, q ? q : ptr<double>(o_q_), iters ? iters : ptr<int>(o_it_));
