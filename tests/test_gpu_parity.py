@@ -320,3 +320,47 @@ def test_embed_plan_info_and_coarse_embedding(ctx, ces):
     assert r.info.n_coarse == r.info.n
     with pytest.raises(ces.CesError):
         mkplan(ctx, ces, dict(w, level="single"))
+
+
+# ------------------------------------------------------------- edge cases
+def test_zero_count_is_a_no_op(ctx, ces):
+    p = mkplan(ctx, ces, dict(cov="matern", nu=1.0, lam=0.1, m=64, level="pair"))
+    out = p.sample(seed=1, first=5, count=0)
+    torch.cuda.synchronize()
+    assert out["y"].numel() == 0
+    # the plan still samples normally afterwards
+    y = p.sample(seed=1, first=5, count=3)["y"].cpu().numpy()
+    yr = np.array([oracle_plan(dict(cov="matern", nu=1.0, lam=0.1, m=64, level="pair")).sample(1, 5 + t)[0]
+                   for t in range(3)])
+    assert np.max(np.abs(y - yr)) <= 1e-6 * np.max(np.abs(yr))
+
+
+@pytest.mark.parametrize("m,level", [(16, "single"), (64, "pair")])
+def test_every_eigenvalue_dropped_gives_the_constant_coefficient_qoi(ctx, ces, m, level):
+    # tau = s: a zero field, k = exp(0) = 1 on every sample (Algorithm 2 with
+    # all eigenvalues dropped); the QoIs equal the deterministic solve's
+    from oracle import smoothing as osmo
+    w = dict(cov="matern", nu=1.5, lam=0.2, m=m, level=level, precision="fp64")
+    probe = mkplan(ctx, ces, w)
+    s = probe.info.n ** 2
+    probe.close()
+    p = mkplan(ctx, ces, dict(w, tau_fine=s, tau_coarse=s))
+    out = p.sample(seed=2, first=0, count=5)
+    qf = out["q_fine"].cpu().numpy()
+    d = W.to_oracle(w)
+    assert np.allclose(qf, osmo.constant_coefficient_qoi(d), rtol=1e-9, atol=0)
+    if level == "pair":
+        qc = out["q_coarse"].cpu().numpy()
+        assert np.allclose(qc, osmo.constant_coefficient_qoi(dict(d, m=m // 2)), rtol=1e-9, atol=0)
+
+
+def test_sample_indices_beyond_32_bits(ctx, ces):
+    # the pair index q = i / 2 spans two counter words
+    w = dict(cov="matern", nu=1.0, lam=0.1, m=32, level="pair", precision="fp64")
+    p = mkplan(ctx, ces, w)
+    first = 2 ** 33 + 5
+    y = p.sample(seed=7, first=first, count=4)["y"].cpu().numpy()
+    o = oracle_plan(w)
+    yr = np.array([o.sample(7, first + t)[0] for t in range(4)])
+    scale = max(abs(o.sample(7, first)[1]), 1e-12)
+    assert np.max(np.abs(y - yr)) <= 1e-9 * scale
