@@ -29,6 +29,7 @@
 // workgroups off (per-sample active flag).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -189,6 +190,32 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
     const int ox = x0 - H, oy = y0 - H;
     const int m = a.L.m, w = a.L.w, bc = a.bc;
     const size_t sbase = (size_t)s * a.L.ss;
+    // this lane's nodes: rhs (and the pre-smoothed z of POST); tiles load
+    // them first, so that their latency overlaps the k tile's (the
+    // 1024-thread whole-level workgroups, alone on their CU, load them
+    // after the conductances instead)
+    const int lane = threadIdx.x % LW, hw = threadIdx.x / LW;
+    const int lx0 = 2 * lane, ly0 = hw * SH;
+    const int gx0 = ox + lx0;
+    using RT = typename std::conditional<L0, double, T>::type;   // level 0: r in double
+    RT rhs_raw[SH][2];
+    T zv[SH][2];
+    auto load_rhs = [&]() {
+        const RT* rin = reinterpret_cast<const RT*>(a.rhs) + sbase;
+        const T* zin = a.za + sbase;
+        const int gxc0 = min(max(gx0, 0), m), gxc1 = min(max(gx0 + 1, 0), m);
+#pragma unroll
+        for (int r = 0; r < SH; ++r) {
+            const int gyc = min(max(oy + ly0 + r, 0), m);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int o = gyc * w + (q == 0 ? gxc0 : gxc1);
+                rhs_raw[r][q] = rin[o];
+                if constexpr (POST) zv[r][q] = zin[o];
+            }
+        }
+    };
+    if constexpr (RXW == 64) load_rhs();
     // k tile (level 0): lane l of wave wv loads padded column l for rows wv, wv+4, ...
     if constexpr (L0) {
         // all loads are issued before any is used (addresses clamped into
@@ -244,9 +271,6 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
         }
     }
     __syncthreads();
-    const int lane = threadIdx.x % LW, hw = threadIdx.x / LW;
-    const int lx0 = 2 * lane, ly0 = hw * SH;
-    const int gx0 = ox + lx0;
     // column masks of this lane
     const bool unk_c0 = gx0 >= 1 && gx0 <= m - 1, unk_c1 = gx0 + 1 >= 1 && gx0 + 1 <= m - 1;
     const bool sqc_m = gx0 - 1 >= 0 && gx0 - 1 <= m - 1, sqc_a = gx0 >= 0 && gx0 <= m - 1,
@@ -304,24 +328,12 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
         }
     }
     T z[SH][2], rhs[SH][2], id[SH][2];
-    const T* zin = a.za + sbase;
-    const T* rhsT = L0 ? nullptr : reinterpret_cast<const T*>(a.rhs) + sbase;
-    const double* rhsD = L0 ? reinterpret_cast<const double*>(a.rhs) + sbase : nullptr;
     T* sz0 = sz + (ly0 + 1) * PX + lx0 + 1;
-    T zv[SH][2];
-    {
-        const int gxc0 = min(max(gx0, 0), m), gxc1 = min(max(gx0 + 1, 0), m);
+    if constexpr (RXW != 64) load_rhs();
 #pragma unroll
-        for (int r = 0; r < SH; ++r) {
-            const int gyc = min(max(oy + ly0 + r, 0), m);
+    for (int r = 0; r < SH; ++r)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int o = gyc * w + (q == 0 ? gxc0 : gxc1);
-                rhs[r][q] = L0 ? (T)rhsD[o] : rhsT[o];
-                if constexpr (POST) zv[r][q] = zin[o];
-            }
-        }
-    }
+        for (int q = 0; q < 2; ++q) rhs[r][q] = (T)rhs_raw[r][q];
 #pragma unroll
     for (int r = 0; r < SH; ++r) {
         const int gy = oy + ly0 + r;
