@@ -216,6 +216,26 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
         }
     };
     if constexpr (RXW == 64) load_rhs();
+    // POST: the coarse correction of the region (with its ring), prefetched
+    // into registers by the tiles for the same reason, except where the
+    // registers would push the float level-0 kernel below four waves per SIMD
+    const int cox = ox >> 1, coy = oy >> 1;  // floor, also for negative origins
+    constexpr bool kEarlyZc = POST && RXW == 64 && !(L0 && sizeof(T) == 4);
+    constexpr int NZC = POST ? (CY * CX + NT - 1) / NT : 1;
+    T zcv[NZC];
+    auto load_zc = [&]() {
+        const T* zc = a.zc + (size_t)s * a.C.ss;
+        const int cm = a.C.m, cw = a.C.w;
+#pragma unroll
+        for (int i = 0; i < NZC; ++i) {
+            const int t = threadIdx.x + i * NT;
+            const int y = t / CX, x = t - y * CX;
+            const int I = cox + x, J = coy + y;
+            const int Ic = min(max(I, 0), cm), Jc = min(max(J, 0), cm);
+            zcv[i] = zc[Jc * cw + Ic];
+        }
+    };
+    if constexpr (kEarlyZc) load_zc();
     // k tile (level 0): lane l of wave wv loads padded column l for rows wv, wv+4, ...
     if constexpr (L0) {
         // all loads are issued before any is used (addresses clamped into
@@ -260,14 +280,16 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
         else if (t < 2 * PX + RY) sz[(t - 2 * PX + 1) * PX] = T(0);
         else sz[(t - 2 * PX - RY + 1) * PX + PX - 1] = T(0);
     }
-    const int cox = ox >> 1, coy = oy >> 1;  // floor, also for negative origins
     if constexpr (POST) {
-        const T* zc = a.zc + (size_t)s * a.C.ss;
-        const int cm = a.C.m, cw = a.C.w;
-        for (int t = threadIdx.x; t < CY * CX; t += blockDim.x) {
+        if constexpr (!kEarlyZc) load_zc();
+        const int cm = a.C.m;
+#pragma unroll
+        for (int i = 0; i < NZC; ++i) {
+            const int t = threadIdx.x + i * NT;
+            if (t >= CY * CX) break;
             const int y = t / CX, x = t - y * CX;
             const int I = cox + x, J = coy + y;
-            szc[t] = is_unknown(I, J, cm, bc) ? zc[J * cw + I] : T(0);
+            szc[t] = is_unknown(I, J, cm, bc) ? zcv[i] : T(0);
         }
     }
     __syncthreads();
