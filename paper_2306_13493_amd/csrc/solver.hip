@@ -668,21 +668,34 @@ __global__ __launch_bounds__(NT) void k_bottom(BottomArgs<T> a) {
     g.m0 = a.m0;
     lds_mg_layout(g);
     __syncthreads();
-    for (int l = 0; l < a.nl; ++l) {
-        const int w = g.w(l), o = off[l];
-        const T* ceg = a.ce[l] + (size_t)s * a.ss[l];
-        const T* cng = a.cn[l] + (size_t)s * a.ss[l];
-        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-            ce[o + t] = ceg[t];
-            cn[o + t] = cng[t];
-        }
-    }
     {
-        const int m = g.m(0), w = g.w(0);
-        const T* rg = a.rhs + (size_t)s * a.ss[0];
-        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-            const int y = t / w, x = t - y * w;
-            rhs[t] = is_unknown(x, y, m, a.bc) ? rg[t] : T(0);
+        // every level's conductances and the first level's rhs, all loads
+        // issued before the LDS stores (node t of the stacked levels)
+        const int total = off[a.nl - 1] + g.w(a.nl - 1) * g.w(a.nl - 1);
+        const int m0 = g.m(0), w0 = g.w(0);
+        constexpr int NLD = (TOT + NT - 1) / NT;
+        T cev[NLD], cnv[NLD], rv[NLD];
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int t = threadIdx.x + i * NT;
+            cev[i] = cnv[i] = rv[i] = T(0);
+            if (t < total) {
+                int l = 0;
+                while (l + 1 < a.nl && t >= off[l + 1]) ++l;
+                const int u = t - off[l];
+                cev[i] = a.ce[l][(size_t)s * a.ss[l] + u];
+                cnv[i] = a.cn[l][(size_t)s * a.ss[l] + u];
+                if (l == 0 && is_unknown(u % w0, u / w0, m0, a.bc)) rv[i] = a.rhs[(size_t)s * a.ss[0] + u];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int t = threadIdx.x + i * NT;
+            if (t < total) {
+                ce[t] = cev[i];
+                cn[t] = cnv[i];
+                if (t < w0 * w0) rhs[t] = rv[i];
+            }
         }
     }
     __syncthreads();

@@ -39,9 +39,11 @@ def mix():
     d = dict(cov="sepexp", lam=0.3, m=128, level="pair", qoi="point")
     e = dict(cov="matern", nu=2.3, lam=0.25, m=32, psd="grow")
     f = dict(W.c3_level(4))
+    # a pair level whose coarse term comes from the coarse mesh's own embedding
+    g = dict(cov="matern", nu=1.0, lam=0.1, m=64, level="pair", tau_fine=-1, tau_coarse=-1, coupling="embed")
     # (desc, seed, first, count): repeated descriptors share a plan
     return [(a, 1, 0, 37), (b, 2, 5, 20), (c, 3, 0, 64), (a, 4, 10, 9), (d, 5, 0, 7), (e, 6, 1, 30),
-            (b, 7, 0, 3), (f, 8, 0, 12), (a, 1, 37, 11)]
+            (b, 7, 0, 3), (f, 8, 0, 12), (a, 1, 37, 11), (g, 9, 3, 21)]
 
 
 def alone(ctx, ces, w, seed, first, count):
