@@ -735,20 +735,37 @@ __device__ __forceinline__ double coarse_n(int I, int J, const NF& N) {
            0.25 * (hmean2(N(x - 1, y), N(x - 1, y + 1)) + hmean2(N(x + 1, y), N(x + 1, y + 1)));
 }
 
+// Coarse nodes in tiles of CCX x CCY per workgroup; the fine k they read
+// (fine nodes 2I-2 .. 2I+2 by 2J-2 .. 2J+2) is staged in LDS first.
+constexpr int CCX = 32, CCY = kBlock / CCX;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarsen_k(const T* __restrict__ kf, long long kfss, Lvl F,
-                                                      T* __restrict__ cec, T* __restrict__ cnc, Lvl C) {
+                                                      T* __restrict__ cec, T* __restrict__ cnc, Lvl C,
+                                                      int tiles_x) {
+    constexpr int KX = 2 * CCX + 3, KY = 2 * CCY + 3;
+    __shared__ T kt[KY * KX];
     const int s = blockIdx.y;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= C.w * C.w) return;
-    const int J = t / C.w, I = t - J * C.w;
+    const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+    const int I0 = tx * CCX, J0 = ty * CCY;
+    const int fx0 = 2 * I0 - 2, fy0 = 2 * J0 - 2;
     const T* k = kf + (size_t)s * kfss;
     const int m = F.m, w = F.w;
-    auto K = [&](int gx, int gy) -> double { return (double)k[(size_t)gy * w + gx]; };
+    for (int t = threadIdx.x; t < KX * KY; t += blockDim.x) {
+        const int y = t / KX, x = t - y * KX;
+        const int gx = fx0 + x, gy = fy0 + y;
+        kt[t] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? k[(size_t)gy * w + gx] : T(0);
+    }
+    __syncthreads();
+    const int I = I0 + (int)threadIdx.x % CCX, J = J0 + (int)threadIdx.x / CCX;
+    if (I >= C.w || J >= C.w) return;
+    // the conductance formulas read only nodes inside the mesh
+    auto K = [&](int gx, int gy) -> double { return (double)kt[(gy - fy0) * KX + (gx - fx0)]; };
     auto E = [&](int x, int y) -> double { return cond_e<double>(x, y, m, K); };
     auto N = [&](int x, int y) -> double { return cond_n<double>(x, y, m, K); };
     const double e = coarse_e(I, J, E);
     const double n = coarse_n(I, J, N);
+    const size_t t = (size_t)J * C.w + I;
     cec[(size_t)s * C.ss + t] = (T)e;
     cnc[(size_t)s * C.ss + t] = (T)n;
 }
@@ -1521,11 +1538,12 @@ public:
         double* part = ptr<double>(o_part_);
         // coefficient hierarchy
         for (int l = 0; l + 1 < nlev_; ++l) {
-            const dim3 g(cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S);
+            const int ctx = (int)cdiv(lv_[l + 1].w, CCX), cty = (int)cdiv(lv_[l + 1].w, CCY);
+            const dim3 g(l == 0 ? (unsigned)(ctx * cty) : (unsigned)cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S);
             launch("coarsen", (l == 0 ? nv(0) : 2.0 * nv(l)) * sT + 2.0 * nv(l + 1) * sT, S, -1, st, [&](const Profiler::Slot& ps) {
                 if (l == 0)
                     PLAUNCH(k_coarsen_k<T>, g, dim3(kBlock), 0, st, k0_, kss, lv_[0], ptr<T>(o_ce_[0]),
-                                       ptr<T>(o_cn_[0]), lv_[1]);
+                                       ptr<T>(o_cn_[0]), lv_[1], ctx);
                 else
                     PLAUNCH(k_coarsen_c<T>, g, dim3(kBlock), 0, st, ptr<T>(o_ce_[l - 1]),
                                        ptr<T>(o_cn_[l - 1]), lv_[l], ptr<T>(o_ce_[l]), ptr<T>(o_cn_[l]), lv_[l + 1]);
