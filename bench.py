@@ -459,8 +459,6 @@ def main():
 
     # parity of the timed path and the plain FP64 GPU path against the oracle
     extra = {}
-    y_last = out["y"].cpu().numpy()
-    last_first = (step_id - 1) * count
     cpu = None
     if not args.no_cpu_baseline:
         nproc = max(1, min(os.cpu_count() or 1, 16))

@@ -145,7 +145,10 @@ typedef struct {
 void ces_level_desc_default(ces_level_desc* d);
 
 /* Bind to HIP device `device`.  mem_budget_bytes caps the library's own
- * workspace (0 = 90% of free device memory). */
+ * workspace (0 = 90% of free device memory).  A plan's sample workspace,
+ * allocated on its first sampling call, holds as many samples as fit in
+ * 4 GiB (at most 8192; 65536 for m <= 32), or in the size in MiB given by
+ * the environment variable CESMLMC_WORKSPACE_MB, and within the budget. */
 int ces_context_create(int device, size_t mem_budget_bytes, ces_context* out);
 int ces_context_destroy(ces_context ctx);
 

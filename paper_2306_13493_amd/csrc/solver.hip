@@ -45,7 +45,6 @@ namespace {
 
 struct Scal {
     double bb, rz, rz_old, pq, rr;
-    double wp;     // w.p of the current direction (linear QoI)
     double qacc;   // sum over iterations of alpha w.p = w.(x - x0)
     int it, active, status, pad;
 };
@@ -1280,7 +1279,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
     if (WHAT == RED_BB) {
         sc.bb = acc;
         sc.it = 0;
-        sc.rz = sc.rz_old = sc.pq = sc.wp = sc.qacc = 0.0;
+        sc.rz = sc.rz_old = sc.pq = sc.qacc = 0.0;
         sc.rr = acc;
         sc.status = 0;
         sc.active = acc > 0.0 ? 1 : 0;
@@ -1291,7 +1290,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
         sc.pq = acc;
         if (part2) {
             // the step alpha = rz / pq of this iteration, as the update takes it
-            sc.wp = acc2;
             sc.qacc += (sc.rz / sc.pq) * acc2;
         }
     } else {
