@@ -334,6 +334,52 @@ def smoothing_study(args):
     print(json.dumps(line), flush=True)
 
 
+def single_workload(args):
+    """--workload c3: the five-level estimator round in one batched call;
+    --workload c5: the 2049^2 flow-cell level (Matern 3/2, lambda 0.01,
+    outflow QoI).  Prints one JSON line each (level samples per second)."""
+    import numpy as np
+    import torch
+    import paper_2306_13493_amd as ces
+    from paper_2306_13493_amd import workloads as W
+
+    torch.cuda.init()
+    ces.load()
+    ctx = ces.Context(0)
+    if args.workload == "c3":
+        r = c3_batch(ces, ctx, W, log, reps=max(3, args.steps))
+        line = {"metric": "MLMC level samples/sec, five-level batched round at 1 GPU",
+                "value": r["level_samples_per_s"], "unit": "samples/s", "n_gpus": 1, "higher_is_better": True,
+                "dtype": "f32+f64", "data": "synthetic",
+                "config": {"workload": "C3: Matern nu=1/2 lambda=0.03, levels m = 16..256 (pairs above 16), "
+                                       "N = 20000/5000/1200/300/80, tau = n below the finest level, mixed precision"},
+                "c3_mlmc_batch": r}
+        print(json.dumps(line), flush=True)
+        return
+    # C5: 2049^2 flow cell
+    plan = ctx.plan(ces.level_desc(**W.C5))
+    count = 64
+    out = plan.sample(0, 0, count)
+    torch.cuda.synchronize()
+    ts = []
+    for k in range(max(3, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = plan.sample(0, (k + 1) * count, count, out=out)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    it = out["iters"].cpu().numpy()
+    v = count / float(np.median(ts))
+    log("C5: %d samples in %.1f ms -> %.1f samples/s; CG iterations mean %.2f" % (count, 1e3 * np.median(ts), v,
+                                                                                it.mean()))
+    line = {"metric": "MLMC level samples/sec, 2049^2 flow cell at 1 GPU", "value": round(v, 1),
+            "unit": "samples/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "C5: Matern nu=3/2 sigma2=2 lambda=0.01, 2049^2 vertices (embedding 4096^2), "
+                                   "flow cell, outflow QoI, %d samples per call, mixed precision" % count},
+            "cg_iterations_mean": float(it.mean())}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,9 +393,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (scale for HBM counters)")
     ap.add_argument("--study-samples", type=int, default=512, help="smoothing: samples per mesh and form")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "smoothing"],
-                    help="c2: throughput of the single-level workload (default); c4: serving trace; "
-                         "smoothing: smoothing error against the mesh")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "smoothing"],
+                    help="c2: throughput of the single-level workload (default); c3: five-level batch; "
+                         "c4: serving trace; c5: 2049^2 flow cell; smoothing: smoothing error against the mesh")
     ap.add_argument("--rate", type=float, default=200.0, help="c4: arrivals per second")
     ap.add_argument("--duration", type=float, default=30.0, help="c4: seconds of arrivals")
     ap.add_argument("--mem-gb", type=float, default=200.0, help="c4: server memory budget")
@@ -365,6 +411,9 @@ def main():
         return
     if args.workload == "smoothing":
         smoothing_study(args)
+        return
+    if args.workload in ("c3", "c5"):
+        single_workload(args)
         return
 
     import numpy as np
