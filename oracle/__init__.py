@@ -30,10 +30,12 @@ qoi         quantities of interest (Sections 3.1 and 4)
 sampler     one MLMC level sample Y = Q_f - Q_c (Sections 3.4-3.5)
 mlmc        adaptive MLMC estimator over level samples (Sections 3.3,
             3.5, 4)
+qmc         randomly shifted lattice rules for the Hartley xi and the
+            multilevel QMC estimator (extension named in Section 5)
 smoothing   tau from the balance of smoothing and discretisation error
             (Section 3.5) and the smoothing error Q_h - Q~_h (Section 4.1)
 
 Parity status per function is listed in each module header.
 """
 
-from . import covariance, embedding, normals, field, fem, qoi, sampler, mlmc, smoothing  # noqa: F401
+from . import covariance, embedding, normals, field, fem, qoi, sampler, mlmc, qmc, smoothing  # noqa: F401

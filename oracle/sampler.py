@@ -20,7 +20,9 @@ level l has the law of the fine term of level l-1 and the smoothed sum
 telescopes exactly.
 
 Sample index i maps to pair q = floor(i/2), component i mod 2 in PAIR field
-mode, and to q = i in HARTLEY field mode.
+mode, and to q = i in HARTLEY field mode.  A HARTLEY plan may carry a
+lattice (qmc.py): its coordinates replace the normals at their eigen
+indices.
 
 desc keys: cov, nu, lam, sigma2, m, level (0 SINGLE / 1 PAIR), tau_f,
 tau_c (-1 = default n), psd, period, max_pad, field_mode, bc, qoi, qx, qy,
@@ -29,7 +31,7 @@ f, stream, coupling (0 RESTRICT / 1 EMBED).
 
 import numpy as np
 
-from . import embedding, field, fem, qoi
+from . import embedding, field, fem, qmc, qoi
 
 SINGLE = 0
 PAIR_LEVEL = 1
@@ -66,6 +68,13 @@ class Plan:
         self.keep_c = self.keep_f if self.coarse_plan is not None else embedding.mask(self.lam, self.tau_c)
         self.a_f = embedding.amplitudes(self.lam, self.keep_f)
         self.a_c = embedding.amplitudes(self.lam, self.keep_c)
+        self.lattice = None
+
+    def set_lattice(self, lat):
+        """Quasi-Monte Carlo normals (qmc.Lattice) for a HARTLEY plan; None = Monte Carlo."""
+        if lat is not None and self.desc.get("field_mode", field.PAIR) != field.HARTLEY:
+            raise ValueError("a lattice needs the Hartley field mode")
+        self.lattice = lat
 
     def fields(self, seed, i):
         """(Z_f, Z_c) nodal fields of sample i; Z_c is None for SINGLE."""
@@ -76,7 +85,10 @@ class Plan:
             q, comp = i // 2, i % 2
         else:
             q, comp = i, 0
-        xi = field.xi(seed, q, d.get("stream", 0), self.n, mode)
+        if self.lattice is not None:
+            xi = qmc.lattice_xi(self.lattice, seed, q, d.get("stream", 0), self.n)
+        else:
+            xi = field.xi(seed, q, d.get("stream", 0), self.n, mode)
         zf = field.fields(self.a_f, xi, m, mode)[comp]
         if d.get("level", SINGLE) == SINGLE:
             return zf, None
