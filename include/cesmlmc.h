@@ -331,6 +331,86 @@ typedef struct {
 int ces_smoothing_error(ces_context ctx, ces_plan full, ces_plan smoothed, uint64_t seed, uint64_t first,
                         int64_t count, void* hip_stream, ces_smoothing_stats* out);
 
+/* ---- randomised quasi-Monte Carlo (extension named in Section 5) ------ */
+
+/* QMC drives the real (Hartley) factorisation of Sections 2.1.1-2.1.2 with
+ * a randomly shifted rank-1 lattice rule instead of Philox normals on the s
+ * eigen indices it is given; the other normals stay Philox ones.
+ *   point i (radical-inverse order: the first 2^k points are the lattice
+ *   rule with N = 2^k for every k) of shift r, coordinate j:
+ *     U = (bitreverse64(i) * z_j + D_rj) mod 2^64,
+ *     u = (floor(U / 2^12) + 1/2) 2^-52,    xi_{dims[j]} = Phi^-1(u),
+ *   D_rj = x0 + 2^32 x1 of Philox4x32-10 with counter (j, r, 2^32-1,
+ *   stream), key = the sampling seed.
+ * Sample index g of a lattice plan is point g / R of shift g mod R, so the
+ * first N R samples are N points of every shift. */
+
+/* Generating vector by the component-by-component construction (Sloan,
+ * Kuo and Joe, 2002) for N = 2^log2_points points: coordinate j takes the
+ * odd z <= N/2 (z = 1 for N <= 2) minimising the shift-averaged worst-case
+ * error of the weighted unanchored Sobolev space with product weights,
+ *   e^2 = -1 + (1/N) sum_k prod_j (1 + gamma_j B2({k z_j / N})),
+ *   B2(x) = x (x - 1) + 1/6,
+ * given z_0..z_{j-1}; each candidate's sum takes every term truncated to a
+ * multiple of 2^-40 and adds them exactly (result independent of the
+ * summation order), ties to the smaller z.  gamma: s host doubles >= 0 with
+ * sum <= 64; z: s host uint32 (out).  0 <= log2_points <= 20, s >= 1.
+ * Host only (threads; O(s N^2 / 2)).  CES_ERR_ARG on invalid arguments. */
+int ces_lattice_cbc(int32_t log2_points, int32_t s, const double* gamma, uint32_t* z);
+
+/* The s eigen indices of the plan's fine embedding with the largest
+ * eigenvalues (value descending, index ascending; clamped eigenvalues)
+ * into dims (s host int64) and their values into lam (s host doubles, may
+ * be NULL).  Needs the plan's eigenvalues (every plan made by
+ * ces_plan_create keeps them). */
+int ces_plan_lattice_order(ces_plan plan, int32_t s, int64_t* dims, double* lam);
+
+/* Attach a lattice to a HARTLEY plan: s coordinates with generating vector
+ * z (s host uint32, odd for every coordinate to be a permutation of the
+ * points) on eigen indices dims (s distinct host int64 in [0, n^2); NULL =
+ * ces_plan_lattice_order's), `shifts` >= 2 random shifts.  s = 0 detaches
+ * (plain Monte Carlo again).  Every later sampling call on the plan (and
+ * the coarse field of an EMBED pair) uses it; sample indices must stay
+ * below 2^63.  Not concurrent with sampling on the plan (CES_ERR_BUSY).
+ * CES_ERR_ARG: not HARTLEY, s out of [0, n^2], repeated or out-of-range
+ * dims, shifts < 2. */
+int ces_plan_set_lattice(ces_plan plan, int32_t s, const uint32_t* z, const int64_t* dims, int32_t shifts);
+
+/* ces_plan_lattice_order + weights gamma_j = lam_j / sum lam (the
+ * eigenvalues of the chosen indices, scaled to sum 1) + ces_lattice_cbc +
+ * ces_plan_set_lattice. */
+int ces_plan_set_lattice_default(ces_plan plan, int32_t s, int32_t log2_points, int32_t shifts);
+
+typedef struct {
+    int32_t struct_size;   /* sizeof(ces_mlqmc_opts) */
+    int32_t l_start;       /* levels 0..l_start are used from the start (>= 0) */
+    double eps;            /* target root mean squared error */
+    int64_t n_pilot;       /* points per shift of a level newly added (>= 1) */
+    double theta;          /* share of eps^2 for the estimator variance */
+    double alpha;          /* weak order for the bias estimate; <= 0: fitted */
+    int32_t cost_model;    /* 0: unknowns of the level's solves, 1: measured */
+    int32_t max_rounds;    /* bound on sampling rounds */
+    uint64_t seed;
+} ces_mlqmc_opts;
+
+void ces_mlqmc_opts_default(ces_mlqmc_opts* o);
+
+/* Multilevel QMC (Giles and Waterhouse, 2009) over lattice plans (every
+ * plan in levels and finest has a lattice; all share one shift count R).
+ * Level l holds N_l points of each of the R shifts (samples 0 .. N_l R - 1);
+ * its estimate is the mean of the R shift averages and V_l their sample
+ * variance / R.  Each round samples what is missing on every level in use
+ * in one ces_sample_batch call (per-shift sums add samples in index
+ * order), then, while sum_l V_l > theta eps^2 with V_l halved per planned
+ * doubling, doubles N_l of the level with the largest V_l / (C_l N_l)
+ * (ties: the lower level).  When nothing is to be sampled the bias and the
+ * addition of levels follow ces_mlmc_run (Richardson, alpha fitted over
+ * levels 1..L when L >= 2, else 1).  out: n[l] = N_l R, mean[l] the level
+ * estimate, var[l] the variance of the shift averages (R - 1 denominator),
+ * variance = sum var[l] / R.  Synchronous. */
+int ces_mlqmc_run(ces_context ctx, const ces_plan* levels, const ces_plan* finest, int32_t nlevels,
+                  const ces_mlqmc_opts* opts, void* hip_stream, ces_mlmc_result* out);
+
 /* ---- serving: continuous batching with memory admission -------------- */
 
 /* A server owns a host thread that plans, admits and runs requests as they

@@ -212,7 +212,7 @@ def run(sample, cost, nlevels, eps, shifts_, l_start=2, n_pilot=1, theta=0.5, al
         if L >= 1 and bias * bias <= (1.0 - theta) * eps * eps:
             converged = True
             break
-        if L + 1 >= nlevels:
+        if L + 1 >= nlevels or rounds >= max_rounds:
             break
         if finest_differs:
             sums[L] = np.zeros(R)

@@ -15,7 +15,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (CesError, LevelDesc, MlmcOpts, MlmcResult, PlanInfo, Request, Schedule, ServerStats,
+from ._lib import (CesError, LevelDesc, MlmcOpts, MlmcResult, MlqmcOpts, PlanInfo, Request, Schedule, ServerStats,
                    SmoothingStats, check, load)
 
 COV = {"matern": 0, "sepexp": 1}
@@ -213,6 +213,31 @@ class Plan:
                                      c.ctypes.data_as(ctypes.c_void_p)))
         return f, c
 
+    def lattice_order(self, s):
+        """(dims, lam): the s eigen indices with the largest eigenvalues."""
+        d = np.empty(int(s), dtype=np.int64)
+        lam = np.empty(int(s), dtype=np.float64)
+        check(self.lib.ces_plan_lattice_order(self.handle, int(s), d.ctypes.data_as(ctypes.c_void_p),
+                                              lam.ctypes.data_as(ctypes.c_void_p)))
+        return d, lam
+
+    def set_lattice(self, z=None, dims=None, shifts=16, s=None, log2_points=10):
+        """Attach a randomly shifted lattice (HARTLEY plans).  With z given:
+        ces_plan_set_lattice(z, dims or the default order); without:
+        ces_plan_set_lattice_default(s, log2_points).  z = [] detaches."""
+        if z is None:
+            check(self.lib.ces_plan_set_lattice_default(self.handle, int(s), int(log2_points), int(shifts)))
+            return
+        z = np.ascontiguousarray(z, dtype=np.uint32)
+        dp = None
+        if dims is not None:
+            dims = np.ascontiguousarray(dims, dtype=np.int64)
+            if dims.size != z.size:
+                raise ValueError("dims and z differ in length")
+            dp = dims.ctypes.data_as(ctypes.c_void_p)
+        check(self.lib.ces_plan_set_lattice(self.handle, int(z.size), z.ctypes.data_as(ctypes.c_void_p), dp,
+                                            int(shifts)))
+
     def field(self, seed, sample, stream=None):
         """(Z_fine, Z_coarse or None) of one sample as float64 device tensors."""
         torch = _torch()
@@ -328,6 +353,36 @@ def mlmc_run(ctx, levels, finest=None, eps=1e-3, l_start=2, n_pilot=100, theta=0
             "var": [r.var[i] for i in range(L)], "cost": [r.cost[i] for i in range(L)]}
 
 
+def lattice_cbc(log2_points, gamma):
+    """ces_lattice_cbc: generating vector (uint32 array) for 2^log2_points points."""
+    g = np.ascontiguousarray(gamma, dtype=np.float64)
+    z = np.empty(g.size, dtype=np.uint32)
+    check(load().ces_lattice_cbc(int(log2_points), int(g.size), g.ctypes.data_as(ctypes.c_void_p),
+                                 z.ctypes.data_as(ctypes.c_void_p)))
+    return z
+
+
+def mlqmc_run(ctx, levels, finest=None, eps=1e-3, l_start=2, n_pilot=1, theta=0.5, alpha=0.0, cost_model=0,
+              max_rounds=50, seed=0, stream=None):
+    """ces_mlqmc_run: multilevel QMC over lattice plans; returns a dict of
+    the result fields (n = points per shift x shifts)."""
+    lib = load()
+    o = MlqmcOpts()
+    lib.ces_mlqmc_opts_default(ctypes.byref(o))
+    o.eps, o.l_start, o.n_pilot, o.theta = float(eps), int(l_start), int(n_pilot), float(theta)
+    o.alpha, o.cost_model, o.max_rounds, o.seed = float(alpha), int(cost_model), int(max_rounds), int(seed)
+    n = len(levels)
+    lv = (ctypes.c_void_p * n)(*[p.handle.value for p in levels])
+    fv = None if finest is None else (ctypes.c_void_p * n)(*[p.handle.value for p in finest])
+    r = MlmcResult()
+    check(lib.ces_mlqmc_run(ctx.handle, lv, fv, n, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(r)))
+    L = r.levels
+    return {"estimate": r.estimate, "variance": r.variance, "bias": r.bias, "alpha": r.alpha, "beta": r.beta,
+            "gamma": r.gamma, "levels": L, "converged": bool(r.converged), "rounds": r.rounds,
+            "n": [r.n[i] for i in range(L)], "mean": [r.mean[i] for i in range(L)],
+            "var": [r.var[i] for i in range(L)], "cost": [r.cost[i] for i in range(L)]}
+
+
 def coarsest_mesh(desc):
     """ces_mlmc_coarsest_mesh: m_0 of the coarsest-mesh rule for a descriptor."""
     m0 = ctypes.c_int32()
@@ -381,5 +436,5 @@ def profile_read(max_entries=64):
             for i in range(min(n.value, max_entries))}
 
 
-__all__ = ["Context", "Plan", "Server", "level_desc", "mlmc_run", "coarsest_mesh", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc",
+__all__ = ["Context", "Plan", "Server", "level_desc", "mlmc_run", "mlqmc_run", "lattice_cbc", "coarsest_mesh", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc",
            "PlanInfo", "Request", "Schedule", "load"]

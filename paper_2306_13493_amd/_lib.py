@@ -79,6 +79,12 @@ class MlmcResult(ctypes.Structure):
                 ("cost", c_double * MLMC_MAX_LEVELS)]
 
 
+class MlqmcOpts(ctypes.Structure):
+    _fields_ = [("struct_size", c_int32), ("l_start", c_int32), ("eps", c_double), ("n_pilot", c_int64),
+                ("theta", c_double), ("alpha", c_double), ("cost_model", c_int32), ("max_rounds", c_int32),
+                ("seed", c_uint64)]
+
+
 class SmoothingStats(ctypes.Structure):
     _fields_ = [("struct_size", c_int32), ("reserved", c_int32), ("n", c_int64), ("mean", c_double),
                 ("mean_abs", c_double), ("var", c_double), ("mean_q", c_double), ("mean_q_smoothed", c_double)]
@@ -114,6 +120,13 @@ SIGNATURES = {
                                ctypes.POINTER(c_double)]),
     "ces_smoothing_error": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_uint64, c_int64, c_void_p,
                                       ctypes.POINTER(SmoothingStats)]),
+    "ces_lattice_cbc": (c_int32, [c_int32, c_int32, c_void_p, c_void_p]),
+    "ces_plan_lattice_order": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "ces_plan_set_lattice": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32]),
+    "ces_plan_set_lattice_default": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "ces_mlqmc_opts_default": (None, [ctypes.POINTER(MlqmcOpts)]),
+    "ces_mlqmc_run": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int32,
+                                ctypes.POINTER(MlqmcOpts), c_void_p, ctypes.POINTER(MlmcResult)]),
     "ces_normals": (c_int32, [c_uint64, c_uint64, c_uint32, c_uint64, c_int64, c_dptr, c_void_p]),
     "ces_plan_eigenvalues": (c_int32, [c_void_p, c_void_p]),
     "ces_plan_mask": (c_int32, [c_void_p, c_void_p, c_void_p]),

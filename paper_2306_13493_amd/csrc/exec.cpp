@@ -242,6 +242,14 @@ int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st) {
 namespace {
 
 template <typename T>
+void set_lattice(FieldBatch<T>& b, const ces_plan p) {
+    if (p->q_s <= 0) return;
+    b.qrank = p->q_rank.as<int32_t>();
+    b.qz = p->q_z.as<uint32_t>();
+    b.qshifts = p->q_shifts;
+}
+
+template <typename T>
 FieldBatch<T> field_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
     FieldBatch<T> b;
     b.n = p->n;
@@ -263,6 +271,7 @@ FieldBatch<T> field_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
     b.kf_stride = p->kf_ss;
     b.kc = p->kc.as<T>();
     b.kc_stride = p->kc_ss;
+    set_lattice(b, p);
     return b;
 }
 
@@ -292,6 +301,7 @@ FieldBatch<T> embedded_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) 
     b.kf = p->kc.as<T>();
     b.kf_stride = p->kc_ss;
     b.n_src = p->n;
+    set_lattice(b, p);   // counters are the fine embedding's
     return b;
 }
 
@@ -445,6 +455,8 @@ int Scheduler::add(const ces_request& r, hipEvent_t done_event, long long max_sl
     if (r.count < 0) return fail(CES_ERR_ARG, "count < 0");
     if (r.count > 0 && !r.y) return fail(CES_ERR_ARG, "y is NULL");
     if (r.first_sample + (uint64_t)r.count < r.first_sample) return fail(CES_ERR_ARG, "sample range overflows");
+    if (p->q_s > 0 && r.first_sample + (uint64_t)r.count > (1ull << 63))
+        return fail(CES_ERR_ARG, "sample indices of a lattice plan must stay below 2^63");
     if (joined_) return fail(CES_ERR_ARG, "scheduler already joined");
     if (r.count == 0) {
         if (done_event) CES_HIP(hipEventRecord(done_event, caller_), "request event");

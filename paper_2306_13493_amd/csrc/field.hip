@@ -43,6 +43,20 @@ __device__ __forceinline__ int src_index(int j, int n, int ns) {
     return (int)(f >= 0 ? f : f + ns);
 }
 
+// Randomly shifted lattice coordinate j of the point whose radical inverse
+// is qpt (64-bit fraction), shift r: U = (qpt z + D) mod 2^64 with D from
+// Philox counter (j, r, 2^32-1, stream); u = (floor(U/2^12) + 1/2) 2^-52 in
+// (0,1); the normal is Phi^-1(u).
+__device__ __forceinline__ double lattice_normal(uint64_t seed, uint32_t stream, uint64_t r, uint64_t qpt,
+                                                 uint32_t z, uint32_t j) {
+    uint32_t c0 = j, c1 = (uint32_t)r, c2 = 0xFFFFFFFFu, c3 = stream;
+    philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t D = (uint64_t)c0 | ((uint64_t)c1 << 32);
+    const uint64_t U = qpt * (uint64_t)z + D;
+    const double u = ((double)(U >> 12) + 0.5) * 0x1.0p-52;
+    return normcdfinv(u);
+}
+
 template <typename T, int E, int MODE, int NF>
 __global__ __launch_bounds__(kBlock) void k_field_rows(FieldBatch<T> b, int L) {
     extern __shared__ unsigned char smem_raw[];
@@ -51,6 +65,13 @@ __global__ __launch_bounds__(kBlock) void k_field_rows(FieldBatch<T> b, int L) {
     const int u = blockIdx.y;
     const uint64_t q = b.q0 + (uint64_t)u;
     const int j2_0 = blockIdx.x * L;
+    // lattice point (radical-inverse order, as a 64-bit fraction) and shift
+    uint64_t qpt = 0, qsh = 0;
+    if (MODE == MODE_HARTLEY && b.qrank) {
+        const uint64_t i = q / (uint64_t)b.qshifts;
+        qsh = q - i * (uint64_t)b.qshifts;
+        qpt = __builtin_bitreverse64(i);
+    }
     for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
         const int line = t / n;
         const int j1 = t - line * n;
@@ -59,7 +80,13 @@ __global__ __launch_bounds__(kBlock) void k_field_rows(FieldBatch<T> b, int L) {
         uint32_t e = ia;                                                  // normal counter
         if (b.n_src > 0) e = (uint32_t)src_index(j1, n, b.n_src) + (uint32_t)b.n_src * (uint32_t)src_index(j2, n, b.n_src);
         double g0, g1;
-        normal_pair(b.seed, q, b.stream, e, g0, g1);
+        const int jq = (MODE == MODE_HARTLEY && b.qrank) ? b.qrank[e] : -1;
+        if (jq >= 0) {
+            g0 = lattice_normal(b.seed, b.stream, qsh, qpt, b.qz[jq], (uint32_t)jq);
+            g1 = 0.0;
+        } else {
+            normal_pair(b.seed, q, b.stream, e, g0, g1);
+        }
         const double xr = g0;
         const double xi = (MODE == MODE_PAIR) ? g1 : 0.0;
         const double a = (double)b.af[ia];

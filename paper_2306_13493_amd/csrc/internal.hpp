@@ -88,6 +88,12 @@ struct FieldBatch {
     // > 0: draw the normals of the embedding of size n_src of the mesh with
     // half this one's spacing, at the nearest signed frequencies
     int n_src = 0;
+    // lattice (HARTLEY only): qrank[e] = coordinate of normal counter e or
+    // -1; qz = generating vector; unit q is point q / qshifts of shift
+    // q mod qshifts.  qrank = nullptr: Philox normals everywhere
+    const int32_t* qrank = nullptr;
+    const uint32_t* qz = nullptr;
+    int qshifts = 0;
 };
 template <typename T>
 hipError_t launch_field(const FieldBatch<T>& b, hipStream_t st);

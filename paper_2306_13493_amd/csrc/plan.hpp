@@ -124,6 +124,11 @@ struct ces_plan_s {
     // mesh 2h with the coarse drop count); its amplitudes drive the coarse
     // field, its workspace is never used
     std::unique_ptr<ces_plan_s> cpl;
+    // quasi-Monte Carlo lattice (HARTLEY plans): q_s coordinates, generating
+    // vector q_z (q_s uint32), coordinate of each fine normal counter q_rank
+    // (n*n int32, -1 = Philox), q_shifts random shifts; q_s = 0: none
+    int32_t q_s = 0, q_shifts = 0;
+    ces::DevBuf q_z, q_rank;
     std::atomic<int> busy{0};           // a scheduler is using the workspace
     // recorded after the last work that used the workspace; the next lane
     // of this plan waits for it (lanes of successive calls may run on

@@ -1,0 +1,208 @@
+"""GPU tests of the randomised quasi-Monte Carlo path (lattice plans and
+ces_mlqmc_run) against the oracle (oracle/qmc.py) through the C ABI.
+
+Lattice inputs (eigen indices, generating vectors) come from the oracle:
+its eigenvalue order and its CBC, never from the library.  Bars: FP64
+fields 1e-11 of max|Z|, mixed fields 1e-5 of max|Z|; level samples 1e-9
+(FP64) / 1e-6 (mixed) relative; the estimator makes the oracle's decisions
+with estimates to the level-sample bar.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import qmc as oqmc
+from oracle import sampler as osm
+from oracle import mlmc as omlmc
+from paper_2306_13493_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ces():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_13493_amd as ces
+    ces.load()
+    return ces
+
+
+@pytest.fixture(scope="module")
+def ctx(ces):
+    return ces.Context(0)
+
+
+def oracle_lattice(op, s, log2n, R):
+    dims = oqmc.eigen_order(op.lam, s)
+    z = oqmc.cbc(log2n, oqmc.default_weights(np.maximum(op.lam.reshape(-1)[dims], 0.0)))
+    return oqmc.Lattice(z, dims, R)
+
+
+def pair(ctx, ces, w, s, log2n=6, R=4):
+    op = osm.Plan(W.to_oracle(w))
+    lat = oracle_lattice(op, s, log2n, R)
+    op.set_lattice(lat)
+    gp = ctx.plan(ces.level_desc(**w))
+    gp.set_lattice(z=lat.z, dims=lat.dims, shifts=R)
+    return gp, op
+
+
+FIELD_CASES = {
+    "single_fp64": (dict(cov="matern", nu=1.5, lam=0.2, m=16, field="hartley", precision="fp64"), 40),
+    "single_mixed": (dict(cov="matern", nu=1.0, lam=0.1, m=32, field="hartley"), 96),
+    "pair_smoothed_fp64": (dict(cov="matern", nu=1.5, lam=0.1, m=32, level="pair", field="hartley",
+                                tau_fine=0, tau_coarse=-1, precision="fp64", stream=3), 64),
+    "embed_pair": (dict(cov="matern", nu=1.0, lam=0.1, m=64, level="pair", tau_fine=0, tau_coarse=-1,
+                        coupling="embed", field="hartley", stream=2), 128),
+    "tiled_fp64": (dict(cov="matern", nu=1.5, lam=0.1, m=128, field="hartley", precision="fp64"), 512),
+}
+
+
+@pytest.mark.parametrize("name", list(FIELD_CASES))
+def test_lattice_fields_match_oracle(ctx, ces, name):
+    w, s = FIELD_CASES[name]
+    gp, op = pair(ctx, ces, w, s, log2n=6, R=4)
+    tol = 1e-11 if w.get("precision") == "fp64" else 1e-5
+    for g in (0, 1, 5, 4 * 37 + 3):
+        zf, zc = gp.field(11, g)
+        rf, rc = op.fields(11, g)
+        sc = max(np.abs(rf).max(), 1.0)
+        assert np.abs(zf.cpu().numpy() - rf).max() <= tol * sc, (name, g)
+        if rc is not None:
+            assert np.abs(zc.cpu().numpy() - rc).max() <= tol * sc, (name, g)
+
+
+@pytest.mark.parametrize("w,count,tol", [
+    (dict(cov="matern", nu=1.5, lam=0.2, m=16, field="hartley", precision="fp64"), 24, 1e-9),
+    (dict(cov="matern", nu=1.5, lam=0.1, m=32, level="pair", field="hartley", tau_coarse=-1, stream=1), 24, 1e-6),
+    (dict(cov="matern", nu=1.0, lam=0.1, m=128, level="pair", field="hartley", stream=4), 12, 1e-6),
+])
+def test_lattice_level_samples_match_oracle(ctx, ces, w, count, tol):
+    gp, op = pair(ctx, ces, w, 64, log2n=5, R=4)
+    first = 8
+    out = gp.sample(3, first, count)
+    y = out["y"].cpu().numpy()
+    assert np.all(out["status"].cpu().numpy() == 0)
+    ref = np.array([op.sample(3, first + t)[0] for t in range(count)])
+    assert np.abs(y - ref).max() <= tol * max(np.abs(ref).max(), 1e-3)
+
+
+def test_default_order_and_weights(ctx, ces):
+    w = dict(cov="matern", nu=1.5, lam=0.1, m=32, field="hartley", precision="fp64")
+    gp = ctx.plan(ces.level_desc(**w))
+    op = osm.Plan(W.to_oracle(w))
+    dims, lam = gp.lattice_order(100)
+    ref = np.sort(np.maximum(op.lam.reshape(-1), 0.0))[::-1][:100]
+    assert np.abs(lam - ref).max() <= 1e-12 * ref[0]
+    assert len(set(dims.tolist())) == 100 and np.all(np.diff(lam) <= 0)
+    # the default attachment = explicit attachment of the library's order and CBC weights
+    gd = ctx.plan(ces.level_desc(**w))
+    gd.set_lattice(s=100, log2_points=7, shifts=8)
+    ge = ctx.plan(ces.level_desc(**w))
+    t = 0.0
+    for v in lam:   # the library sums the weights in index order
+        t += float(v)
+    ge.set_lattice(z=ces.lattice_cbc(7, lam / t), dims=dims, shifts=8)
+    for g in (0, 9, 77):
+        a, _ = gd.field(5, g)
+        b, _ = ge.field(5, g)
+        assert torch.equal(a, b)
+
+
+def test_detach_restores_monte_carlo(ctx, ces):
+    w = dict(cov="matern", nu=1.0, lam=0.2, m=16, field="hartley", precision="fp64")
+    mc = ctx.plan(ces.level_desc(**w))
+    q = ctx.plan(ces.level_desc(**w))
+    q.set_lattice(s=20, log2_points=4, shifts=4)
+    a, _ = q.field(1, 3)
+    b, _ = mc.field(1, 3)
+    assert not torch.equal(a, b)
+    q.set_lattice(z=[])
+    a, _ = q.field(1, 3)
+    assert torch.equal(a, b)
+
+
+def test_lattice_errors(ctx, ces):
+    pw = ctx.plan(ces.level_desc(cov="matern", nu=1.0, lam=0.2, m=16, field="pair"))
+    with pytest.raises(ces.CesError):
+        pw.set_lattice(s=4, log2_points=4, shifts=4)
+    hp = ctx.plan(ces.level_desc(cov="matern", nu=1.0, lam=0.2, m=16, field="hartley"))
+    with pytest.raises(ces.CesError):
+        hp.set_lattice(z=[1, 3], dims=[5, 5], shifts=4)
+    with pytest.raises(ces.CesError):
+        hp.set_lattice(z=[1], dims=[hp.n * hp.n], shifts=4)
+    with pytest.raises(ces.CesError):
+        hp.set_lattice(z=[1], dims=[0], shifts=1)
+    hp.set_lattice(z=[1], dims=[0], shifts=2)
+    with pytest.raises(ces.CesError):
+        hp.sample(0, 2 ** 63 - 1, 2)
+
+
+def test_shift_averages_beat_monte_carlo(ctx, ces):
+    # a smooth field and a linear QoI: with 64 points per shift the variance
+    # of the QMC level estimate is well below the Monte Carlo one at the same
+    # number of samples (property of the lattice rule, not a parity check)
+    w = dict(cov="matern", nu=2.5, lam=0.3, m=32, field="hartley", stream=5)
+    q = ctx.plan(ces.level_desc(**w))
+    q.set_lattice(s=128, log2_points=6, shifts=16)
+    mc = ctx.plan(ces.level_desc(**w))
+    N, R = 64, 16
+    yq = q.sample(2, 0, N * R)["y"].cpu().numpy()
+    ym = mc.sample(2, 0, N * R)["y"].cpu().numpy()
+    shift_means = np.array([yq[r::R].mean() for r in range(R)])
+    v_qmc = shift_means.var(ddof=1) / R
+    v_mc = ym.var(ddof=1) / (N * R)
+    assert abs(shift_means.mean() - ym.mean()) <= 5 * np.sqrt(v_mc)
+    assert v_qmc < 0.25 * v_mc
+
+
+def levels_for(m0, n, R, log2n, s):
+    descs = []
+    for l in range(n):
+        descs.append(dict(cov="matern", nu=1.5, lam=0.2, m=m0 * 2 ** l, level="single" if l == 0 else "pair",
+                          field="hartley", stream=l))
+    return descs
+
+
+def test_estimator_matches_oracle(ctx, ces):
+    n, R, log2n, s = 4, 8, 8, 32
+    descs = levels_for(8, n, R, log2n, s)
+    oplans = [osm.Plan(W.to_oracle(d)) for d in descs]
+    gplans = []
+    for d, op in zip(descs, oplans):
+        lat = oracle_lattice(op, s, log2n, R)
+        op.set_lattice(lat)
+        gp = ctx.plan(ces.level_desc(**d))
+        gp.set_lattice(z=lat.z, dims=lat.dims, shifts=R)
+        gplans.append(gp)
+    opts = dict(eps=5e-4, l_start=1, n_pilot=2, theta=0.5, max_rounds=12)
+    g = ces.mlqmc_run(ctx, gplans, seed=5, **opts)
+
+    def sample(l, finest, first, count):
+        return [oplans[l].sample(5, first + t)[0] for t in range(count)]
+
+    cost = [omlmc.unknowns(d["m"]) + (omlmc.unknowns(d["m"] // 2) if l > 0 else 0) for l, d in enumerate(descs)]
+    o = oqmc.run(sample, cost, n, shifts_=R, **opts)
+    assert g["levels"] == o["levels"] and bool(g["converged"]) == bool(o["converged"])
+    assert g["n"] == o["n"] and g["rounds"] == o["rounds"]
+    for a, b in zip(g["mean"], o["mean"]):
+        assert abs(a - b) <= 1e-6 * max(abs(b), 1e-4)
+    assert abs(g["estimate"] - o["estimate"]) <= 1e-6 * abs(o["estimate"])
+    assert abs(g["variance"] - o["variance"]) <= 1e-4 * o["variance"]
+    # deterministic bit for bit
+    g2 = ces.mlqmc_run(ctx, gplans, seed=5, **opts)
+    assert g2 == g
+
+
+def test_estimator_rejects_plans_without_lattice(ctx, ces):
+    p0 = ctx.plan(ces.level_desc(cov="matern", nu=1.5, lam=0.2, m=8, field="hartley"))
+    p1 = ctx.plan(ces.level_desc(cov="matern", nu=1.5, lam=0.2, m=16, level="pair", field="hartley"))
+    p0.set_lattice(s=8, log2_points=4, shifts=4)
+    with pytest.raises(ces.CesError):
+        ces.mlqmc_run(ctx, [p0, p1], eps=1e-2)
+    p1.set_lattice(s=8, log2_points=4, shifts=8)
+    with pytest.raises(ces.CesError):
+        ces.mlqmc_run(ctx, [p0, p1], eps=1e-2)
