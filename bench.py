@@ -334,6 +334,69 @@ def smoothing_study(args):
     print(json.dumps(line), flush=True)
 
 
+def estimators(args):
+    """--workload mlqmc: the adaptive MLMC estimator and the multilevel QMC
+    estimator (randomly shifted lattice rules, 16 shifts) on one level
+    hierarchy (Matern nu 3/2, lambda 0.3, sigma2 1, L2 QoI, m = 8 .. 128,
+    Hartley fields, mixed precision), timed to the same RMSE targets.
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2306_13493_amd as ces
+
+    torch.cuda.init()
+    ces.load()
+    ctx = ces.Context(0)
+    nlev, shifts, s_dims, log2_points = 5, 16, 256, 11
+    w = dict(cov="matern", nu=1.5, lam=0.3, sigma2=1.0, qoi="l2", field="hartley")
+    descs = [dict(w, m=8 * 2 ** l, level="single" if l == 0 else "pair", stream=l) for l in range(nlev)]
+    mc = [ctx.plan(ces.level_desc(**d)) for d in descs]
+    qm = [ctx.plan(ces.level_desc(**d)) for d in descs]
+    t0 = time.perf_counter()
+    for p in qm:
+        p.set_lattice(s=s_dims, log2_points=log2_points, shifts=shifts)
+    cbc_s = time.perf_counter() - t0
+    log("lattices: %d coordinates, 2^%d points, %d shifts per level; CBC + attach %.2f s" %
+        (s_dims, log2_points, shifts, cbc_s))
+
+    def cost(r):
+        return float(sum(n * c for n, c in zip(r["n"], r["cost"])))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    # warm both paths (workspaces, graphs) at a loose target
+    ces.mlmc_run(ctx, mc, eps=2e-3, l_start=2, n_pilot=100, seed=99)
+    ces.mlqmc_run(ctx, qm, eps=2e-3, l_start=2, n_pilot=4, seed=99)
+    rows = []
+    for eps in (2e-4, 1e-4, 5e-5):
+        a, ta = timed(lambda: ces.mlmc_run(ctx, mc, eps=eps, l_start=2, n_pilot=100, seed=1))
+        b, tb = timed(lambda: ces.mlqmc_run(ctx, qm, eps=eps, l_start=2, n_pilot=4, seed=1))
+        row = {"eps": eps,
+               "mlmc": {"s": round(ta, 4), "estimate": a["estimate"], "sqrt_variance": a["variance"] ** 0.5,
+                        "levels": a["levels"], "converged": a["converged"], "n": a["n"], "cost": cost(a)},
+               "mlqmc": {"s": round(tb, 4), "estimate": b["estimate"], "sqrt_variance": b["variance"] ** 0.5,
+                         "levels": b["levels"], "converged": b["converged"], "n": b["n"], "cost": cost(b)}}
+        rows.append(row)
+        log("eps=%.0e  MLMC %.3f s (N=%s, est %.6f)  MLQMC %.3f s (N=%s, est %.6f)" %
+            (eps, ta, a["n"], a["estimate"], tb, b["n"], b["estimate"]))
+    last = rows[-1]
+    line = {"metric": "seconds to RMSE eps, multilevel QMC vs adaptive MLMC on the same levels",
+            "value": last["mlqmc"]["s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "Matern nu=3/2 lambda=0.3 sigma2=1, L2 QoI, levels m = 8..128, Hartley fields, "
+                                   "mixed precision; QMC: %d lattice coordinates, CBC for 2^%d points, %d shifts"
+                                   % (s_dims, log2_points, shifts)},
+            "speedup_vs_mlmc": round(last["mlmc"]["s"] / max(last["mlqmc"]["s"], 1e-9), 2),
+            "cost_ratio_vs_mlmc": round(last["mlmc"]["cost"] / max(last["mlqmc"]["cost"], 1.0), 2),
+            "lattice_setup_s": round(cbc_s, 3), "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
 def single_workload(args):
     """--workload c3: the five-level estimator round in one batched call;
     --workload c5: the 2049^2 flow-cell level (Matern 3/2, lambda 0.01,
@@ -393,7 +456,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (scale for HBM counters)")
     ap.add_argument("--study-samples", type=int, default=512, help="smoothing: samples per mesh and form")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "smoothing"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "smoothing", "mlqmc"],
                     help="c2: throughput of the single-level workload (default); c3: five-level batch; "
                          "c4: serving trace; c5: 2049^2 flow cell; smoothing: smoothing error against the mesh")
     ap.add_argument("--rate", type=float, default=200.0, help="c4: arrivals per second")
@@ -414,6 +477,9 @@ def main():
         return
     if args.workload in ("c3", "c5"):
         single_workload(args)
+        return
+    if args.workload == "mlqmc":
+        estimators(args)
         return
 
     import numpy as np
