@@ -159,33 +159,47 @@ def test_shift_averages_beat_monte_carlo(ctx, ces):
     assert v_qmc < 0.25 * v_mc
 
 
-def levels_for(m0, n, R, log2n, s):
+def levels_for(m0, n, smoothed=False, finest=False):
     descs = []
     for l in range(n):
-        descs.append(dict(cov="matern", nu=1.5, lam=0.2, m=m0 * 2 ** l, level="single" if l == 0 else "pair",
-                          field="hartley", stream=l))
+        d = dict(cov="matern", nu=1.5, lam=0.2, m=m0 * 2 ** l, level="single" if l == 0 else "pair",
+                 field="hartley", stream=l)
+        if smoothed:
+            d["tau_coarse"] = -1
+            d["tau_fine"] = 0 if finest else -1
+        descs.append(d)
     return descs
 
 
-def test_estimator_matches_oracle(ctx, ces):
-    n, R, log2n, s = 4, 8, 8, 32
-    descs = levels_for(8, n, R, log2n, s)
-    oplans = [osm.Plan(W.to_oracle(d)) for d in descs]
-    gplans = []
-    for d, op in zip(descs, oplans):
+def lattice_levels(ctx, ces, descs, s, log2n, R):
+    oplans, gplans = [], []
+    for d in descs:
+        op = osm.Plan(W.to_oracle(d))
         lat = oracle_lattice(op, s, log2n, R)
         op.set_lattice(lat)
         gp = ctx.plan(ces.level_desc(**d))
         gp.set_lattice(z=lat.z, dims=lat.dims, shifts=R)
+        oplans.append(op)
         gplans.append(gp)
+    return oplans, gplans
+
+
+@pytest.mark.parametrize("smoothed", [False, True])
+def test_estimator_matches_oracle(ctx, ces, smoothed):
+    n, R, log2n, s = 4, 8, 8, 32
+    descs = levels_for(8, n, smoothed)
+    oplans, gplans = lattice_levels(ctx, ces, descs, s, log2n, R)
+    ofin, gfin = (lattice_levels(ctx, ces, levels_for(8, n, True, True), s, log2n, R) if smoothed
+                  else (None, None))
     opts = dict(eps=5e-4, l_start=1, n_pilot=2, theta=0.5, max_rounds=12)
-    g = ces.mlqmc_run(ctx, gplans, seed=5, **opts)
+    g = ces.mlqmc_run(ctx, gplans, finest=gfin, seed=5, **opts)
 
     def sample(l, finest, first, count):
-        return [oplans[l].sample(5, first + t)[0] for t in range(count)]
+        p = ofin[l] if finest else oplans[l]
+        return [p.sample(5, first + t)[0] for t in range(count)]
 
     cost = [omlmc.unknowns(d["m"]) + (omlmc.unknowns(d["m"] // 2) if l > 0 else 0) for l, d in enumerate(descs)]
-    o = oqmc.run(sample, cost, n, shifts_=R, **opts)
+    o = oqmc.run(sample, cost, n, shifts_=R, finest_differs=smoothed, **opts)
     assert g["levels"] == o["levels"] and bool(g["converged"]) == bool(o["converged"])
     assert g["n"] == o["n"] and g["rounds"] == o["rounds"]
     for a, b in zip(g["mean"], o["mean"]):
@@ -193,7 +207,7 @@ def test_estimator_matches_oracle(ctx, ces):
     assert abs(g["estimate"] - o["estimate"]) <= 1e-6 * abs(o["estimate"])
     assert abs(g["variance"] - o["variance"]) <= 1e-4 * o["variance"]
     # deterministic bit for bit
-    g2 = ces.mlqmc_run(ctx, gplans, seed=5, **opts)
+    g2 = ces.mlqmc_run(ctx, gplans, finest=gfin, seed=5, **opts)
     assert g2 == g
 
 
