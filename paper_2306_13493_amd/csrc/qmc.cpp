@@ -195,6 +195,9 @@ int ces_plan_set_lattice(ces_plan p, int32_t s, const uint32_t* z, const int64_t
         ~Release() { p->busy.store(0); }
     } release{p};
     if (s == 0) {
+        // earlier sampling on the plan may still read the tables
+        CES_HIP(hipSetDevice(p->ctx->device), "hipSetDevice");
+        CES_HIP(hipDeviceSynchronize(), "lattice detach");
         p->q_s = 0;
         p->q_shifts = 0;
         p->q_z.reset();
