@@ -58,6 +58,8 @@ FIELD_CASES = {
     "embed_pair": (dict(cov="matern", nu=1.0, lam=0.1, m=64, level="pair", tau_fine=0, tau_coarse=-1,
                         coupling="embed", field="hartley", stream=2), 128),
     "tiled_fp64": (dict(cov="matern", nu=1.5, lam=0.1, m=128, field="hartley", precision="fp64"), 512),
+    # the benchmark's mesh and covariance (257^2, n = 512) in Hartley form, 1024 lattice coordinates
+    "c2_mesh_mixed": (dict(W.C2, field="hartley"), 1024),
 }
 
 
