@@ -465,8 +465,8 @@ def main():
     ap.add_argument("--max-inflight", type=int, default=64, help="c4: admitted requests at most")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(samples shard by index across GPUs; see the design notes). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(samples would shard by index across GPUs). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "c4":

@@ -6,7 +6,7 @@ smooth periodisation), Algorithm 1 steps 1-3 and Algorithm 2 step 4(b).
 Array convention: a 2-D array ``a`` of the embedding (size n x n) is indexed
 ``a[j2, j1]`` -- x index fastest, the lexicographic order of Section 2.1.2.
 
-Readings of the paper taken here (each listed in the design doc):
+Readings of the paper taken here:
 * J = 0 is the classical mirrored embedding (the cutoff is undefined there).
 * J > 0 evaluates the periodised covariance C^ext of eq. (periodic-cov-fun)
   at every embedding node; the cutoff phi is the paper's eta-quotient with

@@ -4,7 +4,7 @@ Section 3.1 (the Darcy model and its boundary conditions) and Section 3.2
 (piecewise-linear elements; the system is assembled with a nodal
 quadrature rule so that u_h depends on k only through its grid values).
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here:
 * mesh: the (m+1)^2 vertex grid, each square split along the diagonal
   (i, j)-(i+1, j+1);
 * quadrature: trapezoidal (vertex) rule on each triangle, so a triangle's

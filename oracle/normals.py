@@ -1,7 +1,6 @@
 """Seeded standard normals for Algorithm 1 step 4(a) (oracle; test only).
 
-The paper does not name its generator.  Reading used here (listed in
-the design doc): Philox4x32-10 of Salmon, Moraes, Dror and Shaw (SC'11,
+The paper does not name its generator.  Reading used here: Philox4x32-10 of Salmon, Moraes, Dror and Shaw (SC'11,
 "Parallel random numbers: as easy as 1, 2, 3"), written from that paper's
 definition: two 32x32->64 multiplies per round with multipliers
 0xD2511F53 and 0xCD9E8D57, key schedule bumped by the Weyl constants

@@ -9,8 +9,8 @@ Algorithm 1 (level estimate with circulant embedding) and Algorithm 2
 with the fine and coarse coefficients restricted from one field (step
 4(e)).  Smoothing is expressed by two drop counts of the fine level's
 embedding: tau_f for the field solved on the fine mesh and tau_c for the
-field solved on the coarse mesh.  Reading of eq. (mlmc-estimator-smoothed)
-(listed in the design doc): on levels l < L both use tau_l; on the finest level
+field solved on the coarse mesh.  Reading of eq. (mlmc-estimator-smoothed):
+on levels l < L both use tau_l; on the finest level
 L the fine term is unsmoothed (tau_f = 0) and the coarse term keeps tau_L;
 when tau_f != tau_c the two fields come from two DFTs of the same xi.
 With coupling EMBED the coarse field instead comes from the coarse mesh's
