@@ -143,6 +143,34 @@ def test_lattice_errors(ctx, ces):
         hp.sample(0, 2 ** 63 - 1, 2)
 
 
+def test_lattice_levels_in_a_batch(ctx, ces):
+    # lattice and Monte Carlo levels of several sizes in one batch equal one
+    # call per level, bit for bit, also under a small chunk size
+    ws = [dict(cov="matern", nu=1.5, lam=0.2, m=16, field="hartley", stream=0),
+          dict(cov="matern", nu=1.5, lam=0.2, m=64, level="pair", field="hartley", stream=1),
+          dict(cov="matern", nu=1.0, lam=0.1, m=256, level="pair", field="hartley", stream=2),
+          dict(cov="matern", nu=1.0, lam=0.1, m=128, level="pair", stream=3)]
+    plans = [ctx.plan(ces.level_desc(**w)) for w in ws]
+    for p, s in zip(plans[:3], (16, 64, 256)):
+        p.set_lattice(s=s, log2_points=6, shifts=8)
+    counts = [200, 96, 24, 40]
+    reqs = [(p, 9, 8 * i + 3, c) for i, (p, c) in enumerate(zip(plans, counts))]
+    alone = [p.sample(9, f, c) for p, _, f, c in reqs]
+    both = ctx.sample_batch(reqs)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, both):
+        assert torch.equal(a["y"], b["y"])
+    old = ctx.schedule
+    try:
+        ctx.schedule = (2, 2, 7, 0)
+        small = ctx.sample_batch(reqs)
+        torch.cuda.synchronize()
+        for a, b in zip(alone, small):
+            assert torch.equal(a["y"], b["y"])
+    finally:
+        ctx.schedule = old
+
+
 def test_shift_averages_beat_monte_carlo(ctx, ces):
     # a smooth field and a linear QoI: with 64 points per shift the variance
     # of the QMC level estimate is well below the Monte Carlo one at the same
