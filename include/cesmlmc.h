@@ -25,7 +25,8 @@
  *     take a stream only enqueue work unless stated otherwise.
  *   - Contexts and plans are created and destroyed by the library.  A
  *     context is used by one host thread at a time.  A plan is immutable
- *     after creation and belongs to its context.
+ *     after creation, apart from the lattice ces_plan_set_lattice attaches,
+ *     and belongs to its context.
  *   - Nodal arrays are (m+1) x (m+1) with the x index fastest
  *     (p = i1 + (m+1) i2), the lexicographic order of Section 2.1.2.
  *   - Determinism: sample i of a plan is a pure function of
@@ -147,8 +148,10 @@ void ces_level_desc_default(ces_level_desc* d);
 /* Bind to HIP device `device`.  mem_budget_bytes caps the library's own
  * workspace (0 = 90% of free device memory).  A plan's sample workspace,
  * allocated on its first sampling call, holds as many samples as fit in
- * 4 GiB (at most 8192; 65536 for m <= 32), or in the size in MiB given by
- * the environment variable CESMLMC_WORKSPACE_MB, and within the budget. */
+ * 4.5 GiB (at most 8192; 65536 for m <= 32), or in the size in MiB given by
+ * the environment variable CESMLMC_WORKSPACE_MB, and within the budget.  A
+ * request larger than the workspace runs in the fewest chunks that fit,
+ * all of (nearly) equal size. */
 int ces_context_create(int device, size_t mem_budget_bytes, ces_context* out);
 int ces_context_destroy(ces_context ctx);
 

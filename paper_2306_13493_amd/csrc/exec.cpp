@@ -172,7 +172,7 @@ long long workspace_slots(const ces_plan p, long long max_slots) {
     const int m = p->d.m_fine;
     const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
     const size_t per_slot = slot_bytes(p);
-    size_t target = (size_t)4 << 30;
+    size_t target = (size_t)9 << 29;   // 4.5 GiB
     if (const char* env = std::getenv("CESMLMC_WORKSPACE_MB")) target = (size_t)std::atoll(env) << 20;
     const size_t used = p->ctx->used.load();
     if (p->ctx->budget && p->ctx->budget - std::min(p->ctx->budget, used) < target)
@@ -472,6 +472,9 @@ int Scheduler::add(const ces_request& r, hipEvent_t done_event, long long max_sl
     if (s_.chunk_samples > 0) cu = std::max<long long>(1, std::min<long long>(cu, s_.chunk_samples / per_unit));
     const uint64_t first = r.first_sample, last = first + (uint64_t)r.count - 1;
     const uint64_t u_begin = first / per_unit, u_end = last / per_unit + 1;
+    // as few chunks as the workspace allows, of equal size (no short tail chunk)
+    const uint64_t nch = (u_end - u_begin + (uint64_t)cu - 1) / (uint64_t)cu;
+    cu = (long long)((u_end - u_begin + nch - 1) / nch);
     for (uint64_t u0 = u_begin; u0 < u_end; u0 += (uint64_t)cu) {
         Job j;
         j.seed = r.seed;

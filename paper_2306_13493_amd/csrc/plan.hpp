@@ -154,7 +154,7 @@ int validate_desc(const ces_level_desc* d);
 
 // Allocates the plan's sample workspace on first use (zeroed on stream st).
 // max_slots > 0 caps the samples per chunk (the serving loop sizes
-// workspaces per request); 0 sizes it for throughput (about 4 GiB, at
+// workspaces per request); 0 sizes it for throughput (about 4.5 GiB, at
 // most 8192 samples, 65536 for m <= 32).
 int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st);
 // Device bytes ensure_workspace(p, max_slots) would allocate.
