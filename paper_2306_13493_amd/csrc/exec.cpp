@@ -226,11 +226,15 @@ int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st) {
     cfg.qoi = p->d.qoi;
     cfg.qx = p->d.qoi_x;
     cfg.qy = p->d.qoi_y;
+    // single levels (plain Monte Carlo, the coarsest MLMC level) run the
+    // most samples per chunk: there the second visit of level 1 pays
+    cfg.twice1 = p->d.level_kind == CES_LEVEL_SINGLE;
     std::string err;
     p->sf = make_solver(cfg, (int)slots, p->is_double, A, st, &err);
     if (!p->sf) return fail(CES_ERR_NOMEM, err);
     if (p->d.level_kind == CES_LEVEL_PAIR) {
         cfg.m = m / 2;
+        cfg.twice1 = false;
         p->sc = make_solver(cfg, (int)slots, p->is_double, A, st, &err);
         if (!p->sc) return fail(CES_ERR_NOMEM, err);
     }

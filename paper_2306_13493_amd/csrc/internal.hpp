@@ -118,10 +118,15 @@ struct SolverCfg {
     int maxit = 500;
     int qoi = Q_INTEGRAL;
     double qx = 7.0 / 15.0, qy = 7.0 / 15.0;
+    // visit multigrid level 1 twice per cycle when it is a whole level
+    // (fewer CG iterations for a few extra launches: worth it where chunks
+    // hold many samples, as single levels do)
+    bool twice1 = false;
 };
 
 // Batched PCG (double) preconditioned by a geometric multigrid V(2,2) cycle
-// in T, for S samples of one mesh at a time.  A solve is a small state
+// in T (level 1 visited twice when SolverCfg::twice1 asks and it is a whole
+// level), for S samples of one mesh at a time.  A solve is a small state
 // machine so that one host thread can interleave the solves of several
 // meshes on several streams: begin() enqueues the set-up, each advance()
 // enqueues at most one more iteration and notes (without blocking) which

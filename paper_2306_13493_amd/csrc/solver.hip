@@ -176,16 +176,21 @@ __device__ __forceinline__ void mg_half_sweep(T (&z)[SH][2], const T (&rhs)[SH][
 // RXW = 128 (float only): the same with 128 x 128 regions, a workgroup of
 // 16 waves of 64 lanes (lane k owns columns 2k, 2k+1 of its wave's SH
 // rows), for Dirichlet levels with 64 < m - 1 <= 128.
-template <typename T, int SH, bool POST, bool L0, bool WHOLE, int RXW = 64>
+// MID (POST, WHOLE, coarser levels): the step between the two coarse
+// corrections of a level visited twice per cycle: z = z_pre + P z_c, then
+// the residual restricted to the coarse rhs (no smoothing); z goes back
+// to z_pre in place (one workgroup holds the whole level).
+template <typename T, int SH, bool POST, bool L0, bool WHOLE, int RXW = 64, bool MID = false>
 __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
     static_assert(RXW == 64 || (RXW == 128 && WHOLE), "128-wide regions: whole levels only");
+    static_assert(!MID || (POST && WHOLE && !L0), "MID: whole coarser levels");
     constexpr int NT = RXW == 64 ? kBlock : 1024, LW = RXW / 2;
     constexpr int RX = RXW, NH = NT / LW, RY = NH * SH;
     constexpr int H = WHOLE ? 0 : (POST ? 4 : 6);
     constexpr int TX = RX - 2 * H, TY = RY - 2 * H;
     constexpr int PX = RX + 2, PY = RY + 2;   // padded: one-node ring on every side
     __shared__ T sz[PY * PX];
-    __shared__ T sk[(L0 || !POST) ? PY * PX : 1];    // level 0: k; PRE reuses it for the residual
+    __shared__ T sk[(L0 || !POST || MID) ? PY * PX : 1];    // level 0: k; PRE and MID: the residual
     constexpr int CX = RX / 2 + 3, CY = RY / 2 + 3;
     __shared__ T szc[POST ? CY * CX : 1];
     __shared__ double red[NT / 64];
@@ -398,17 +403,19 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
     // the active column of row 0 for colour c is (c - ox - oy) & 1 (ly0 is even)
     const int par = (ox + oy) & 1;
     const int c0 = POST ? 1 : 0;
+    if constexpr (!MID) {
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-        const int c = (h & 1) ? 1 - c0 : c0;
-        if (((c - par) & 1) == 0)
-            mg_half_sweep<T, SH, 0, PX>(z, rhs, id, ce, cw0, cn, sz0);
-        else
-            mg_half_sweep<T, SH, 1, PX>(z, rhs, id, ce, cw0, cn, sz0);
+        for (int h = 0; h < 4; ++h) {
+            const int c = (h & 1) ? 1 - c0 : c0;
+            if (((c - par) & 1) == 0)
+                mg_half_sweep<T, SH, 0, PX>(z, rhs, id, ce, cw0, cn, sz0);
+            else
+                mg_half_sweep<T, SH, 1, PX>(z, rhs, id, ce, cw0, cn, sz0);
+        }
     }
     // outputs on the tile (margin >= H); id != 0 marks unknown nodes
     double acc = 0.0;
-    T* out = POST ? a.zout + sbase : a.za + sbase;
+    T* out = (POST && !MID) ? a.zout + sbase : a.za + sbase;
 #pragma unroll
     for (int r = 0; r < SH; ++r) {
         const int ly = ly0 + r, gy = oy + ly;
@@ -423,7 +430,7 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
             }
         }
     }
-    if constexpr (POST) {
+    if constexpr (POST && !MID) {
         if constexpr (L0) {
             acc = block_sum(acc, red);
             if (threadIdx.x == 0) a.dot[(size_t)s * a.ntiles + tile] = acc;
@@ -1805,10 +1812,19 @@ private:
         return sizeof(T) == 4 && cfg_.bc == BC_DIRICHLET0 && lv_[l].m - 1 > 64 && lv_[l].m - 1 <= 128;
     }
 
+    // Level 1 is visited twice per cycle (a W-cycle at that level) when the
+    // configuration asks for it and level 1 is a whole level with coarser
+    // kernel levels or the bottom below it: the second coarse correction
+    // costs a fraction of an iteration and cuts the CG iterations (257^2,
+    // Matern nu = 1, lambda = 0.1: 10 -> 8), a gain where launches carry
+    // many samples.  Both corrections are the same symmetric operator, so
+    // the preconditioner stays symmetric.
+    bool twice1() const { return cfg_.twice1 && lb_ >= 2 && (whole(1) || whole128(1)); }
+
     void vcycle(int it, hipStream_t st) {
         const int S = S_;
         const double sT = sizeof(T);
-        for (int l = 0; l < lb_; ++l) {
+        auto pre = [&](int l) {
             const Lvl& L = lv_[l];
             const bool w128 = whole128(l);
             const bool wh = whole(l) || w128;
@@ -1832,8 +1848,8 @@ private:
                 else if (wh) PLAUNCH((k_mg<T, SH, false, false, true>), g, b, 0, st, a);
                 else PLAUNCH((k_mg<T, SH, false, false, false>), g, b, 0, st, a);
             });
-        }
-        {
+        };
+        auto bottom = [&]() {
             BottomArgs<T> b{};
             b.nl = nlev_ - lb_;
             b.bc = cfg_.bc;
@@ -1856,8 +1872,8 @@ private:
                 else
                     PLAUNCH((k_bottom<T, MB, 1024>), dim3(S), dim3(1024), 0, st, b);
             });
-        }
-        for (int l = lb_ - 1; l >= 0; --l) {
+        };
+        auto post = [&](int l) {
             const Lvl& L = lv_[l];
             const bool w128 = whole128(l);
             const bool wh = whole(l) || w128;
@@ -1883,6 +1899,35 @@ private:
                 else if (wh) PLAUNCH((k_mg<T, SH, true, false, true>), g, b, 0, st, a);
                 else PLAUNCH((k_mg<T, SH, true, false, false>), g, b, 0, st, a);
             });
+        };
+        // between the two coarse corrections of level l (a whole level):
+        // z_pre += P z_c in place, coarse rhs = R (rhs - A z_pre)
+        auto mid = [&](int l) {
+            MgArgs<T> a = mg_args(l, 1, 1);
+            a.zc = ptr<T>(o_zb_[l]);
+            a.rhs_c = ptr<T>(o_rhs_[l]);
+            launch("mg_mid", 2.0 * nv(l) * sT + nu(l) * 3.0 * sT + 2.0 * nu(l + 1) * sT, S, it, st,
+                   [&](const Profiler::Slot& ps) {
+                if constexpr (sizeof(T) == 4) {
+                    if (whole128(l)) {
+                        PLAUNCH((k_mg<T, SH, true, false, true, 128, true>), dim3(S), dim3(1024), 0, st, a);
+                        return;
+                    }
+                }
+                PLAUNCH((k_mg<T, SH, true, false, true, 64, true>), dim3(S), dim3(kBlock), 0, st, a);
+            });
+        };
+        const bool w1 = twice1();
+        for (int l = 0; l < lb_; ++l) pre(l);
+        bottom();
+        for (int l = lb_ - 1; l >= 0; --l) {
+            if (w1 && l == 1) {
+                mid(1);
+                for (int k = 2; k < lb_; ++k) pre(k);
+                bottom();
+                for (int k = lb_ - 1; k >= 2; --k) post(k);
+            }
+            post(l);
         }
     }
 

@@ -135,7 +135,10 @@ def test_field_parity(ctx, ces, name, prec, tol):
 
 # ------------------------------------------------------------------ solve
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("bc,m", [("dirichlet0", 32), ("flowcell", 32), ("dirichlet0", 64), ("flowcell", 128)])
+# single-level plans visit multigrid level 1 twice when it is a whole level:
+# Dirichlet m = 64 (FP64), 128 and 256 (mixed) take that path
+@pytest.mark.parametrize("bc,m", [("dirichlet0", 32), ("flowcell", 32), ("dirichlet0", 64), ("flowcell", 128),
+                                  ("dirichlet0", 128), ("dirichlet0", 256)])
 def test_solve_parity(ctx, ces, prec, bc, m):
     w = dict(cov="matern", nu=1.0, lam=0.2, m=m, bc=bc, precision=prec, cg_rtol=1e-12)
     p = mkplan(ctx, ces, w)
