@@ -27,10 +27,11 @@ METRIC = "MLMC level samples/sec (field+solve) at 1 GPU, p50/p99 latency, % HBM 
 HBM_PEAK_GBS = 8000.0
 # library kernel name -> device kernel symbol (mixed path) in rocprofv3 output
 KERNEL_SYMBOL = {
-    "mg_post_l0": "k_mg<float, 8, true, true, false>",
-    "mg_pre_l0": "k_mg<float, 8, false, true, false>",
-    "mg_post": "k_mg<float, 8, true, false, false>",
-    "mg_pre": "k_mg<float, 8, false, false, false>",
+    "mg_post_l0": "k_mg<float, 8, true, true, false, 64, false>",
+    "mg_pre_l0": "k_mg<float, 8, false, true, false, 64, false>",
+    "mg_post": "k_mg<float, 8, true, false, false, 64, false>",
+    "mg_pre": "k_mg<float, 8, false, false, false, 64, false>",
+    "mg_mid": "k_mg<float, 8, true, false, true, 128, true>",
     "mg_bottom": "k_bottom<float, 32, 256>",
     "pcg_dir": "k_pcg_dir<float>",
     "pcg_update": "k_pcg_update<false>",
