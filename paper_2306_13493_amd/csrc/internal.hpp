@@ -120,7 +120,8 @@ struct SolverCfg {
     double qx = 7.0 / 15.0, qy = 7.0 / 15.0;
     // visit multigrid level 1 twice per cycle when it is a whole level
     // (fewer CG iterations for a few extra launches: worth it where chunks
-    // hold many samples, as single levels do)
+    // hold many samples, as single levels do, and the coarse levels resolve
+    // the coefficient)
     bool twice1 = false;
 };
 
