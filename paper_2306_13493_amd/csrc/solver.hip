@@ -176,14 +176,14 @@ __device__ __forceinline__ void mg_half_sweep(T (&z)[SH][2], const T (&rhs)[SH][
 // RXW = 128 (float only): the same with 128 x 128 regions, a workgroup of
 // 16 waves of 64 lanes (lane k owns columns 2k, 2k+1 of its wave's SH
 // rows), for Dirichlet levels with 64 < m - 1 <= 128.
-// MID (POST, WHOLE, coarser levels): the step between the two coarse
-// corrections of a level visited twice per cycle: z = z_pre + P z_c, then
-// the residual restricted to the coarse rhs (no smoothing); z goes back
-// to z_pre in place (one workgroup holds the whole level).
+// MID (POST, coarser levels): the step between the two coarse corrections
+// of a level visited twice per cycle: z = z_pre + P z_c, then the residual
+// restricted to the coarse rhs (no smoothing); z goes to zout, which a
+// whole level may point at z_pre itself (one workgroup holds the level).
 template <typename T, int SH, bool POST, bool L0, bool WHOLE, int RXW = 64, bool MID = false>
 __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
     static_assert(RXW == 64 || (RXW == 128 && WHOLE), "128-wide regions: whole levels only");
-    static_assert(!MID || (POST && WHOLE && !L0), "MID: whole coarser levels");
+    static_assert(!MID || (POST && !L0), "MID: coarser levels");
     constexpr int NT = RXW == 64 ? kBlock : 1024, LW = RXW / 2;
     constexpr int RX = RXW, NH = NT / LW, RY = NH * SH;
     constexpr int H = WHOLE ? 0 : (POST ? 4 : 6);
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
     }
     // outputs on the tile (margin >= H); id != 0 marks unknown nodes
     double acc = 0.0;
-    T* out = (POST && !MID) ? a.zout + sbase : a.za + sbase;
+    T* out = POST ? a.zout + sbase : a.za + sbase;
 #pragma unroll
     for (int r = 0; r < SH; ++r) {
         const int ly = ly0 + r, gy = oy + ly;
@@ -1464,6 +1464,7 @@ public:
             o_za_.push_back(take(nl));
             o_zb_.push_back(take(nl));
         }
+        if (twice1_tiled()) o_zm_ = take((size_t)cap * lv_[1].ss * sizeof(T));
         o_part_ = take((size_t)cap * max_parts_ * 8);
         o_part2_ = take((size_t)cap * max_parts_ * 8);
         o_scal_ = take((size_t)cap * sizeof(Scal));
@@ -1813,13 +1814,15 @@ private:
     }
 
     // Level 1 is visited twice per cycle (a W-cycle at that level) when the
-    // configuration asks for it and level 1 is a whole level with coarser
-    // kernel levels or the bottom below it: the second coarse correction
-    // costs a fraction of an iteration and cuts the CG iterations (257^2,
-    // Matern nu = 1, lambda = 0.1: 10 -> 8), a gain where launches carry
-    // many samples.  Both corrections are the same symmetric operator, so
-    // the preconditioner stays symmetric.
-    bool twice1() const { return cfg_.twice1 && lb_ >= 2 && (whole(1) || whole128(1)); }
+    // configuration asks for it and level 1 has coarser kernel levels or the
+    // bottom below it: the second coarse correction costs a fraction of an
+    // iteration and cuts the CG iterations (257^2, Matern nu = 1, lambda =
+    // 0.1: 10 -> 8), a gain where launches carry many samples.  Both
+    // corrections are the same symmetric operator, so the preconditioner
+    // stays symmetric.  A tiled level 1 keeps its corrected z_pre in a
+    // buffer of its own (tiles read their neighbours' z_pre).
+    bool twice1() const { return cfg_.twice1 && lb_ >= 2; }
+    bool twice1_tiled() const { return twice1() && !(whole(1) || whole128(1)); }
 
     void vcycle(int it, hipStream_t st) {
         const int S = S_;
@@ -1882,6 +1885,7 @@ private:
             a.zc = ptr<T>(o_zb_[l]);
             a.zout = l == 0 ? ptr<T>(o_Z_) : ptr<T>(o_zb_[l - 1]);
             a.dot = ptr<double>(o_part_);
+            if (l == 1 && twice1_tiled()) a.za = ptr<T>(o_zm_);
             // k, z_pre, rhs, coarse correction in; z out (level 0: r in double)
             const double post = l == 0 ? nv(0) * sT + nu(0) * (sT + 8.0 + sT) + nu(1) * sT
                                        : 2.0 * nv(l) * sT + nu(l) * 3.0 * sT + nu(l + 1) * sT;
@@ -1900,21 +1904,28 @@ private:
                 else PLAUNCH((k_mg<T, SH, true, false, false>), g, b, 0, st, a);
             });
         };
-        // between the two coarse corrections of level l (a whole level):
-        // z_pre += P z_c in place, coarse rhs = R (rhs - A z_pre)
+        // between the two coarse corrections of level l: z = z_pre + P z_c
+        // (in place on a whole level, else into its own buffer), coarse
+        // rhs = R (rhs - A z)
         auto mid = [&](int l) {
-            MgArgs<T> a = mg_args(l, 1, 1);
+            const Lvl& L = lv_[l];
+            const bool w128 = whole128(l);
+            const bool wh = whole(l) || w128;
+            const int tx = wh ? 1 : cdiv(L.m - 1, POST_TX), ty = wh ? 1 : cdiv(L.yhi - L.ylo + 1, POST_TY);
+            MgArgs<T> a = mg_args(l, tx, tx * ty);
             a.zc = ptr<T>(o_zb_[l]);
             a.rhs_c = ptr<T>(o_rhs_[l]);
+            a.zout = wh ? a.za : ptr<T>(o_zm_);
             launch("mg_mid", 2.0 * nv(l) * sT + nu(l) * 3.0 * sT + 2.0 * nu(l + 1) * sT, S, it, st,
                    [&](const Profiler::Slot& ps) {
                 if constexpr (sizeof(T) == 4) {
-                    if (whole128(l)) {
+                    if (w128) {
                         PLAUNCH((k_mg<T, SH, true, false, true, 128, true>), dim3(S), dim3(1024), 0, st, a);
                         return;
                     }
                 }
-                PLAUNCH((k_mg<T, SH, true, false, true, 64, true>), dim3(S), dim3(kBlock), 0, st, a);
+                if (wh) PLAUNCH((k_mg<T, SH, true, false, true, 64, true>), dim3(S), dim3(kBlock), 0, st, a);
+                else PLAUNCH((k_mg<T, SH, true, false, false, 64, true>), dim3(tx * ty * S), dim3(kBlock), 0, st, a);
             });
         };
         const bool w1 = twice1();
@@ -1938,7 +1949,7 @@ private:
     int rz_parts_ = 0, ublocks_ = 0, max_parts_ = 0;
     size_t o_X_ = 0, o_R_ = 0, o_P0_ = 0, o_P1_ = 0, o_Q_ = 0, o_Z_ = 0, o_za0_ = 0;
     std::vector<size_t> o_ce_, o_cn_, o_rhs_, o_za_, o_zb_;
-    size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0;
+    size_t o_part_ = 0, o_part2_ = 0, o_scal_ = 0, o_q_ = 0, o_it_ = 0, o_cnt_ = 0, o_zm_ = 0;
     std::vector<int> hist_h_;   // active samples per iteration (launch profiler)
     std::vector<std::pair<int, int>> recs_;
     size_t bytes_ = 0;
