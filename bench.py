@@ -605,22 +605,30 @@ def main():
         v64 = nrep * count / (time.perf_counter() - t1)
         om = plan.sample(seed, (nrep - 1) * count, count)
         diff = float(torch.max(torch.abs(om["y"] - o64["y"]) / torch.abs(o64["y"])).item())
-        # the plain FP64 path one sample per call (no batching)
+        # the plain FP64 path one sample per call (no batching), with the
+        # default cycle and with the V-cycle (fewer launches per iteration)
         n1 = 32
         y1 = torch.empty(1, dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for i in range(n1):
-            p64.lib.ces_sample(p64.handle, seed, i, 1, ces._ptr(y1), None, None, None, None,
-                               ces._stream_ptr(None))
-        torch.cuda.synchronize()
-        v1 = n1 / (time.perf_counter() - t1)
+        pv = ctx.plan(ces.level_desc(**dict(w, precision="fp64", cycle="v")))
+
+        def one_per_call(pp):
+            pp.lib.ces_sample(pp.handle, seed, 0, 1, ces._ptr(y1), None, None, None, None, ces._stream_ptr(None))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for i in range(n1):
+                pp.lib.ces_sample(pp.handle, seed, i, 1, ces._ptr(y1), None, None, None, None,
+                                  ces._stream_ptr(None))
+            torch.cuda.synchronize()
+            return n1 / (time.perf_counter() - t1)
+
+        v1 = one_per_call(p64)
+        v1v = one_per_call(pv)
         extra["fp64_plain_path"] = {"value": round(v64, 1), "unit": "samples/s",
                                     "mixed_vs_fp64_max_rel_diff_Y": diff,
                                     "one_sample_per_call": {"value": round(v1, 1), "unit": "samples/s",
-                                                            "samples": n1}}
-        log("plain FP64 path %.1f samples/s batched, %.1f samples/s one per call; mixed vs FP64 max rel diff %.2e"
-            % (v64, v1, diff))
+                                                            "samples": n1, "v_cycle": round(v1v, 1)}}
+        log("plain FP64 path %.1f samples/s batched, %.1f samples/s one per call (%.1f with the V-cycle); "
+            "mixed vs FP64 max rel diff %.2e" % (v64, v1, v1v, diff))
 
     if not args.no_c3:
         extra["c3_mlmc_batch"] = c3_batch(ces, ctx, W, log)

@@ -92,6 +92,15 @@ enum { CES_QOI_INTEGRAL = 0, CES_QOI_POINT = 1, CES_QOI_L2 = 2, CES_QOI_OUTFLUX 
  * exactly; plan creation fails with CES_ERR_ARG when n_f < 2 n_c (the
  * coarse mesh padded relatively more than the fine one). */
 enum { CES_COUPLE_RESTRICT = 0, CES_COUPLE_EMBED = 1 };
+/* Multigrid cycle of the CG preconditioner (the solver of Algorithm 1 step
+ * 4(g) is this build's; the paper uses GMRES with ILU).  V: V(2,2) cycle.
+ * W1: level 1 visited twice per cycle (two coarse corrections, the same
+ * symmetric operator), fewer CG iterations for a few more launches per
+ * iteration: faster where a call carries many samples, slower for one
+ * sample per call.  AUTO: W1 for SINGLE levels whose length scale (lambda /
+ * sqrt(2 nu) for Matern, lambda for SEPEXP) spans at least 8 fine cells, V
+ * otherwise.  Meshes with m <= 32 solve with their own small-mesh cycle. */
+enum { CES_CYCLE_AUTO = 0, CES_CYCLE_V = 1, CES_CYCLE_W1 = 2 };
 
 typedef struct ces_context_s* ces_context;
 typedef struct ces_plan_s* ces_plan;
@@ -123,6 +132,8 @@ typedef struct {
     double cg_rtol;        /* stop when ||r||_2 <= cg_rtol ||r_0||_2 */
     int32_t cg_max_iter;   /* iteration cap per solve */
     uint32_t stream;       /* level tag: fourth Philox counter word */
+    int32_t mg_cycle;      /* CES_CYCLE_* */
+    int32_t reserved;      /* 0 */
 } ces_level_desc;
 
 typedef struct {

@@ -27,6 +27,7 @@ PREC = {"fp64": 0, "mixed": 1}
 BC = {"dirichlet0": 0, "flowcell": 1}
 QOI = {"integral": 0, "point": 1, "l2": 2, "outflux": 3}
 COUPLE = {"restrict": 0, "embed": 1}
+CYCLE = {"auto": 0, "v": 1, "w1": 2}
 
 
 def _enum(table, v):
@@ -36,7 +37,7 @@ def _enum(table, v):
 def level_desc(cov="matern", nu=0.5, lam=0.1, sigma2=1.0, m=32, level="single", tau_fine=0,
                tau_coarse=0, psd="grow", period="euclid", max_pad=4, field="pair", precision="mixed",
                bc="dirichlet0", qoi="integral", qoi_x=7.0 / 15.0, qoi_y=7.0 / 15.0, f=1.0, cg_rtol=1e-10,
-               cg_max_iter=500, stream=0, coupling="restrict"):
+               cg_max_iter=500, stream=0, coupling="restrict", cycle="auto"):
     """Build a ces_level_desc (library defaults, then the given fields)."""
     lib = load()
     d = LevelDesc()
@@ -57,6 +58,7 @@ def level_desc(cov="matern", nu=0.5, lam=0.1, sigma2=1.0, m=32, level="single", 
     d.bc = _enum(BC, bc)
     d.qoi = _enum(QOI, qoi)
     d.coupling = _enum(COUPLE, coupling)
+    d.mg_cycle = _enum(CYCLE, cycle)
     d.qoi_x = float(qoi_x)
     d.qoi_y = float(qoi_y)
     d.f_value = float(f)

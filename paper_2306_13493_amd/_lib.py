@@ -31,7 +31,8 @@ class LevelDesc(ctypes.Structure):
         ("tau_coarse", c_int64), ("psd_policy", c_int32), ("periodization", c_int32),
         ("max_pad_factor", c_int32), ("field_mode", c_int32), ("precision", c_int32), ("bc", c_int32),
         ("qoi", c_int32), ("coupling", c_int32), ("qoi_x", c_double), ("qoi_y", c_double), ("f_value", c_double),
-        ("cg_rtol", c_double), ("cg_max_iter", c_int32), ("stream", c_uint32)]
+        ("cg_rtol", c_double), ("cg_max_iter", c_int32), ("stream", c_uint32), ("mg_cycle", c_int32),
+        ("reserved", c_int32)]
 
 
 class PlanInfo(ctypes.Structure):

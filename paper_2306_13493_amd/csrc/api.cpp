@@ -145,6 +145,7 @@ int validate_desc(const ces_level_desc* d) {
     if (d->coupling != CES_COUPLE_RESTRICT && d->coupling != CES_COUPLE_EMBED) return fail(CES_ERR_ARG, "coupling");
     if (d->coupling == CES_COUPLE_EMBED && d->level_kind != CES_LEVEL_PAIR)
         return fail(CES_ERR_ARG, "coupling EMBED applies to PAIR levels");
+    if (d->mg_cycle < CES_CYCLE_AUTO || d->mg_cycle > CES_CYCLE_W1) return fail(CES_ERR_ARG, "mg_cycle");
     return CES_OK;
 }
 

@@ -237,13 +237,14 @@ int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st) {
     // 11.0 -> 10.0 iterations but -3%; Matern 3/2 at lambda = 0.01 more
     // iterations (11.4 -> 11.9) and -15%.
     const double ell = p->d.cov_kind == CES_COV_MATERN ? p->d.lambda / std::sqrt(2.0 * p->d.nu) : p->d.lambda;
-    cfg.twice1 = p->d.level_kind == CES_LEVEL_SINGLE && ell * m >= 8.0;
+    const bool w1 = p->d.mg_cycle == CES_CYCLE_W1;
+    cfg.twice1 = w1 || (p->d.mg_cycle == CES_CYCLE_AUTO && p->d.level_kind == CES_LEVEL_SINGLE && ell * m >= 8.0);
     std::string err;
     p->sf = make_solver(cfg, (int)slots, p->is_double, A, st, &err);
     if (!p->sf) return fail(CES_ERR_NOMEM, err);
     if (p->d.level_kind == CES_LEVEL_PAIR) {
         cfg.m = m / 2;
-        cfg.twice1 = false;
+        cfg.twice1 = w1;
         p->sc = make_solver(cfg, (int)slots, p->is_double, A, st, &err);
         if (!p->sc) return fail(CES_ERR_NOMEM, err);
     }

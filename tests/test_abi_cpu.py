@@ -40,7 +40,7 @@ def test_struct_layouts(lib):
     from paper_2306_13493_amd import _lib
     d = _lib.LevelDesc()
     lib.ces_level_desc_default(ctypes.byref(d))
-    assert d.struct_size == ctypes.sizeof(_lib.LevelDesc) == 128
+    assert d.struct_size == ctypes.sizeof(_lib.LevelDesc) == 136 and d.mg_cycle == 0
     assert ctypes.sizeof(_lib.PlanInfo) == 72
     assert d.m_fine == 32 and d.cg_rtol == 1e-10 and d.cg_max_iter == 500 and d.f_value == 1.0
     assert abs(d.qoi_x - 7 / 15) < 1e-16 and d.precision == 1 and d.psd_policy == 0

@@ -367,3 +367,37 @@ def test_sample_indices_beyond_32_bits(ctx, ces):
     yr = np.array([o.sample(7, first + t)[0] for t in range(4)])
     scale = max(abs(o.sample(7, first)[1]), 1e-12)
     assert np.max(np.abs(y - yr)) <= 1e-9 * scale
+
+
+# ------------------------------------------------------ multigrid cycle
+@pytest.mark.parametrize("w", [
+    dict(cov="matern", nu=1.0, lam=0.1, m=256, precision="mixed"),
+    dict(cov="matern", nu=1.0, lam=0.1, m=128, level="pair", precision="fp64", stream=3),
+    dict(cov="matern", nu=1.0, lam=0.2, m=128, bc="flowcell", qoi="outflux", precision="mixed", cg_rtol=1e-12),
+])
+def test_cycle_choices_agree_with_oracle(ctx, ces, w):
+    # the cycle changes the iterations, not the solution: V, W1 and the
+    # automatic choice all meet the level-sample bar against the oracle
+    count = 4
+    o = oracle_plan(w)
+    ref = np.array([o.sample(5, t)[0] for t in range(count)])
+    tol = 1e-9 if w["precision"] == "fp64" else 1e-6
+    its = {}
+    for cyc in ("v", "w1", "auto"):
+        p = mkplan(ctx, ces, dict(w, cycle=cyc))
+        out = p.sample(seed=5, first=0, count=count)
+        torch.cuda.synchronize()
+        assert np.all(out["status"].cpu().numpy() == 0)
+        y = out["y"].cpu().numpy()
+        assert np.max(np.abs(y - ref)) <= tol * max(np.abs(ref).max(), 1e-3), cyc
+        its[cyc] = out["iters"].cpu().numpy().mean()
+    assert its["w1"] <= its["v"]
+    if w["m"] == 256:
+        assert its["w1"] < its["v"] and its["auto"] == its["w1"]
+
+
+def test_cycle_rejects_unknown_value(ctx, ces):
+    d = ces.level_desc(cov="matern", nu=1.0, lam=0.1, m=64)
+    d.mg_cycle = 7
+    with pytest.raises(ces.CesError):
+        ctx.plan(d)
