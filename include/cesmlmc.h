@@ -92,8 +92,8 @@ enum { CES_QOI_INTEGRAL = 0, CES_QOI_POINT = 1, CES_QOI_L2 = 2, CES_QOI_OUTFLUX 
  * exactly; plan creation fails with CES_ERR_ARG when n_f < 2 n_c (the
  * coarse mesh padded relatively more than the fine one). */
 enum { CES_COUPLE_RESTRICT = 0, CES_COUPLE_EMBED = 1 };
-/* Multigrid cycle of the CG preconditioner (the solver of Algorithm 1 step
- * 4(g) is this build's; the paper uses GMRES with ILU).  V: V(2,2) cycle.
+/* Multigrid cycle of the CG preconditioner (the library's own solver for
+ * Algorithm 1 step 4(g); the paper uses GMRES with ILU).  V: V(2,2) cycle.
  * W1: level 1 visited twice per cycle (two coarse corrections, the same
  * symmetric operator), fewer CG iterations for a few more launches per
  * iteration: faster where a call carries many samples, slower for one
