@@ -295,7 +295,10 @@ void ces_mlmc_opts_default(ces_mlmc_opts* o);
  * exceeds (1 - theta) eps^2 the next level is added (up to nlevels), else
  * the run has converged.  alpha, beta, gamma are least-squares slopes of
  * log2 |mean_l|, log2 V_l, log2 C_l against l over levels 1..L.
- * Synchronous; hip_stream orders the sampling. */
+ * Levels must be independent: every level samples indices from 0 under
+ * the one seed, so the level tags (desc.stream) of level l (levels[l] and
+ * finest[l], which may share a tag) must differ from every other level's
+ * (CES_ERR_ARG otherwise).  Synchronous; hip_stream orders the sampling. */
 int ces_mlmc_run(ces_context ctx, const ces_plan* levels, const ces_plan* finest, int32_t nlevels,
                  const ces_mlmc_opts* opts, void* hip_stream, ces_mlmc_result* out);
 
@@ -421,7 +424,8 @@ void ces_mlqmc_opts_default(ces_mlqmc_opts* o);
  * addition of levels follow ces_mlmc_run (Richardson, alpha fitted over
  * levels 1..L when L >= 2, else 1).  out: n[l] = N_l R, mean[l] the level
  * estimate, var[l] the variance of the shift averages (R - 1 denominator),
- * variance = sum var[l] / R.  Synchronous. */
+ * variance = sum var[l] / R.  Level tags as for ces_mlmc_run.
+ * Synchronous. */
 int ces_mlqmc_run(ces_context ctx, const ces_plan* levels, const ces_plan* finest, int32_t nlevels,
                   const ces_mlqmc_opts* opts, void* hip_stream, ces_mlmc_result* out);
 

@@ -99,7 +99,7 @@ hipError_t DevicePool::alloc(size_t bytes, void** p) {
     {
         std::lock_guard<std::mutex> g(mu_);
         auto it = free_.lower_bound(b);
-        if (it != free_.end() && it->first <= 2 * b) {
+        if (it != free_.end() && it->first <= b + b / kReuseSlack) {
             *p = it->second;
             cached_ -= it->first;
             in_use_ += it->first;
@@ -251,6 +251,15 @@ int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st) {
     p->ws_bytes = p->work.bytes + p->kf.bytes + p->kc.bytes + p->sf->bytes() + (p->sc ? p->sc->bytes() : 0);
     p->ctx->used += p->ws_bytes;
     return CES_OK;
+}
+
+void drop_workspace(ces_plan p) {
+    p->sf.reset();
+    p->sc.reset();
+    for (DevBuf* b : {&p->work, &p->kf, &p->kc, &p->qf, &p->qc, &p->itf, &p->itc, &p->zf, &p->zc}) b->reset();
+    p->ctx->used -= std::min(p->ctx->used.load(), p->ws_bytes);
+    p->ws_bytes = 0;
+    p->chunk_slots = p->chunk_units = 0;
 }
 
 namespace {

@@ -50,6 +50,26 @@ double unknowns(const ces_level_desc& d, int m) {
 
 }  // namespace
 
+int ces::check_level_tags(const ces_plan* levels, const ces_plan* finest, int nlevels) {
+    auto tags = [&](int l, uint32_t* t) {
+        t[0] = levels[l]->d.stream;
+        t[1] = finest ? finest[l]->d.stream : t[0];
+    };
+    for (int l = 0; l < nlevels; ++l)
+        for (int k = l + 1; k < nlevels; ++k) {
+            uint32_t a[2], b[2];
+            tags(l, a);
+            tags(k, b);
+            for (uint32_t x : a)
+                for (uint32_t y : b)
+                    if (x == y)
+                        return fail(CES_ERR_ARG, "levels " + std::to_string(l) + " and " + std::to_string(k) +
+                                                     " share the level tag (stream) " + std::to_string(x) +
+                                                     ": their normals would coincide");
+        }
+    return CES_OK;
+}
+
 extern "C" {
 
 void ces_mlmc_opts_default(ces_mlmc_opts* o) {
@@ -93,6 +113,7 @@ int ces_mlmc_run(ces_context ctx, const ces_plan* levels, const ces_plan* finest
         if (l > 0 && p->d.m_fine != 2 * levels[l - 1]->d.m_fine)
             return fail(CES_ERR_ARG, "level l must halve the mesh of level l-1");
     }
+    if (int rc = check_level_tags(levels, finest, nlevels); rc != CES_OK) return rc;
     CES_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     std::memset(out, 0, sizeof(*out));

@@ -50,10 +50,18 @@ struct DevBuf {
 };
 
 // Caching device allocator: released blocks are kept (keyed by size) and
-// handed out again for requests they fit within a factor of two; nothing
+// handed out again for requests they fit within 25% (kReuseSlack); nothing
 // is returned to HIP until trim() or destruction.  Thread-safe.
 class DevicePool final : public DeviceAllocator {
 public:
+    // a cached block of b' bytes serves a request of b (rounded up to 256)
+    // when b' <= b (1 + 1/kReuseSlack)
+    static constexpr size_t kReuseSlack = 4;
+    // bytes the pool may count against its user for a request of `bytes`
+    static size_t charged(size_t bytes) {
+        const size_t b = (bytes + 255) / 256 * 256;
+        return b + b / kReuseSlack;
+    }
     DevicePool() = default;
     DevicePool(const DevicePool&) = delete;
     DevicePool& operator=(const DevicePool&) = delete;
@@ -144,6 +152,14 @@ namespace ces {
 // Device bytes per in-flight sample of a plan's workspace.
 size_t slot_bytes(const ces_plan p);
 
+// The levels of one estimator must draw independent normals (the variance
+// of eq. (mlmc-estimator) is the sum of the level variances only for
+// independent levels).  Sample indices restart at 0 on every level and all
+// levels share the seed, so the level tag (fourth Philox counter word) is
+// what keeps them apart: CES_ERR_ARG unless the tags of level l (levels[l]
+// and finest[l], which may share one) differ from those of every other level.
+int check_level_tags(const ces_plan* levels, const ces_plan* finest, int nlevels);
+
 // Plan set-up (Algorithm 1 steps 1-3 and the masks of Algorithm 2) with
 // device buffers from `alloc`, device work on stream st (synchronised).
 // keep_eigenvalues = false drops the n*n eigenvalue array once the
@@ -151,12 +167,21 @@ size_t slot_bytes(const ces_plan p);
 int plan_create(ces_context ctx, const ces_level_desc* desc, DeviceAllocator* alloc, hipStream_t st,
                 ces_plan* out, bool keep_eigenvalues = true);
 int validate_desc(const ces_level_desc* d);
+// Upper bound on the device bytes plan_create(d) holds at once (the
+// eigenvalue set-up at the largest embedding GROW may try, the masks and
+// amplitudes, the coarse plan of an EMBED pair), allowing for the caching
+// pool's reuse of slightly larger blocks.
+size_t plan_setup_bytes(const ces_level_desc* d);
 
 // Allocates the plan's sample workspace on first use (zeroed on stream st).
 // max_slots > 0 caps the samples per chunk (the serving loop sizes
 // workspaces per request); 0 sizes it for throughput (about 4.5 GiB, at
 // most 8192 samples, 65536 for m <= 32).
 int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st);
+// Gives the sample workspace back to the plan's allocator (the next
+// sampling call makes a new one).  The caller guarantees that no enqueued
+// work still uses it.
+void drop_workspace(ces_plan p);
 // Device bytes ensure_workspace(p, max_slots) would allocate.
 size_t workspace_bytes(const ces_plan p, long long max_slots);
 

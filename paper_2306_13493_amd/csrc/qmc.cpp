@@ -292,6 +292,7 @@ int ces_mlqmc_run(ces_context ctx, const ces_plan* levels, const ces_plan* fines
         if (l > 0 && levels[l]->d.m_fine != 2 * levels[l - 1]->d.m_fine)
             return fail(CES_ERR_ARG, "level l must halve the mesh of level l-1");
     }
+    if (int rc = check_level_tags(levels, finest, nlevels); rc != CES_OK) return rc;
     CES_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     std::memset(out, 0, sizeof(*out));

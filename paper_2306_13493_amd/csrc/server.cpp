@@ -68,7 +68,8 @@ private:
 struct PlanRef {
     std::string key;
     ces_plan p = nullptr;
-    int refs = 0;   // requests holding the plan
+    int refs = 0;      // requests holding the plan
+    int running = 0;   // of those, admitted and not complete
 };
 
 struct Request {
@@ -119,11 +120,29 @@ struct ces_server_s {
     size_t mem_peak = 0;
     int loop_error = CES_OK;
     std::string loop_msg;
+    // bytes promised to allocations in progress outside mu (a plan set-up
+    // on the planner, a request's workspace and outputs on the loop)
+    size_t reserved = 0;
 
     std::thread planner, loop;
 
     static constexpr size_t kMaxReady = 8;        // planned ahead of admission
     static constexpr size_t kMaxIdlePlans = 16;   // kept for repeated descriptors
+
+    // the pool can take `need` more bytes within the budget (caller holds mu)
+    bool fits(size_t need) const { return pool.in_use() + reserved + need <= budget; }
+
+    // Make room for `need` bytes (caller holds mu): destroy idle plans, then
+    // drop the workspaces of plans whose requests are all still queued
+    // (they make new ones when admitted), `keep` excepted.
+    void evict_for(size_t need, const PlanRef* keep = nullptr) {
+        while (!fits(need) && !idle_plans.empty() && evict_one()) {
+        }
+        for (auto it = plans.begin(); it != plans.end() && !fits(need); ++it) {
+            PlanRef* ref = it->second.get();
+            if (ref != keep && ref->running == 0 && ref->p->sf) drop_workspace(ref->p);
+        }
+    }
 
     void finish_request(Request* r, int state) {
         // caller holds mu
@@ -136,6 +155,7 @@ struct ces_server_s {
             ++n_failed;
         }
         cv_done.notify_all();
+        cv_plan.notify_all();   // memory may have come free for a set-up
     }
 
     void release_plan(PlanRef* ref) {
@@ -157,31 +177,59 @@ struct ces_server_s {
         return true;
     }
 
+    // Once the loop has stopped on an error nothing will run again: every
+    // request not yet finished fails with that error (caller holds mu).
+    void fail_unfinished() {
+        for (Request* r : ready) {
+            release_plan(r->plan);
+            finish_request(r, loop_error);
+        }
+        ready.clear();
+        for (Request* r : submitted) finish_request(r, loop_error);
+        submitted.clear();
+    }
+
     void planner_main() {
         (void)hipSetDevice(ctx->device);
         hipStream_t st = nullptr;
         const bool have_stream = planner_streams.stream(0, &st) == hipSuccess;
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
-            cv_plan.wait(lk, [&] { return stop || (!submitted.empty() && ready.size() < kMaxReady); });
+            cv_plan.wait(lk, [&] {
+                return stop || (!submitted.empty() && (ready.size() < kMaxReady || loop_error != CES_OK));
+            });
+            if (loop_error != CES_OK) fail_unfinished();
             if (submitted.empty()) {
                 if (stop) return;
                 continue;
             }
             Request* r = submitted.front();
-            submitted.pop_front();
             const std::string key = desc_key(r->d);
             auto it = plans.find(key);
             if (it != plans.end()) {
+                submitted.pop_front();
                 PlanRef* ref = it->second.get();
                 if (ref->refs == 0) idle_plans.remove(ref);
                 ++ref->refs;
                 r->plan = ref;
             } else {
+                // the set-up's buffers must fit in the budget next to what
+                // runs; with nothing admitted, waiting or being set up it
+                // goes ahead regardless, so that the stream always moves
+                const size_t sb = plan_setup_bytes(&r->d);
+                evict_for(sb);
+                if (!fits(sb) && !(n_admitted_now == 0 && ready.empty() && reserved == 0)) {
+                    cv_plan.wait_for(lk, std::chrono::milliseconds(20));
+                    continue;
+                }
+                submitted.pop_front();
+                reserved += sb;
                 lk.unlock();
                 ces_plan p = nullptr;
                 const int rc = have_stream ? plan_create(ctx, &r->d, &pool, st, &p, false) : CES_ERR_DEVICE;
                 lk.lock();
+                reserved -= sb;
+                cv_loop.notify_all();
                 if (rc != CES_OK) {
                     finish_request(r, rc);
                     continue;
@@ -193,6 +241,12 @@ struct ces_server_s {
                 r->plan = ref.get();
                 plans[key] = std::move(ref);
             }
+            if (loop_error != CES_OK) {
+                // the loop stopped while this request was being planned
+                release_plan(r->plan);
+                finish_request(r, loop_error);
+                continue;
+            }
             ready.push_back(r);
             cv_loop.notify_all();
         }
@@ -200,8 +254,10 @@ struct ces_server_s {
 
     // device bytes a ready request needs beyond what its plan holds
     size_t need_bytes(const Request* r) const {
-        size_t b = (size_t)r->count * 12 + 512;
-        if (!r->plan->p->sf) b += workspace_bytes(r->plan->p, r->count);
+        size_t b = DevicePool::charged((size_t)r->count * 8) + DevicePool::charged((size_t)r->count * 4);
+        // the workspace's buffers (about twenty), each possibly a slightly
+        // larger cached block
+        if (!r->plan->p->sf) b += DevicePool::charged(workspace_bytes(r->plan->p, r->count)) + 32 * 256;
         return b;
     }
 
@@ -262,18 +318,21 @@ struct ces_server_s {
                 while (!ready.empty() && n_admitted_now < max_inflight) {
                     Request* r = ready.front();
                     const size_t need = need_bytes(r);
-                    while (pool.in_use() + need > budget && !idle_plans.empty() && evict_one()) {
-                    }
-                    if (pool.in_use() + need > budget && n_admitted_now > 0) break;
+                    evict_for(need, r->plan);
+                    if (!fits(need) && (n_admitted_now > 0 || reserved > 0)) break;
                     ready.pop_front();
                     cv_plan.notify_all();
                     hipEvent_t ev = nullptr;
+                    reserved += need;
+                    ++r->plan->running;   // its workspace is in use from here on
                     lk.unlock();
                     int rc = get_event(&ev) == hipSuccess ? admit(S, r, ev) : CES_ERR_DEVICE;
                     lk.lock();
+                    reserved -= need;
                     if (rc != CES_OK) {
                         free_request_buffers(r);
                         if (ev) free_events.push_back(ev);
+                        --r->plan->running;
                         release_plan(r->plan);
                         finish_request(r, rc);
                         continue;
@@ -290,13 +349,22 @@ struct ces_server_s {
             if (rc == CES_OK) rc = S.retire(&released);
             released.clear();
             if (rc != CES_OK) {
+                const std::string msg = ces_last_error();
+                // end the scheduler's use of the plans before their
+                // references go, so that none is destroyed under a lane
+                (void)S.join();
                 std::lock_guard<std::mutex> g(mu);
                 loop_error = rc;
-                loop_msg = ces_last_error();
-                for (Request* r : running) finish_request(r, rc);
+                loop_msg = msg;
+                for (Request* r : running) {
+                    --r->plan->running;
+                    release_plan(r->plan);
+                    --n_admitted_now;
+                    finish_request(r, rc);
+                }
                 running.clear();
-                for (Request* r : ready) finish_request(r, rc);
-                ready.clear();
+                fail_unfinished();
+                cv_plan.notify_all();
                 return;
             }
             did = did || prog;
@@ -320,6 +388,7 @@ struct ces_server_s {
                 free_request_buffers(r);
                 free_events.push_back(r->done);
                 r->done = nullptr;
+                --r->plan->running;
                 release_plan(r->plan);
                 --n_admitted_now;
                 finish_request(r, ok ? 2 : CES_ERR_DEVICE);

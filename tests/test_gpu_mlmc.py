@@ -94,3 +94,20 @@ def test_coarsest_mesh_rule(ces):
     for w in (dict(cov="matern", nu=0.5, lam=0.03), dict(cov="sepexp", lam=0.1),
               dict(cov="matern", nu=1.5, lam=0.1)):
         assert ces.coarsest_mesh(ces.level_desc(**w)) == omlmc.coarsest_mesh(w["cov"], w.get("nu", 0.5), w["lam"])
+
+
+def test_estimator_refuses_levels_sharing_a_tag(ctx, ces):
+    # every level restarts its sample indices at 0 under one seed, so two
+    # levels with one tag would draw the same normals (correlated levels)
+    descs = [level_desc(l, 8, False) for l in range(3)]
+    plans = [ctx.plan(ces.level_desc(**dict(d, stream=0))) for d in descs]
+    with pytest.raises(ces.CesError, match="level tag"):
+        ces.mlmc_run(ctx, plans, eps=1e-2)
+    # the finest form of a level may share its level's tag, not another's
+    plans = [ctx.plan(ces.level_desc(**d)) for d in descs]
+    fdescs = [level_desc(l, 8, True, finest=True) for l in range(3)]
+    finest = [ctx.plan(ces.level_desc(**d)) for d in fdescs]
+    ces.mlmc_run(ctx, plans, finest=finest, eps=5e-2, max_rounds=2)
+    finest[2] = ctx.plan(ces.level_desc(**dict(fdescs[2], stream=1)))
+    with pytest.raises(ces.CesError, match="level tag"):
+        ces.mlmc_run(ctx, plans, finest=finest, eps=5e-2, max_rounds=2)

@@ -243,10 +243,20 @@ def test_estimator_matches_oracle(ctx, ces, smoothed):
 
 def test_estimator_rejects_plans_without_lattice(ctx, ces):
     p0 = ctx.plan(ces.level_desc(cov="matern", nu=1.5, lam=0.2, m=8, field="hartley"))
-    p1 = ctx.plan(ces.level_desc(cov="matern", nu=1.5, lam=0.2, m=16, level="pair", field="hartley"))
+    p1 = ctx.plan(ces.level_desc(cov="matern", nu=1.5, lam=0.2, m=16, level="pair", field="hartley", stream=1))
     p0.set_lattice(s=8, log2_points=4, shifts=4)
     with pytest.raises(ces.CesError):
         ces.mlqmc_run(ctx, [p0, p1], eps=1e-2)
     p1.set_lattice(s=8, log2_points=4, shifts=8)
     with pytest.raises(ces.CesError):
+        ces.mlqmc_run(ctx, [p0, p1], eps=1e-2)
+
+
+def test_estimator_refuses_levels_sharing_a_tag(ctx, ces):
+    w = dict(cov="matern", nu=1.5, lam=0.2, field="hartley")
+    p0 = ctx.plan(ces.level_desc(m=8, **w))
+    p1 = ctx.plan(ces.level_desc(m=16, level="pair", **w))
+    for p in (p0, p1):
+        p.set_lattice(s=8, log2_points=4, shifts=4)
+    with pytest.raises(ces.CesError, match="level tag"):
         ces.mlqmc_run(ctx, [p0, p1], eps=1e-2)

@@ -124,7 +124,10 @@ def test_failed_request_does_not_disturb_others(ctx, ces):
 
 def test_c4_trace_prefix_alone_vs_mix(ctx, ces):
     # first requests of the serving workload, submitted back to back
-    trace = [r for r in W.c4_trace(duration_s=0.2) if r["w"]["m"] <= 256][:10]
+    full = W.c4_trace(duration_s=2.0)
+    trace = [r for r in full if r["w"]["m"] <= 256][:10]
+    # and the first large levels (grown embeddings, radix-3 DFT sizes)
+    trace += [r for r in full if r["w"]["m"] >= 512][:2]
     srv = ces.Server(ctx, max_inflight=16)
     try:
         ids = [srv.submit(r["w"], r["seed"], r["first"], r["count"]) for r in trace]
@@ -132,5 +135,39 @@ def test_c4_trace_prefix_alone_vs_mix(ctx, ces):
         for rid, r in zip(ids, trace):
             ya, _ = alone(ctx, ces, r["w"], r["seed"], r["first"], r["count"])
             assert np.array_equal(srv.result(rid)[0].view(np.uint64), ya.view(np.uint64))
+    finally:
+        srv.close()
+
+
+def test_requests_overlap_on_the_device(ctx, ces):
+    # continuous batching: short requests submitted while a long one runs
+    # are admitted next to it and complete before it does
+    import time
+    srv = ces.Server(ctx, max_inflight=8)
+    try:
+        big = dict(cov="matern", nu=1.0, lam=0.1, m=1024, level="pair")
+        small = [dict(cov="matern", nu=0.5, lam=0.05, m=16, stream=1 + i) for i in range(4)]
+        ra = srv.submit(big, 1, 0, 256)
+        t0 = time.time()
+        while srv.poll(ra)[0] == 0:
+            assert time.time() - t0 < 60
+        rs = [srv.submit(w, 2, 0, 8) for w in small]
+        max_admitted, overtaken = 0, 0
+        while True:
+            st = srv.stats()
+            max_admitted = max(max_admitted, st["admitted"])
+            states = [srv.poll(r)[0] for r in rs]
+            big_state = srv.poll(ra)[0]
+            overtaken = max(overtaken, sum(s == 2 for s in states) if big_state == 1 else 0)
+            if big_state == 2 and all(s == 2 for s in states):
+                break
+            assert big_state >= 0 and min(states) >= 0
+            assert time.time() - t0 < 120
+        srv.drain()
+        assert max_admitted >= 2
+        assert overtaken >= 1
+        for r, w in zip(rs, small):
+            ya, _ = alone(ctx, ces, w, 2, 0, 8)
+            assert np.array_equal(srv.result(r)[0].view(np.uint64), ya.view(np.uint64))
     finally:
         srv.close()
