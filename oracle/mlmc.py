@@ -115,7 +115,9 @@ def run(sample, cost, nlevels, eps, l_start=2, n_pilot=100, theta=0.5, alpha=0.0
         if L >= 1 and bias * bias <= (1 - theta) * eps * eps:
             converged = True
             break
-        if L + 1 >= nlevels:
+        # a level is added only when a round is left to sample it, so that
+        # every level of the result has samples
+        if L + 1 >= nlevels or rounds >= max_rounds:
             break
         if finest_differs:
             stats[L] = RunningStats()

@@ -213,7 +213,9 @@ int ces_mlmc_run(ces_context ctx, const ces_plan* levels, const ces_plan* finest
             converged = true;
             break;
         }
-        if (L + 1 >= nlevels) break;
+        // a level is added only when a round is left to sample it, so that
+        // every level of the result has samples
+        if (L + 1 >= nlevels || rounds >= o->max_rounds) break;
         // add a level; the old finest level changes plan if finest plans differ
         if (finest && finest[L] != levels[L]) {
             W[L] = Welford();

@@ -77,3 +77,20 @@ def test_finest_level_form_is_replaced_when_a_level_is_added():
         target = 1.0 if l == 0 else 4.0 ** -l
         assert abs(r["mean"][l] - target) < 0.05
     assert abs(r["mean"][L] - (4.0 ** -L + 0.5)) < 0.05
+
+
+def test_round_cap_adds_no_unsampled_level():
+    # levels with E[Y_l] = 4^-l and no variance: after the pilot round the
+    # bias |E[Y_1]| / 3 = 1/12 exceeds eps, so a level would be added; with
+    # no round left the run stops with the sampled levels only
+    def sample(l, finest, first, count):
+        return [4.0 ** -l] * count
+
+    cost = [4.0 ** l for l in range(6)]
+    r = mlmc.run(sample, cost, 6, 1e-3, l_start=1, n_pilot=4, alpha=2.0, max_rounds=1)
+    assert r["rounds"] == 1 and r["levels"] == 2 and not r["converged"]
+    assert r["n"] == [4, 4] and all(n > 0 for n in r["n"])
+    # one more round samples the added level (pilot only: no variance)
+    r = mlmc.run(sample, cost, 6, 1e-3, l_start=1, n_pilot=4, alpha=2.0, max_rounds=2)
+    assert r["levels"] == 3 and r["n"] == [4, 4, 4]
+    assert r["estimate"] == 1.0 + 0.25 + 0.0625

@@ -164,3 +164,19 @@ def test_run_doubling_rule_hand_computed():
     assert abs(r["variance"] - (0.01 + 0.0016)) <= 1e-15
     r2 = qmc.run(sample, cost, 2, eps=0.1, shifts_=2, l_start=1, n_pilot=1, max_rounds=2)
     assert r2["points"] == [4, 1] and r2["n"] == [8, 2]
+
+
+def test_run_round_cap_adds_no_unsampled_level():
+    # shift means equal c_l on every shift (no variance); the bias after the
+    # pilot round exceeds eps, and with no round left no level is added
+    c = [1.0, 0.25, 0.0625, 0.015625]
+
+    def sample(l, finest, first, count):
+        return [c[l]] * count
+
+    r = qmc.run(sample, [1.0, 2.0, 4.0, 8.0], 4, eps=1e-3, shifts_=4, l_start=1, n_pilot=2, alpha=2.0,
+                max_rounds=1)
+    assert r["rounds"] == 1 and r["levels"] == 2 and r["converged"] == 0 and r["points"] == [2, 2]
+    r = qmc.run(sample, [1.0, 2.0, 4.0, 8.0], 4, eps=1e-3, shifts_=4, l_start=1, n_pilot=2, alpha=2.0,
+                max_rounds=2)
+    assert r["levels"] == 3 and r["points"] == [2, 2, 2]
