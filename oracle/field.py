@@ -20,8 +20,11 @@ embedding's xi takes the fine xi at the nearest signed frequencies
 (embedded_xi); the selection is injective when n_f >= 2 n_c, so its law is
 that of an independent draw.
 
-Pins (tests/test_oracle_field.py): the linear map xi -> Z satisfies
-A A^T = R exactly (covariance identity of Section 2.1); tau = 0 gives the
+Pins (tests/test_oracle_field.py, tests/test_oracle_law.py): the linear
+map xi -> Z satisfies A A^T = R exactly (covariance identity of Section
+2.1); the emitted samples (Philox normals included) have the law of dense
+Cholesky samples of R (eq. (sample-from-Z)) by two-sample tests on tiny
+grids, and the two fields of one complex xi are independent; tau = 0 gives the
 unsmoothed field bitwise; tau = s gives zero; empirical covariance of many
 samples against C within Monte Carlo error; the smoothing error against
 the explicit constant of Theorem 1's proof.

@@ -40,8 +40,10 @@ definitions:
 
 Parity status: lattice_points, cbc, error2 and run are pinned in
 tests/test_oracle_qmc.py (closed forms, the dual-lattice sum, exact
-integration of trigonometric polynomials, brute-force argmin, synthetic
-levels).  Phi^{-1} is scipy.special.ndtri (a library primitive).
+integration of trigonometric polynomials, brute-force argmin, the exact
+rational argmin up to the truncation's resolution 2^-40 on constructed
+near-ties, synthetic levels).  Phi^{-1} is scipy.special.ndtri (a library
+primitive).
 """
 
 import numpy as np

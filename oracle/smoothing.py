@@ -23,7 +23,11 @@ differences and the two sample means, over samples first .. first+count-1.
 
 Pins (tests/test_oracle_smoothing.py): the separable exponential closed
 form satisfies the balance C_alpha h^alpha = C_s tau / (s - tau + 1) it
-comes from; the Matern root satisfies its equation and lies in [0, s];
+comes from; the Matern root balances C_alpha h^alpha against C_s times the
+bound of Corollary (error-matern-cov) evaluated in its general
+d-dimensional form (s = 2^d prod (m_i + J_i), exponent -(1 + 2 nu/d)/2),
+and the embedding's sorted eigenvalues decay at the rate j^-(1 + nu) that
+exponent rests on; the root lies in [0, s];
 tau decreases as C_s / C_alpha grows and tends to s as it vanishes; tau = 0
 gives identically zero differences; tau = s gives Q~_h equal to the
 constant-coefficient QoI (k = exp(0) = 1) for every sample; the statistics

@@ -180,3 +180,46 @@ def test_run_round_cap_adds_no_unsampled_level():
     r = qmc.run(sample, [1.0, 2.0, 4.0, 8.0], 4, eps=1e-3, shifts_=4, l_start=1, n_pilot=2, alpha=2.0,
                 max_rounds=2)
     assert r["levels"] == 3 and r["points"] == [2, 2, 2]
+
+
+def exact_error2(z, p, gamma):
+    """e^2 of the rank-1 rule in exact rational arithmetic (the definition,
+    B2(x) = x^2 - x + 1/6 at x = {k z / N}, with the float weights taken
+    exactly)."""
+    from fractions import Fraction
+    N = 1 << p
+    g = [Fraction(float(v)) for v in gamma]
+    tot = Fraction(0)
+    for k in range(N):
+        prod = Fraction(1)
+        for zj, gj in zip(z, g):
+            x = Fraction((k * int(zj)) % N, N)
+            prod *= 1 + gj * (x * x - x + Fraction(1, 6))
+        tot += prod
+    return tot / N - 1
+
+
+@pytest.mark.parametrize("p,gamma", [(4, [1.0, 1e-13, 0.3]), (5, [0.8, 3e-12, 1e-12]), (4, [0.5, 0.0, 0.25]),
+                                     (6, [1.0, 0.6, 2e-12]), (5, [1.0, 0.9, 0.8])])
+def test_cbc_choice_is_the_exact_argmin_up_to_its_truncation(p, gamma):
+    # the CBC criterion truncates every term to a multiple of 2^-40 (so that
+    # any summation order gives the same choice); each term moves by less
+    # than 2^-40, so e^2 of the chosen candidate is within 2^-40 (plus the
+    # float rounding of the products, far smaller) of the exact minimum,
+    # and the choice is the exact argmin wherever that is ahead by more.
+    # Weights near 1e-12 build near-ties below that resolution.
+    from fractions import Fraction
+    N = 1 << p
+    tol = Fraction(2) ** -40 + Fraction(1, 10 ** 14)
+    z = qmc.cbc(p, gamma)
+    cand = list(range(1, N // 2 + 1, 2))
+    for j in range(len(gamma)):
+        e = {c: exact_error2(z[:j] + [c], p, gamma[: j + 1]) for c in cand}
+        best = min(e.values())
+        assert e[z[j]] - best <= tol, (j, float(e[z[j]] - best))
+        winners = [c for c in cand if e[c] == best]
+        runner_up = min((v for c, v in e.items() if v != best), default=None)
+        if len(winners) == 1 and runner_up is not None and runner_up - best > tol:
+            assert z[j] == winners[0]
+        if gamma[j] == 0.0:
+            assert z[j] == 1      # exact tie over every candidate: the smallest

@@ -87,3 +87,49 @@ def test_library_tau_rule_rejects_bad_arguments():
                  ("matern", 0, 1.0, 1.0)]:
         with pytest.raises(ces.CesError):
             ces.tau_rule(*args)
+
+
+def matern_smoothing_bound(m, J, nu, tau, d=2):
+    """The constant-free bound of Corollary (error-matern-cov) for p = 1 in
+    d dimensions with m_i = m and J_i = J:
+    s^(-1/2) (prod m_i)^(1/2) (s - tau + 1)^(-(1 + 2 nu / d) / 2) tau,
+    s = 2^d prod (m_i + J_i)."""
+    s = 2.0 ** d * float(m + J) ** d
+    return s ** -0.5 * float(m) ** (d / 2.0) * (s - tau + 1.0) ** (-0.5 * (1.0 + 2.0 * nu / d)) * tau
+
+
+@pytest.mark.parametrize("m,J,nu,alpha,c", [(32, 0, 1.5, 1.0, 1.0), (64, 32, 1.5, 1.0, 0.3), (128, 64, 1.0, 2.0, 5.0),
+                                            (256, 0, 0.5, 1.0, 50.0), (64, 64, 2.5, 1.5, 0.02)])
+def test_matern_root_balances_the_corollary_bound(m, J, nu, alpha, c):
+    # the rule of Section 3.5: the discretisation error C_alpha h^alpha equals
+    # the smoothing error C_s x (bound of Corollary (error-matern-cov)); here
+    # C_alpha = 1, C_s = c.  Evaluated from the corollary's general form, so
+    # a wrong exponent or a dropped (1/h + J) factor in the oracle's equation
+    # fails.
+    _, t = osm.tau_rule(osm.MATERN, m, alpha, c, nu=nu, J=J)
+    s = 4.0 * (m + J) ** 2
+    assert 0.0 < t <= s
+    if t < s:
+        assert (1.0 / m) ** alpha == pytest.approx(c * matern_smoothing_bound(m, J, nu, t), rel=1e-9)
+    else:
+        assert (1.0 / m) ** alpha >= c * matern_smoothing_bound(m, J, nu, s) * (1 - 1e-12)
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.0, 1.5, 2.5])
+def test_embedding_eigenvalues_decay_at_the_rate_the_rule_assumes(nu):
+    # the corollary's exponent comes from the Matern eigenvalue decay
+    # Lambda^ord_j ~ j^-(1 + 2 nu / d) (d = 2: j^-(1 + nu)); the oracle's
+    # sorted embedding eigenvalues decay at that rate (log-log slope over
+    # s/64 <= j <= s/4, within the pre-asymptotic band of 15%), and not at
+    # the rates a dropped 1/2 or 2 / d would give
+    from oracle import embedding as em
+    from oracle.covariance import MATERN
+    st = em.setup(dict(cov=MATERN, nu=nu, lam=0.05, sigma2=1.0, m=128))
+    lam = np.sort(np.maximum(st["lam"].ravel(), 0.0))[::-1]
+    j = np.arange(1, lam.size + 1)
+    sel = (j >= lam.size // 64) & (j <= lam.size // 4)
+    slope = np.polyfit(np.log(j[sel]), np.log(lam[sel]), 1)[0]
+    want = -(1.0 + nu)
+    assert abs(slope - want) <= 0.15 * abs(want), slope
+    others = [-(1.0 + nu) / 2.0, -(1.0 + 2.0 * nu)]
+    assert all(abs(slope - want) < abs(slope - o) for o in others), slope
