@@ -79,6 +79,131 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def dominant_roofline(prof, log, traffic_known=True):
+    """Roofline of the kernel with the largest total time in a launch
+    profile (HIP events around each launch, algorithmic bytes per launch)
+    and the per-kernel table."""
+    name, (launches, ms, nbytes) = max(prof.items(), key=lambda kv: kv[1][1])
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    total_ms = sum(v[1] for v in prof.values())
+    symbol = KERNEL_SYMBOL.get(name, name)
+    traffic = measured_traffic(symbol) if traffic_known else None
+    roofline = {"bound": "hbm", "kernel": name, "symbol": symbol,
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic) if traffic is not None else None,
+                "avg_launch_us": round(ms * 1e3 / launches, 2), "launches": launches,
+                "algorithmic_bytes_per_launch": round(nbytes / launches),
+                "share_of_kernel_time": round(ms / total_ms, 4)}
+    all_bytes = sum(v[2] for v in prof.values())
+    kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
+                   "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+               for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    log("dominant kernel %s: %.1f GB/s (%.1f%% of 8 TB/s); whole path %.1f GB/s"
+        % (name, achieved, 100 * achieved / HBM_PEAK_GBS, all_bytes / (total_ms * 1e-3) / 1e9))
+    return roofline, kernels
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def c5_record(ces, ctx, W, log, steps=2):
+    """The large flow-cell level (Matern nu=3/2, sigma2=2, lambda=0.01,
+    2049^2 vertices, embedding 4096^2, outflow QoI, mixed precision) at its
+    1024 samples per call: samples/s over `steps` timed calls (after one
+    warm-up call and one call with the launch profiler on, which gives the
+    live roofline of its dominant kernel), CG iterations, parity of sample
+    0 (its field against the oracle's, and the device solve of its
+    coefficient checked by the residual and flux balance of the flow cell
+    under the oracle's element-by-element operator), and the oracle's time
+    for the field of one sample (its SuperLU solve at 4.2 million unknowns
+    takes minutes per sample and is not run here)."""
+    import numpy as np
+    import torch
+    from oracle import fem as ofem, qoi as oqoi, sampler
+    from paper_2306_13493_amd.workloads import to_oracle
+    w = dict(W.C5)
+    count = 1024
+    t0 = time.perf_counter()
+    plan = ctx.plan(ces.level_desc(**w))
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    out = plan.sample(0, 0, count)
+    torch.cuda.synchronize()
+    log("C5: plan n=%d, warm-up call of %d samples done" % (plan.info.n, count))
+    ces.profile_enable(True)
+    torch.cuda.synchronize()
+    out = plan.sample(0, count, count, out=out)
+    torch.cuda.synchronize()
+    prof = ces.profile_read()
+    ces.profile_enable(False)
+    roofline, kernels = dominant_roofline(prof, log, traffic_known=False)
+    ts = []
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = plan.sample(0, (k + 2) * count, count, out=out)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    it = out["iters"].cpu().numpy()
+    ok = bool(np.all(out["status"].cpu().numpy() == 0))
+    value = count / float(np.median(ts))
+    log("C5: %d samples per call in %.3f s -> %.1f samples/s; CG iterations mean %.2f" % (count, np.median(ts),
+                                                                                       value, it.mean()))
+    # parity of sample 0
+    m = w["m"]
+    y0 = float(plan.sample(0, 0, 1)["y"].cpu().numpy()[0])
+    zf, _ = plan.field(0, 0)
+    z = zf.cpu().numpy()
+    t1 = time.perf_counter()
+    ref = sampler.Plan(to_oracle(w))
+    t_setup = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    zr, _ = ref.fields(0, 0)
+    t_field = time.perf_counter() - t1
+    field_err = float(np.max(np.abs(z - zr)) / np.max(np.abs(zr)))
+    k = np.exp(z).astype(np.float32).astype(np.float64)   # the coefficient the mixed solver sees
+    u, _ = plan.solve(torch.from_numpy(k).reshape(1, m + 1, m + 1).to("cuda"))
+    uu = u.cpu().numpy().reshape(-1)
+    A, b = ofem.assemble(k, m, 1.0)
+    res = b - A @ uu
+    i = np.arange((m + 1) ** 2) % (m + 1)
+    free = (i > 0) & (i < m)
+    r0 = b - A @ (i == 0).astype(np.float64)
+    rel_res = float(np.linalg.norm(res[free]) / np.linalg.norm(r0[free]))
+    balance = float(abs(res[i == 0].sum() + res[i == m].sum() - b.sum()))
+    q = oqoi.outflux(uu, m, A, b)
+    qoi_err = abs(y0 - q) / abs(q)
+    log("C5 parity: field %.2e of max|Z|; residual %.2e of r0; flux balance %.2e; outflow QoI %.2e"
+        % (field_err, rel_res, balance, qoi_err))
+    return {
+        "metric": "MLMC level samples/sec (field+solve), 2049^2 flow cell at 1 GPU", "value": round(value, 1),
+        "unit": "samples/s", "samples_per_call": count, "calls_timed": steps,
+        "ms_per_call": round(float(np.median(ts)) * 1e3, 1), "setup_ms": round(setup_ms, 1),
+        "cg_iterations_mean": round(float(it.mean()), 3), "all_converged": ok,
+        "config": {"workload": "Matern nu=3/2 sigma2=2 lambda=0.01, 2049x2049 vertices, embedding 4096x4096 "
+                               "(nonnegative at 2m), flow cell (u=1 at x1=0, u=0 at x1=1), f=1, outflow QoI, "
+                               "float field+multigrid, double CG to 1e-10, %d samples per call" % count},
+        "roofline": roofline, "kernels": kernels,
+        "parity_sample0": {"field_max_rel_diff": field_err, "field_bar": 1e-5,
+                           "residual_rel_r0": rel_res, "flux_balance_abs": balance,
+                           "outflow_qoi_rel_diff": qoi_err, "qoi_bar": 1e-6,
+                           "operator": "oracle element-by-element P1 assembly on the float coefficient"},
+        "cpu_oracle": {"kind": "oracle", "cores": 1, "cpu_model": cpu_model(),
+                       "sample": "the field of sample 0 (normals, FP64 DFT at 4096^2, restriction)",
+                       "setup_s": round(t_setup, 2), "field_s_per_sample": round(t_field, 2),
+                       "solve_s_per_sample": None,
+                       "note": "the oracle's SuperLU solve of one sample at 2049^2 took 678 s on one core of "
+                               "the build container; far beyond this run's time, so not timed here"},
+    }
+
+
 def _oracle_worker(args):
     desc, seed, idx = args
     os.environ["OMP_NUM_THREADS"] = "1"
@@ -420,27 +545,11 @@ def single_workload(args):
                 "c3_mlmc_batch": r}
         print(json.dumps(line), flush=True)
         return
-    # C5: 2049^2 flow cell
-    plan = ctx.plan(ces.level_desc(**W.C5))
-    count = 64
-    out = plan.sample(0, 0, count)
-    torch.cuda.synchronize()
-    ts = []
-    for k in range(max(3, args.steps)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        out = plan.sample(0, (k + 1) * count, count, out=out)
-        torch.cuda.synchronize()
-        ts.append(time.perf_counter() - t0)
-    it = out["iters"].cpu().numpy()
-    v = count / float(np.median(ts))
-    log("C5: %d samples in %.1f ms -> %.1f samples/s; CG iterations mean %.2f" % (count, 1e3 * np.median(ts), v,
-                                                                                it.mean()))
-    line = {"metric": "MLMC level samples/sec, 2049^2 flow cell at 1 GPU", "value": round(v, 1),
-            "unit": "samples/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
-            "config": {"workload": "C5: Matern nu=3/2 sigma2=2 lambda=0.01, 2049^2 vertices (embedding 4096^2), "
-                                   "flow cell, outflow QoI, %d samples per call, mixed precision" % count},
-            "cg_iterations_mean": float(it.mean())}
+    # C5: the 2049^2 flow cell at its 1024 samples per call
+    r = c5_record(ces, ctx, W, log, steps=max(2, args.steps))
+    line = {"metric": r.pop("metric"), "value": r.pop("value"), "unit": r.pop("unit"), "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic", "config": r.pop("config")}
+    line.update(r)
     print(json.dumps(line), flush=True)
 
 
@@ -453,7 +562,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=0)
-    ap.add_argument("--no-c3", action="store_true", help="skip the five-level batched estimator line")
+    ap.add_argument("--no-c3", action="store_true", help="skip the five-level batched estimator record")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 2049^2 flow-cell record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (scale for HBM counters)")
     ap.add_argument("--study-samples", type=int, default=512, help="smoothing: samples per mesh and form")
@@ -553,32 +663,17 @@ def main():
     value_np = args.steps * count / elapsed_np
     log("unprofiled: %d steps in %.3f s -> %.1f samples/s" % (args.steps, elapsed_np, value_np))
 
-    # dominant kernel: largest total time inside the timed region
-    name, (launches, ms, nbytes) = max(prof.items(), key=lambda kv: kv[1][1])
-    achieved = nbytes / (ms * 1e-3) / 1e9
-    total_ms = sum(v[1] for v in prof.values())
-    symbol = KERNEL_SYMBOL.get(name, name)
-    traffic = measured_traffic(symbol)
-    roofline = {"bound": "hbm", "kernel": name, "symbol": symbol,
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": round(traffic) if traffic is not None else None,
-                "avg_launch_us": round(ms * 1e3 / launches, 2), "launches": launches,
-                "algorithmic_bytes_per_launch": round(nbytes / launches),
-                "share_of_kernel_time": round(ms / total_ms, 4)}
-    all_bytes = sum(v[2] for v in prof.values())
-    solver_kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
-                          "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
-                      for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
-    log("dominant kernel %s: %.1f GB/s (%.1f%% of 8 TB/s); whole path %.1f GB/s"
-        % (name, achieved, 100 * achieved / HBM_PEAK_GBS, all_bytes / (total_ms * 1e-3) / 1e9))
+    roofline, solver_kernels = dominant_roofline(prof, log)
 
     # parity of the timed path and the plain FP64 GPU path against the oracle
     extra = {}
     cpu = None
     if not args.no_cpu_baseline:
-        nproc = max(1, min(os.cpu_count() or 1, 16))
-        ns = args.cpu_samples or max(8, nproc)
+        # one process per core of the CPU share a one-GPU machine grants (16),
+        # however many cores the host shows
+        visible = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        nproc = max(1, min(visible, 16))
+        ns = args.cpu_samples or 4 * nproc
         log("cpu baseline: oracle on %d samples with %d processes ..." % (ns, nproc))
         y_ref, dt = cpu_baseline(w, seed, ns, nproc)
         y_ref = np.array(y_ref)
@@ -587,7 +682,8 @@ def main():
         rel = float(np.max(np.abs(g - y_ref) / np.abs(y_ref)))
         cpu = {"value": round(ns / dt, 3), "unit": "samples/s", "cores": nproc, "kind": "oracle",
                "sample": "samples 0..%d of the same workload (seed 0), FP64 NumPy/SciPy (SuperLU), "
-                         "%d processes x 1 thread, wall %.1f s" % (ns - 1, nproc, dt)}
+                         "%d processes x 1 thread, wall %.1f s" % (ns - 1, nproc, dt),
+               "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count()}
         extra["parity_vs_oracle_max_rel"] = rel
         log("cpu baseline %.3f samples/s; GPU vs oracle max rel diff %.2e" % (ns / dt, rel))
     if not args.no_cpu_baseline:
@@ -632,6 +728,8 @@ def main():
 
     if not args.no_c3:
         extra["c3_mlmc_batch"] = c3_batch(ces, ctx, W, log)
+    if not args.no_c5:
+        extra["c5_flowcell"] = c5_record(ces, ctx, W, log)
 
     line = {
         "metric": METRIC,
