@@ -184,6 +184,24 @@ int ces_sample(ces_plan plan, uint64_t seed, uint64_t first_sample, int64_t coun
                double* y_dev, double* q_fine_dev, double* q_coarse_dev,
                int32_t* iters_dev, int32_t* status_dev, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ces_sample with every workspace buffer taken from one static device array
+ * of 256 MiB per device (held from the library's load until the process
+ * ends).  Arguments and outputs as for ces_sample, bit for bit the same
+ * results.  Allocates nothing: the call zeroes the plan's part of the array
+ * with a kernel, then enqueues the field, solve and finalize kernels on
+ * hip_stream chunk by chunk (fine and coarse solves one after the other)
+ * and returns once every solve's convergence has been read back.  All
+ * calls on a device share the array, which keeps the last call's contents:
+ * calls that overlap on one device (other streams or threads) race.
+ * CES_ERR_ARG when one sample unit of the plan (two samples in PAIR field
+ * mode) needs more workspace than the array holds (the message gives the
+ * bytes; 2049^2 meshes do not fit); CES_ERR_BUSY when the plan is in use. */
+int ces_sample_noalloc(ces_plan plan, uint64_t seed, uint64_t first_sample, int64_t count,
+                       double* y_dev, double* q_fine_dev, double* q_coarse_dev,
+                       int32_t* iters_dev, int32_t* status_dev, void* hip_stream);
+
 /* ---- batches of levels of uneven size (MLMC rounds, served work) ------ */
 
 /* One request: samples first_sample .. first_sample+count-1 of `plan`

@@ -181,22 +181,36 @@ class Plan:
     def m(self):
         return self.desc.m_fine
 
+    def _outputs(self, count, out):
+        if out is not None:
+            return out
+        torch = _torch()
+        dev = torch.device("cuda", self.ctx.device)
+        return {
+            "y": torch.empty(count, dtype=torch.float64, device=dev),
+            "q_fine": torch.empty(count, dtype=torch.float64, device=dev),
+            "q_coarse": torch.empty(count, dtype=torch.float64, device=dev),
+            "iters": torch.empty(count, dtype=torch.int32, device=dev),
+            "status": torch.empty(count, dtype=torch.int32, device=dev),
+        }
+
     def sample(self, seed, first, count, stream=None, out=None):
         """Y, Q_f, Q_c, iterations and status of samples first..first+count-1
         as device tensors (dict)."""
-        torch = _torch()
-        dev = torch.device("cuda", self.ctx.device)
-        if out is None:
-            out = {
-                "y": torch.empty(count, dtype=torch.float64, device=dev),
-                "q_fine": torch.empty(count, dtype=torch.float64, device=dev),
-                "q_coarse": torch.empty(count, dtype=torch.float64, device=dev),
-                "iters": torch.empty(count, dtype=torch.int32, device=dev),
-                "status": torch.empty(count, dtype=torch.int32, device=dev),
-            }
+        out = self._outputs(count, out)
         check(self.lib.ces_sample(self.handle, int(seed), int(first), int(count), _ptr(out["y"]),
                                   _ptr(out.get("q_fine")), _ptr(out.get("q_coarse")), _ptr(out.get("iters")),
                                   _ptr(out.get("status")), _stream_ptr(stream)))
+        return out
+
+    def sample_noalloc(self, seed, first, count, stream=None, out=None):
+        """ces_sample_noalloc: as sample(), with the library's workspace in
+        its static device array (the outputs are the caller's: pass `out`
+        to allocate nothing at all)."""
+        out = self._outputs(count, out)
+        check(self.lib.ces_sample_noalloc(self.handle, int(seed), int(first), int(count), _ptr(out["y"]),
+                                          _ptr(out.get("q_fine")), _ptr(out.get("q_coarse")),
+                                          _ptr(out.get("iters")), _ptr(out.get("status")), _stream_ptr(stream)))
         return out
 
     def eigenvalues(self):

@@ -101,6 +101,8 @@ SIGNATURES = {
     "ces_plan_destroy": (c_int32, [c_void_p]),
     "ces_sample": (c_int32, [c_void_p, c_uint64, c_uint64, c_int64, c_dptr, c_dptr, c_dptr, c_dptr,
                              c_dptr, c_void_p]),
+    "ces_sample_noalloc": (c_int32, [c_void_p, c_uint64, c_uint64, c_int64, c_dptr, c_dptr, c_dptr, c_dptr,
+                                     c_dptr, c_void_p]),
     "ces_sample_batch": (c_int32, [c_void_p, ctypes.POINTER(Request), c_int32, c_void_p]),
     "ces_schedule_get": (c_int32, [c_void_p, ctypes.POINTER(Schedule)]),
     "ces_schedule_set": (c_int32, [c_void_p, ctypes.POINTER(Schedule)]),

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(LIBDIR, "libcesmlmc.so")
-SOURCES = ["field.hip", "setup.hip", "solver.hip", "api.cpp", "desc.cpp", "exec.cpp", "server.cpp", "mlmc.cpp", "study.cpp", "qmc.cpp", "profile.cpp"]
+SOURCES = ["field.hip", "setup.hip", "solver.hip", "noalloc.hip", "api.cpp", "desc.cpp", "exec.cpp", "server.cpp", "mlmc.cpp", "study.cpp", "qmc.cpp", "profile.cpp"]
 ARCH = os.environ.get("CESMLMC_ARCH", "gfx950")
 
 

@@ -276,6 +276,9 @@ int ces_context_create(int device, size_t mem_budget_bytes, ces_context* out) {
     CES_HIP(hipSetDevice(device), "hipSetDevice");
     size_t fr = 0, tot = 0;
     CES_HIP(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+    // the static array of ces_sample_noalloc: its address on this device
+    int rc = scratch_init(device);
+    if (rc != CES_OK) return rc;
     auto* c = new ces_context_s;
     c->device = device;
     c->budget = mem_budget_bytes ? mem_budget_bytes : (size_t)(0.9 * (double)fr);
@@ -296,7 +299,15 @@ int ces_plan_create(ces_context ctx, const ces_level_desc* desc, ces_plan* out) 
     CES_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = nullptr;
     CES_HIP(ctx->pool.stream(0, &st), "set-up stream");
-    return plan_create(ctx, desc, default_allocator(), st, out);
+    rc = plan_create(ctx, desc, default_allocator(), st, out);
+    if (rc != CES_OK) return rc;
+    // offsets of ces_sample_noalloc's workspace in the static array
+    rc = scratch_layout(*out, st);
+    if (rc != CES_OK) {
+        ces_plan_destroy(*out);
+        *out = nullptr;
+    }
+    return rc;
 }
 
 int ces_plan_info_get(ces_plan p, ces_plan_info* info) {

@@ -189,6 +189,33 @@ long long workspace_slots(const ces_plan p, long long max_slots) {
 
 }  // namespace
 
+SolverCfg solver_cfg(const ces_plan p, bool coarse) {
+    const int m = p->d.m_fine;
+    SolverCfg cfg;
+    cfg.m = coarse ? m / 2 : m;
+    cfg.bc = p->d.bc;
+    cfg.f = p->d.f_value;
+    cfg.rtol = p->d.cg_rtol;
+    cfg.maxit = p->d.cg_max_iter;
+    cfg.qoi = p->d.qoi;
+    cfg.qx = p->d.qoi_x;
+    cfg.qy = p->d.qoi_y;
+    // single levels (plain Monte Carlo, the coarsest MLMC level) run the
+    // most samples per chunk: there the second visit of level 1 pays when
+    // it saves enough iterations, which needs a field that the coarse
+    // levels resolve: the length scale ell (lambda / sqrt(2 nu) for Matern,
+    // lambda for the separable exponential) spanning at least 8 fine cells.
+    // Measured at 257^2 (Matern nu = 1): lambda = 0.1 (ell = 18 cells)
+    // 9.96 -> 8.01 iterations, +7% samples/s; lambda = 0.02 (3.6 cells)
+    // 11.0 -> 10.0 iterations but -3%; Matern 3/2 at lambda = 0.01 more
+    // iterations (11.4 -> 11.9) and -15%.
+    const double ell = p->d.cov_kind == CES_COV_MATERN ? p->d.lambda / std::sqrt(2.0 * p->d.nu) : p->d.lambda;
+    const bool w1 = p->d.mg_cycle == CES_CYCLE_W1;
+    cfg.twice1 = w1 || (!coarse && p->d.mg_cycle == CES_CYCLE_AUTO && p->d.level_kind == CES_LEVEL_SINGLE &&
+                        ell * m >= 8.0);
+    return cfg;
+}
+
 size_t workspace_bytes(const ces_plan p, long long max_slots) {
     const long long slots = workspace_slots(p, max_slots);
     return slots > 0 ? (size_t)slots * slot_bytes(p) : 0;
@@ -218,34 +245,11 @@ int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st) {
     CES_HIP(p->qc.alloc((size_t)slots * 8, A), "qoi workspace");
     CES_HIP(p->itf.alloc((size_t)slots * 4, A), "qoi workspace");
     CES_HIP(p->itc.alloc((size_t)slots * 4, A), "qoi workspace");
-    SolverCfg cfg;
-    cfg.m = m;
-    cfg.bc = p->d.bc;
-    cfg.f = p->d.f_value;
-    cfg.rtol = p->d.cg_rtol;
-    cfg.maxit = p->d.cg_max_iter;
-    cfg.qoi = p->d.qoi;
-    cfg.qx = p->d.qoi_x;
-    cfg.qy = p->d.qoi_y;
-    // single levels (plain Monte Carlo, the coarsest MLMC level) run the
-    // most samples per chunk: there the second visit of level 1 pays when
-    // it saves enough iterations, which needs a field that the coarse
-    // levels resolve: the length scale ell (lambda / sqrt(2 nu) for Matern,
-    // lambda for the separable exponential) spanning at least 8 fine cells.
-    // Measured at 257^2 (Matern nu = 1): lambda = 0.1 (ell = 18 cells)
-    // 9.96 -> 8.01 iterations, +7% samples/s; lambda = 0.02 (3.6 cells)
-    // 11.0 -> 10.0 iterations but -3%; Matern 3/2 at lambda = 0.01 more
-    // iterations (11.4 -> 11.9) and -15%.
-    const double ell = p->d.cov_kind == CES_COV_MATERN ? p->d.lambda / std::sqrt(2.0 * p->d.nu) : p->d.lambda;
-    const bool w1 = p->d.mg_cycle == CES_CYCLE_W1;
-    cfg.twice1 = w1 || (p->d.mg_cycle == CES_CYCLE_AUTO && p->d.level_kind == CES_LEVEL_SINGLE && ell * m >= 8.0);
     std::string err;
-    p->sf = make_solver(cfg, (int)slots, p->is_double, A, st, &err);
+    p->sf = make_solver(solver_cfg(p, false), (int)slots, p->is_double, A, st, &err);
     if (!p->sf) return fail(CES_ERR_NOMEM, err);
     if (p->d.level_kind == CES_LEVEL_PAIR) {
-        cfg.m = m / 2;
-        cfg.twice1 = w1;
-        p->sc = make_solver(cfg, (int)slots, p->is_double, A, st, &err);
+        p->sc = make_solver(solver_cfg(p, true), (int)slots, p->is_double, A, st, &err);
         if (!p->sc) return fail(CES_ERR_NOMEM, err);
     }
     p->ws_bytes = p->work.bytes + p->kf.bytes + p->kc.bytes + p->sf->bytes() + (p->sc ? p->sc->bytes() : 0);
@@ -272,14 +276,16 @@ void set_lattice(FieldBatch<T>& b, const ces_plan p) {
     b.qshifts = p->q_shifts;
 }
 
+}  // namespace
+
 template <typename T>
-FieldBatch<T> field_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
+FieldBatch<T> make_field_batch(ces_plan p, const WsBufs& w, uint64_t seed, uint64_t q0, int units) {
     FieldBatch<T> b;
     b.n = p->n;
     b.m = p->d.m_fine;
     b.mode = p->d.field_mode == CES_FIELD_PAIR ? MODE_PAIR : MODE_HARTLEY;
     b.nf = p->nf;
-    // EMBED pairs draw the coarse field in a second batch (embedded_batch)
+    // EMBED pairs draw the coarse field in a second batch (make_embedded_batch)
     b.coarse = p->d.level_kind == CES_LEVEL_PAIR && !p->cpl;
     b.af = p->af.as<T>();
     b.ac = p->nf == 2 ? p->ac.as<T>() : p->af.as<T>();
@@ -289,22 +295,17 @@ FieldBatch<T> field_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
     b.q0 = q0;
     b.stream = p->d.stream;
     b.units = units;
-    b.work = p->work.as<cplx<T>>();
-    b.kf = p->kf.as<T>();
-    b.kf_stride = p->kf_ss;
-    b.kc = p->kc.as<T>();
-    b.kc_stride = p->kc_ss;
+    b.work = static_cast<cplx<T>*>(w.work);
+    b.kf = static_cast<T*>(w.kf);
+    b.kf_stride = w.kf_ss;
+    b.kc = static_cast<T*>(w.kc);
+    b.kc_stride = w.kc_ss;
     set_lattice(b, p);
     return b;
 }
 
-// CES_COUPLE_EMBED: the coarse field of the same units from the coarse
-// plan's amplitudes, its normals taken from the fine embedding's counters;
-// written as that plan's fine field into the pair's coarse coefficients.
-// It reuses the fine batch's intermediate buffer, so it must be enqueued
-// after the fine batch on the same stream.
 template <typename T>
-FieldBatch<T> embedded_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
+FieldBatch<T> make_embedded_batch(ces_plan p, const WsBufs& w, uint64_t seed, uint64_t q0, int units) {
     const ces_plan c = p->cpl.get();
     FieldBatch<T> b;
     b.n = c->n;
@@ -320,12 +321,32 @@ FieldBatch<T> embedded_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) 
     b.q0 = q0;
     b.stream = p->d.stream;
     b.units = units;
-    b.work = p->work.as<cplx<T>>();
-    b.kf = p->kc.as<T>();
-    b.kf_stride = p->kc_ss;
+    b.work = static_cast<cplx<T>*>(w.work);
+    b.kf = static_cast<T*>(w.kc);
+    b.kf_stride = w.kc_ss;
     b.n_src = p->n;
     set_lattice(b, p);   // counters are the fine embedding's
     return b;
+}
+
+template FieldBatch<float> make_field_batch<float>(ces_plan, const WsBufs&, uint64_t, uint64_t, int);
+template FieldBatch<double> make_field_batch<double>(ces_plan, const WsBufs&, uint64_t, uint64_t, int);
+template FieldBatch<float> make_embedded_batch<float>(ces_plan, const WsBufs&, uint64_t, uint64_t, int);
+template FieldBatch<double> make_embedded_batch<double>(ces_plan, const WsBufs&, uint64_t, uint64_t, int);
+
+namespace {
+
+
+WsBufs plan_ws(const ces_plan p) { return WsBufs{p->work.p, p->kf.p, p->kc.p, p->kf_ss, p->kc_ss}; }
+
+template <typename T>
+FieldBatch<T> field_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
+    return make_field_batch<T>(p, plan_ws(p), seed, q0, units);
+}
+
+template <typename T>
+FieldBatch<T> embedded_batch(ces_plan p, uint64_t seed, uint64_t q0, int units) {
+    return make_embedded_batch<T>(p, plan_ws(p), seed, q0, units);
 }
 
 template <typename T>

@@ -172,9 +172,16 @@ public:
     virtual long long xstride() const = 0;
 };
 // is_double selects T = double (plain path) or float (mixed path).  The
-// workspace comes from `alloc` and is zeroed on stream st.
+// workspace comes from `alloc` and is zeroed on stream st (by a kernel)
+// unless zero = false (the caller zeroes it before every use).
 std::unique_ptr<Solver> make_solver(const SolverCfg& cfg, int capacity, bool is_double,
-                                    DeviceAllocator* alloc, hipStream_t st, std::string* err);
+                                    DeviceAllocator* alloc, hipStream_t st, std::string* err, bool zero = true);
+// Device bytes make_solver(cfg, capacity, is_double, ...) takes from its
+// allocator (host arithmetic only).
+size_t solver_bytes(const SolverCfg& cfg, int capacity, bool is_double);
+// Zero `bytes` bytes at dst (a multiple of 4, dst 4-byte aligned) with a
+// kernel (no memset node when the stream is being captured).
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
 
 // y[i] = qf[i] - qc[i] (or qf if qc null) scattered to out slots.
 hipError_t launch_finalize(const double* qf, const double* qc, const int* itf, const int* itc,

@@ -98,6 +98,49 @@ private:
 
 size_t lvl_stride(int m);
 
+// Bump allocator over a caller-given device range: consecutive 256-byte
+// aligned blocks, release does nothing (the range is reused as a whole).
+class ArenaAllocator final : public DeviceAllocator {
+public:
+    ArenaAllocator(void* base, size_t bytes) : base_(static_cast<char*>(base)), size_(bytes) {}
+    hipError_t alloc(size_t bytes, void** p) override {
+        const size_t b = (bytes + 255) / 256 * 256;
+        if (b > size_ - off_) return hipErrorOutOfMemory;
+        *p = base_ + off_;
+        off_ += b;
+        return hipSuccess;
+    }
+    void release(void*) override {}
+    size_t used() const { return off_; }
+
+private:
+    char* base_;
+    size_t size_, off_ = 0;
+};
+
+// Device buffers of one sample workspace: the field DFT intermediate and
+// the coefficient slots of the fine and coarse meshes.
+struct WsBufs {
+    void* work = nullptr;
+    void* kf = nullptr;
+    void* kc = nullptr;
+    long long kf_ss = 0, kc_ss = 0;
+};
+
+// Workspace of ces_sample_noalloc: every buffer lies at a fixed offset of
+// the library's static device array (see noalloc.hip), set up with the plan;
+// the solvers keep only host state here.
+struct StaticWs {
+    int device = -1;
+    int units = 0, slots = 0;
+    size_t bytes = 0;              // extent of the static array this layout covers
+    WsBufs w;
+    double *qf = nullptr, *qc = nullptr;
+    int *itf = nullptr, *itc = nullptr;
+    std::unique_ptr<ArenaAllocator> arena;   // declared before the solvers: outlives them
+    std::unique_ptr<Solver> sf, sc;
+};
+
 }  // namespace ces
 
 struct ces_context_s {
@@ -137,6 +180,8 @@ struct ces_plan_s {
     // (n*n int32, -1 = Philox), q_shifts random shifts; q_s = 0: none
     int32_t q_s = 0, q_shifts = 0;
     ces::DevBuf q_z, q_rank;
+    // layout of ces_sample_noalloc (null when a sample unit does not fit)
+    std::unique_ptr<ces::StaticWs> sws;
     std::atomic<int> busy{0};           // a scheduler is using the workspace
     // recorded after the last work that used the workspace; the next lane
     // of this plan waits for it (lanes of successive calls may run on
@@ -184,6 +229,23 @@ int ensure_workspace(ces_plan p, long long max_slots, hipStream_t st);
 void drop_workspace(ces_plan p);
 // Device bytes ensure_workspace(p, max_slots) would allocate.
 size_t workspace_bytes(const ces_plan p, long long max_slots);
+// Solver settings of the plan's fine (coarse = false) or coarse mesh.
+SolverCfg solver_cfg(const ces_plan p, bool coarse);
+// Field batches of units q0 .. q0+units-1 into the workspace buffers w (the
+// coarse field of an EMBED pair: make_embedded_batch, enqueued after the
+// fine batch on the same stream, since it reuses w.work).
+template <typename T>
+FieldBatch<T> make_field_batch(ces_plan p, const WsBufs& w, uint64_t seed, uint64_t q0, int units);
+template <typename T>
+FieldBatch<T> make_embedded_batch(ces_plan p, const WsBufs& w, uint64_t seed, uint64_t q0, int units);
+
+// The static device array behind ces_sample_noalloc (noalloc.hip).
+// scratch_init: with `device` current, looks up the array's address on
+// that device once (later calls return at once).  scratch_layout: sets up
+// p->sws when a sample unit of p fits (no error otherwise: the entry
+// point reports it).
+int scratch_init(int device);
+int scratch_layout(ces_plan p, hipStream_t st);
 
 // Gaussian field of one sample into z_fine / z_coarse (parity hook).
 int field_impl(ces_plan p, uint64_t seed, uint64_t sample, double* zf, double* zc, hipStream_t st);

@@ -1372,6 +1372,14 @@ __global__ __launch_bounds__(kBlock) void k_qoi(const double* __restrict__ X, Lv
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_zero(uint4* __restrict__ dst, long long n16, unsigned* __restrict__ tail,
+                                               int ntail) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0u;
+}
+
 __global__ void k_set_int(int* dst, int v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
 }
@@ -1483,7 +1491,7 @@ public:
         for (auto& e : ev_)
             if (e) (void)hipEventDestroy(e);
     }
-    bool alloc(DeviceAllocator* a, hipStream_t st, std::string* err) {
+    bool alloc(DeviceAllocator* a, hipStream_t st, std::string* err, bool zero) {
         alloc_ = a;
         hipError_t e = alloc_->alloc(bytes_, &base_);
         if (e != hipSuccess) {
@@ -1491,7 +1499,7 @@ public:
             *err = std::string("solver workspace allocation failed: ") + hipGetErrorString(e);
             return false;
         }
-        e = hipMemsetAsync(base_, 0, bytes_, st);
+        if (zero) e = launch_zero(base_, bytes_, st);
         if (e == hipSuccess) {
             hcnt_ = pinned_slot_acquire();
             if (!hcnt_) e = hipErrorOutOfMemory;
@@ -1976,20 +1984,40 @@ private:
 
 }  // namespace
 
+size_t solver_bytes(const SolverCfg& cfg, int capacity, bool is_double) {
+    if (cfg.m < 4 || (cfg.m & (cfg.m - 1)) != 0) return 0;
+    if (is_double) return SolverImpl<double>(cfg, capacity).bytes();
+    return SolverImpl<float>(cfg, capacity).bytes();
+}
+
 std::unique_ptr<Solver> make_solver(const SolverCfg& cfg, int capacity, bool is_double, DeviceAllocator* alloc,
-                                    hipStream_t st, std::string* err) {
+                                    hipStream_t st, std::string* err, bool zero) {
     if (cfg.m < 4 || (cfg.m & (cfg.m - 1)) != 0) {
         *err = "solver mesh must be a power of two >= 4";
         return nullptr;
     }
     if (is_double) {
         auto s = std::make_unique<SolverImpl<double>>(cfg, capacity);
-        if (!s->alloc(alloc, st, err)) return nullptr;
+        if (!s->alloc(alloc, st, err, zero)) return nullptr;
         return s;
     }
     auto s = std::make_unique<SolverImpl<float>>(cfg, capacity);
-    if (!s->alloc(alloc, st, err)) return nullptr;
+    if (!s->alloc(alloc, st, err, zero)) return nullptr;
     return s;
+}
+
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    // library buffers are 256-byte aligned: 16-byte stores, then at most
+    // three words
+    if (((uintptr_t)dst & 15) != 0 || (bytes & 3) != 0) return hipErrorInvalidValue;
+    const size_t head = bytes / 16 * 16;
+    const long long n16 = (long long)(head / 16);
+    const int ntail = (int)((bytes - head) / 4);
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>(cdiv(n16, kBlock), 4096));
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(kBlock), 0, st, reinterpret_cast<uint4*>(dst), n16,
+                       reinterpret_cast<unsigned*>(static_cast<char*>(dst) + head), ntail);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double* qf, const double* qc, const int* itf, const int* itc, int slot0,

@@ -214,7 +214,7 @@ private:
 }  // namespace
 
 std::unique_ptr<Solver> make_solver(const SolverCfg& cfg, int capacity, bool is_double, DeviceAllocator* alloc,
-                                    hipStream_t, std::string* err) {
+                                    hipStream_t, std::string* err, bool) {
     auto s = std::make_unique<FakeSolver>(cfg, capacity, is_double, alloc);
     if (s->init() != hipSuccess) {
         *err = "solver workspace (fake)";
