@@ -37,8 +37,8 @@ KERNEL_SYMBOL = {
     "pcg_update": "k_pcg_update<false>",
     "pcg_init": "k_pcg_init<float>",
     "small_pcg": "k_small_pcg<float, 256>",
-    "field_rows": "k_field_rows<float, 16, 0, 1>",
-    "field_cols": "k_field_cols<float, 16, 0, 1, false>",
+    "field_y": "k_field_y<float, 16, 0, 1>",
+    "field_x": "k_field_x<float, 16, 0, 1, false>",
     "qoi": "k_qoi<float>",
 }
 # HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters,
@@ -276,15 +276,25 @@ def c3_batch(ces, ctx, W, log, reps=5):
             ts.append((time.perf_counter() - t0) * 1e3)
         return float(np.median(ts))
 
+    default = list(ctx.schedule)
+    t_default = timed(lambda: ctx.sample_batch(reqs, outs=outs))
+    # the autotuner's schedule for this batch (a stored choice when
+    # CESMLMC_AUTOTUNE_CACHE names a file that has one)
+    tuned, tune_ms, _ = ctx.autotune(reqs, outs=outs)
     t_batch = timed(lambda: ctx.sample_batch(reqs, outs=outs))
     t_seq = timed(lambda: [p.sample(0, 0, n, out=o) for p, n, o in zip(plans, W.C3_N, seq)])
+    torch.cuda.synchronize()
+    same = same and all(bool(torch.equal(a["y"], b["y"])) for a, b in zip(outs, seq))
     total = sum(W.C3_N)
-    log("C3 five-level batch: %.2f ms per round (%d level samples), one call per level %.2f ms; identical %s"
-        % (t_batch, total, t_seq, same))
+    log("C3 five-level batch: %.2f ms per round (%d level samples) under the tuned schedule %s (default %s: "
+        "%.2f ms), one call per level %.2f ms; identical %s" % (t_batch, total, list(tuned), default, t_default,
+                                                               t_seq, same))
+    ctx.schedule = tuple(default)
     return {"ms_per_round": round(t_batch, 3), "level_samples_per_round": total,
             "level_samples_per_s": round(total / (t_batch * 1e-3), 1),
             "ms_one_call_per_level": round(t_seq, 3), "batch_equals_per_level_bitwise": same,
-            "schedule": list(ctx.schedule)}
+            "schedule": list(tuned), "schedule_fields": ["depth", "max_lanes", "chunk_samples", "graphs"],
+            "default_schedule": default, "ms_per_round_default_schedule": round(t_default, 3)}
 
 
 def serve(args):

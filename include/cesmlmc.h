@@ -159,8 +159,9 @@ void ces_level_desc_default(ces_level_desc* d);
 /* Bind to HIP device `device`.  mem_budget_bytes caps the library's own
  * workspace (0 = 90% of free device memory).  A plan's sample workspace,
  * allocated on its first sampling call, holds as many samples as fit in
- * 4.5 GiB (at most 8192; 65536 for m <= 32), or in the size in MiB given by
- * the environment variable CESMLMC_WORKSPACE_MB, and within the budget.  A
+ * 4.5 GiB or 64 samples, whichever is more (at most 8192; 65536 for
+ * m <= 32), or in the size in MiB given by the environment variable
+ * CESMLMC_WORKSPACE_MB, and within the budget.  A
  * request larger than the workspace runs in the fewest chunks that fit,
  * all of (nearly) equal size. */
 int ces_context_create(int device, size_t mem_budget_bytes, ces_context* out);
@@ -255,7 +256,12 @@ int ces_schedule_set(ces_context ctx, const ces_schedule* sched);
 /* Autotuner: runs ces_sample_batch(reqs) under candidate schedules (each
  * run recomputes the same samples into the requests' outputs), keeps the
  * fastest as the context's schedule and returns it in *chosen and its
- * time in *best_ms (either may be NULL).  Synchronous. */
+ * time in *best_ms (either may be NULL).  Synchronous.  When the
+ * environment variable CESMLMC_AUTOTUNE_CACHE names a file, the choice is
+ * appended to it under a key of the device architecture and, per distinct
+ * plan, its descriptor and sample count in the batch; a later call with the
+ * same key applies the stored choice and runs the batch once (its outputs
+ * computed, *best_ms the stored time) instead of tuning again. */
 int ces_autotune(ces_context ctx, const ces_request* reqs, int32_t nreq, void* hip_stream,
                  ces_schedule* chosen, double* best_ms);
 

@@ -4,8 +4,11 @@
 // for many requests of different mesh sizes at once.
 #include <algorithm>
 #include <chrono>
+#include <cinttypes>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <thread>
 
 #include "plan.hpp"
@@ -173,7 +176,11 @@ long long workspace_slots(const ces_plan p, long long max_slots) {
     const int m = p->d.m_fine;
     const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
     const size_t per_slot = slot_bytes(p);
-    size_t target = (size_t)9 << 29;   // 4.5 GiB
+    // 4.5 GiB, but room for at least 64 samples: on meshes of about 300 MB
+    // per sample the per-chunk overheads (one host round trip per CG
+    // iteration) dominate small chunks (2049^2 flow cell, 1024 samples per
+    // call: 13 per chunk 781 samples/s, 55 per chunk 845, 138 per chunk 857)
+    size_t target = std::max((size_t)9 << 29, 64 * per_slot);
     if (const char* env = std::getenv("CESMLMC_WORKSPACE_MB")) target = (size_t)std::atoll(env) << 20;
     const size_t used = p->ctx->used.load();
     if (p->ctx->budget && p->ctx->budget - std::min(p->ctx->budget, used) < target)
@@ -747,6 +754,68 @@ int run_batch(ces_context ctx, const ces_request* reqs, int32_t nreq, hipStream_
     return rc != CES_OK ? rc : rj;
 }
 
+// ---- persisted autotuner choices (file named by CESMLMC_AUTOTUNE_CACHE) --
+// One line per tuned batch: "<key> depth max_lanes chunk_samples graphs
+// best_ms".  The key is an FNV-1a hash of the device's architecture name
+// and, per distinct plan in request order, its descriptor bytes and the
+// batch's sample count on it.
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+    const unsigned char* p = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+    return h;
+}
+
+uint64_t batch_key(ces_context ctx, const ces_request* reqs, int32_t nreq) {
+    uint64_t h = 1469598103934665603ull;
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess)
+        h = fnv1a(h, prop.gcnArchName, std::strlen(prop.gcnArchName));
+    for (int32_t i = 0; i < nreq; ++i) {
+        bool seen = false;
+        for (int32_t j = 0; j < i; ++j) seen = seen || reqs[j].plan == reqs[i].plan;
+        if (seen || !reqs[i].plan) continue;
+        int64_t total = 0;
+        for (int32_t j = i; j < nreq; ++j)
+            if (reqs[j].plan == reqs[i].plan) total += reqs[j].count;
+        h = fnv1a(h, &reqs[i].plan->d, sizeof(ces_level_desc));
+        h = fnv1a(h, &total, sizeof(total));
+    }
+    return h;
+}
+
+bool cache_lookup(const char* path, uint64_t key, ces_schedule* s, double* ms) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        uint64_t k = 0;
+        int depth = 0, lanes = 0, graphs = 0;
+        long long chunk = 0;
+        double t = 0.0;
+        if (std::sscanf(line, "%" SCNx64 " %d %d %lld %d %lf", &k, &depth, &lanes, &chunk, &graphs, &t) == 6 &&
+            k == key && depth >= 1 && depth <= 4 && lanes >= 0 && chunk >= 0 && (graphs == 0 || graphs == 1)) {
+            *s = ces_schedule{};
+            s->depth = depth;
+            s->max_lanes = lanes;
+            s->chunk_samples = chunk;
+            s->graphs = graphs;
+            *ms = t;
+            found = true;   // the last entry for a key wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char* path, uint64_t key, const ces_schedule& s, double ms) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%016" PRIx64 " %d %d %lld %d %.4f\n", key, s.depth, s.max_lanes, (long long)s.chunk_samples,
+                 s.graphs, ms);
+    std::fclose(f);
+}
+
 }  // namespace
 
 extern "C" {
@@ -794,6 +863,21 @@ int ces_autotune(ces_context ctx, const ces_request* reqs, int32_t nreq, void* s
     if (nreq <= 0 || !reqs) return fail(CES_ERR_ARG, "requests");
     CES_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // a choice persisted for this batch: apply it and run the batch once
+    const char* cache = std::getenv("CESMLMC_AUTOTUNE_CACHE");
+    const uint64_t key = cache && *cache ? batch_key(ctx, reqs, nreq) : 0;
+    if (cache && *cache) {
+        ces_schedule c{};
+        double ms = 0.0;
+        if (cache_lookup(cache, key, &c, &ms)) {
+            int rc = run_batch(ctx, reqs, nreq, st, c);
+            if (rc != CES_OK) return rc;
+            ctx->sched = c;
+            if (chosen) *chosen = c;
+            if (best_ms) *best_ms = ms;
+            return CES_OK;
+        }
+    }
     auto timed = [&](const ces_schedule& s, double* ms) -> int {
         double best = 1e300;
         for (int rep = 0; rep < 2; ++rep) {
@@ -856,6 +940,7 @@ int ces_autotune(ces_context ctx, const ces_request* reqs, int32_t nreq, void* s
     ctx->sched = best;
     if (chosen) *chosen = best;
     if (best_ms) *best_ms = tbest;
+    if (cache && *cache) cache_store(cache, key, best, tbest);
     return CES_OK;
 }
 

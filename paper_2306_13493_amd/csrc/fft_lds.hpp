@@ -4,7 +4,7 @@
 // Sign: V_p = sum_j v_j exp(+2 pi i j p / N) (the Fourier matrix of the
 // paper has a positive exponent); no normalisation.
 //
-// Mixed-radix (4, 2, 3) Stockham autosort: stage with radix R over
+// Mixed-radix (8, 4, 2, 3) Stockham autosort: stage with radix R over
 // sub-length Ns takes inputs v_r = x[j + r N/R], twiddles them by
 // W_{Ns R}^{r k} (k = j mod Ns), applies the R-point DFT and writes
 // y[(j - k) R + k + r Ns].  One LDS buffer: each thread first reads all its
@@ -28,6 +28,7 @@ inline FftPlan make_fft_plan(int n) {
     FftPlan p{};
     p.n = n;
     int r = n;
+    while (r % 8 == 0 && r > 1) { p.rad[p.nst++] = 8; r /= 8; }
     while (r % 4 == 0 && r > 1) { p.rad[p.nst++] = 4; r /= 4; }
     if (r % 2 == 0) { p.rad[p.nst++] = 2; r /= 2; }
     while (r % 3 == 0) { p.rad[p.nst++] = 3; r /= 3; }
@@ -48,6 +49,25 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
         v[2] = csub(t0, t2);
         v[1] = cadd(t1, cmuli(t3));
         v[3] = csub(t1, cmuli(t3));
+    } else if constexpr (R == 8) {
+        // two 4-point DFTs (even, odd inputs), odd ones twiddled by
+        // W8^k = exp(+2 pi i k / 8), then 2-point butterflies
+        cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+        cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<T, 4>(e);
+        dft_small<T, 4>(o);
+        const T c = T(0.70710678118654752440);   // 1/sqrt(2)
+        const cplx<T> o1 = {c * (o[1].x - o[1].y), c * (o[1].x + o[1].y)};     // (1+i)/sqrt2
+        const cplx<T> o2 = cmuli(o[2]);                                        // i
+        const cplx<T> o3 = {-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y)};    // (-1+i)/sqrt2
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
     } else {  // R == 3, W = exp(+2 pi i / 3)
         const T h = T(0.5);
         const T s3 = T(0.86602540378443864676);  // sqrt(3)/2
@@ -62,10 +82,11 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
     }
 }
 
-// One Stockham stage over `lines` lines of length n held back to back in buf.
+// One Stockham stage over `lines` lines of length n in buf, line l at
+// buf + l * ld (ld >= n; a padded stride spreads lines over the LDS banks).
 // MB = maximum butterflies per thread (compile time, registers).
 template <typename T, int R, int MB>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int lines, int Ns,
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int ld, int lines, int Ns,
                                           const cplx<T>* __restrict__ tw) {
     const int NR = n / R;
     const int total = NR * lines;
@@ -77,7 +98,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int lines, int Ns
         if (g < total) {
             const int line = g / NR;
             const int j = g - line * NR;
-            const cplx<T>* x = buf + line * n;
+            const cplx<T>* x = buf + line * ld;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b][r] = x[j + r * NR];
         }
@@ -95,7 +116,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int lines, int Ns
                 for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * stride]);
             }
             dft_small<T, R>(v[b]);
-            cplx<T>* y = buf + line * n + (j - k) * R + k;
+            cplx<T>* y = buf + line * ld + (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) y[r * Ns] = v[b][r];
         }
@@ -103,19 +124,21 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int lines, int Ns
     __syncthreads();
 }
 
-// In-place DFT of `lines` consecutive lines of length fp.n in LDS.
+// In-place DFT of `lines` lines of length fp.n in LDS, line l at buf + l * ld.
 // E bounds the complex values per thread: lines * n <= E * blockDim.x.
 template <typename T, int E>
-__device__ void fft_lines(cplx<T>* buf, int lines, const FftPlan& fp, const cplx<T>* __restrict__ tw) {
+__device__ void fft_lines(cplx<T>* buf, int lines, int ld, const FftPlan& fp, const cplx<T>* __restrict__ tw) {
     int Ns = 1;
     for (int s = 0; s < fp.nst; ++s) {
         const int R = fp.rad[s];
-        if (R == 4)
-            fft_stage<T, 4, (E + 3) / 4>(buf, fp.n, lines, Ns, tw);
+        if (R == 8)
+            fft_stage<T, 8, (E + 7) / 8>(buf, fp.n, ld, lines, Ns, tw);
+        else if (R == 4)
+            fft_stage<T, 4, (E + 3) / 4>(buf, fp.n, ld, lines, Ns, tw);
         else if (R == 2)
-            fft_stage<T, 2, (E + 1) / 2>(buf, fp.n, lines, Ns, tw);
+            fft_stage<T, 2, (E + 1) / 2>(buf, fp.n, ld, lines, Ns, tw);
         else
-            fft_stage<T, 3, (E + 2) / 3>(buf, fp.n, lines, Ns, tw);
+            fft_stage<T, 3, (E + 2) / 3>(buf, fp.n, ld, lines, Ns, tw);
         Ns *= R;
     }
 }

@@ -4,13 +4,18 @@
 // restriction to the fine and coarse meshes, exponential).
 //
 // The 2-D DFT is two passes of workgroup-local 1-D DFTs (fft_lds.hpp):
-//   rows:    for each embedding row j2, transform along j1 and keep only the
-//            m+1 outputs p1 <= m that the restriction reads; store them
-//            transposed, work[p1][j2] (contiguous along j2).
-//   columns: for each kept p1, transform along j2, keep p2 <= m, combine
-//            and write exp(Z) at the mesh nodes.
+//   y pass:  for each embedding column j1 (a workgroup takes L adjacent
+//            ones), draw the normals, scale, transform along j2 and keep
+//            only the m+1 outputs p2 <= m that the restriction reads; store
+//            them as work[p2][j1] (L adjacent j1 per store: aligned 8L-byte
+//            runs of complex values).
+//   x pass:  for each kept p2 (a row of the mesh), transform along j1, keep
+//            p1 <= m, combine and write exp(Z) at the mesh nodes: whole
+//            mesh rows (and whole coarse rows at even p2) per store.
 // Pruning the first pass to m+1 of n outputs cuts the intermediate and the
-// second pass to (m+1)/n ~ 1/2..1/4 of a full transform.
+// second pass to (m+1)/n ~ 1/2..1/4 of a full transform.  LDS lines are
+// padded by one complex value so that lines written across threads do not
+// share a bank.
 #include "internal.hpp"
 #include "philox_bm.hpp"
 
@@ -58,13 +63,13 @@ __device__ __forceinline__ double lattice_normal(uint64_t seed, uint32_t stream,
 }
 
 template <typename T, int E, int MODE, int NF>
-__global__ __launch_bounds__(kBlock) void k_field_rows(FieldBatch<T> b, int L) {
+__global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int n = b.n;
+    const int n = b.n, ld = n + 1;
     const int u = blockIdx.y;
     const uint64_t q = b.q0 + (uint64_t)u;
-    const int j2_0 = blockIdx.x * L;
+    const int j1_0 = blockIdx.x * L;
     // lattice point (radical-inverse order, as a 64-bit fraction) and shift
     uint64_t qpt = 0, qsh = 0;
     if (MODE == MODE_HARTLEY && b.qrank) {
@@ -72,10 +77,12 @@ __global__ __launch_bounds__(kBlock) void k_field_rows(FieldBatch<T> b, int L) {
         qsh = q - i * (uint64_t)b.qshifts;
         qpt = __builtin_bitreverse64(i);
     }
+    // adjacent threads take adjacent j1 of one row j2 (coalesced amplitude
+    // reads); line `line` of the LDS buffer is column j1_0 + line
     for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
-        const int line = t / n;
-        const int j1 = t - line * n;
-        const int j2 = j2_0 + line;
+        const int j2 = t / L;
+        const int line = t - j2 * L;
+        const int j1 = j1_0 + line;
         const uint32_t ia = (uint32_t)j1 + (uint32_t)n * (uint32_t)j2;   // amplitude index
         uint32_t e = ia;                                                  // normal counter
         if (b.n_src > 0) e = (uint32_t)src_index(j1, n, b.n_src) + (uint32_t)b.n_src * (uint32_t)src_index(j2, n, b.n_src);
@@ -90,46 +97,50 @@ __global__ __launch_bounds__(kBlock) void k_field_rows(FieldBatch<T> b, int L) {
         const double xr = g0;
         const double xi = (MODE == MODE_PAIR) ? g1 : 0.0;
         const double a = (double)b.af[ia];
-        buf[line * n + j1] = cplx<T>{(T)(a * xr), (T)(a * xi)};
+        buf[line * ld + j2] = cplx<T>{(T)(a * xr), (T)(a * xi)};
         if constexpr (NF == 2) {
             const double c = (double)b.ac[ia];
-            buf[(L + line) * n + j1] = cplx<T>{(T)(c * xr), (T)(c * xi)};
+            buf[(L + line) * ld + j2] = cplx<T>{(T)(c * xr), (T)(c * xi)};
         }
     }
     __syncthreads();
-    fft_lines<T, E>(buf, NF * L, b.fp, b.tw);
+    fft_lines<T, E>(buf, NF * L, ld, b.fp, b.tw);
     const int mp1 = b.m + 1;
     for (int t = threadIdx.x; t < NF * mp1 * L; t += blockDim.x) {
         const int line = t % L;
         const int rest = t / L;
-        const int p1 = rest % mp1;
+        const int p2 = rest % mp1;
         const int f = rest / mp1;
-        b.work[((size_t)(f * b.units + u) * mp1 + p1) * n + j2_0 + line] = buf[(f * L + line) * n + p1];
+        b.work[((size_t)(f * b.units + u) * mp1 + p2) * n + j1_0 + line] = buf[(f * L + line) * ld + p2];
     }
 }
 
 template <typename T, int E, int MODE, int NF, bool ZOUT>
-__global__ __launch_bounds__(kBlock) void k_field_cols(FieldBatch<T> b, int L) {
+__global__ __launch_bounds__(kBlock) void k_field_x(FieldBatch<T> b, int L) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int n = b.n;
+    const int n = b.n, ld = n + 1;
     const int mp1 = b.m + 1;
-    const int p1_0 = blockIdx.x * L;
+    const int p2_0 = blockIdx.x * L;
     const int u = blockIdx.y;
     const int f = blockIdx.z;
-    const int lines = min(L, mp1 - p1_0);
-    const cplx<T>* src = b.work + ((size_t)(f * b.units + u) * mp1 + p1_0) * n;
-    for (int t = threadIdx.x; t < lines * n; t += blockDim.x) buf[t] = src[t];
+    const int lines = min(L, mp1 - p2_0);
+    const cplx<T>* src = b.work + ((size_t)(f * b.units + u) * mp1 + p2_0) * n;
+    for (int t = threadIdx.x; t < lines * n; t += blockDim.x) {
+        const int l = t / n;
+        buf[l * ld + (t - l * n)] = src[t];
+    }
     __syncthreads();
-    fft_lines<T, E>(buf, lines, b.fp, b.tw);
+    fft_lines<T, E>(buf, lines, ld, b.fp, b.tw);
     const bool fine = (f == 0);
     const bool coarse = b.coarse && (f == NF - 1);
-    const int mc = b.m / 2, mcp1 = mc + 1;
+    const int mcp1 = b.m / 2 + 1;
+    // adjacent threads write adjacent p1 of one mesh row p2
     for (int t = threadIdx.x; t < lines * mp1; t += blockDim.x) {
-        const int l = t % lines;
-        const int p2 = t / lines;
-        const int p1 = p1_0 + l;
-        const cplx<T> v = buf[l * n + p2];
+        const int l = t / mp1;
+        const int p1 = t - l * mp1;
+        const int p2 = p2_0 + l;
+        const cplx<T> v = buf[l * ld + p1];
         const bool even = ((p1 | p2) & 1) == 0;
         if (MODE == MODE_PAIR) {
             const T z0 = v.x, z1 = v.y;
@@ -183,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_eig_rows(const double* __restrict__ 
         buf[t] = cplx<double>{s[(size_t)j2_0 * n + t], 0.0};
     }
     __syncthreads();
-    fft_lines<double, E>(buf, L, fp, tw);
+    fft_lines<double, E>(buf, L, n, fp, tw);
     for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
         const int line = t % L;
         const int p1 = t / L;
@@ -202,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_eig_cols(const cplx<double>* __restr
     const int p1_0 = blockIdx.x * L;
     for (int t = threadIdx.x; t < L * n; t += blockDim.x) buf[t] = work[(size_t)p1_0 * n + t];
     __syncthreads();
-    fft_lines<double, E>(buf, L, fp, tw);
+    fft_lines<double, E>(buf, L, n, fp, tw);
     double im = 0.0;
     for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
         const int l = t % L;
@@ -233,9 +244,9 @@ __global__ __launch_bounds__(kBlock) void k_convert_d2f(const double* __restrict
 
 template <typename T, int E, int MODE, int NF>
 hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2) {
-    const size_t lds1 = (size_t)NF * L1 * b.n * sizeof(cplx<T>);
-    const size_t lds2 = (size_t)L2 * b.n * sizeof(cplx<T>);
-    auto kr = k_field_rows<T, E, MODE, NF>;
+    const size_t lds1 = (size_t)NF * L1 * (b.n + 1) * sizeof(cplx<T>);
+    const size_t lds2 = (size_t)L2 * (b.n + 1) * sizeof(cplx<T>);
+    auto kr = k_field_y<T, E, MODE, NF>;
     hipError_t e = allow_lds(kr, lds1);
     if (e != hipSuccess) return e;
     // algorithmic bytes: amplitudes once, the pruned intermediate written
@@ -248,20 +259,20 @@ hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2
     Profiler& P = Profiler::get();
     Profiler::Slot ps = P.begin();
     hipExtLaunchKernelGGL(kr, dim3(b.n / L1, b.units), dim3(kBlock), lds1, st, ps.a, ps.b, 0, b, L1);
-    P.end(ps, "field_rows", (double)NF * b.n * b.n * sT + inter, 1);
+    P.end(ps, "field_y", (double)NF * b.n * b.n * sT + inter, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     dim3 g2(cdiv(b.m + 1, L2), b.units, NF);
     ps = P.begin();
     if (b.zf) {
-        auto kc = k_field_cols<T, E, MODE, NF, true>;
+        auto kc = k_field_x<T, E, MODE, NF, true>;
         if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
         hipExtLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, ps.a, ps.b, 0, b, L2);
     } else {
-        auto kc = k_field_cols<T, E, MODE, NF, false>;
+        auto kc = k_field_x<T, E, MODE, NF, false>;
         if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
         hipExtLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, ps.a, ps.b, 0, b, L2);
     }
-    P.end(ps, "field_cols", inter + kout, 1);
+    P.end(ps, "field_x", inter + kout, 1);
     return hipGetLastError();
 }
 

@@ -68,6 +68,12 @@ const char* hipGetErrorString(hipError_t e) {
 }
 
 hipError_t hipSetDevice(int) { return hipSuccess; }
+
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* prop, int) {
+    std::memset(prop, 0, sizeof(*prop));
+    std::strcpy(prop->gcnArchName, "fake-host");
+    return hipSuccess;
+}
 hipError_t hipDeviceSynchronize(void) { return hipSuccess; }
 hipError_t hipGetLastError(void) { return hipSuccess; }
 

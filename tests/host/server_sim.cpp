@@ -12,11 +12,14 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <random>
 #include <string>
 #include <thread>
 #include <vector>
+
+#include <unistd.h>
 
 #include "plan.hpp"
 
@@ -27,6 +30,7 @@ void fake_device_fail_after(long long n);
 void fake_device_set_iteration_delay_us(int us);
 int fake_device_max_concurrent_solves();
 void fake_device_reset_counters();
+long long fake_device_solves();
 }
 
 namespace {
@@ -166,6 +170,77 @@ void scenario_batch() {
     }
     // a plan in two concurrent calls is refused, not corrupted
     CHECK(plans[0]->busy.load() == 0);
+    for (ces_plan p : plans) ces_plan_destroy(p);
+    CHECK(fake_hip_live_bytes() == 0);
+    delete ctx;
+}
+
+// ces_autotune with CESMLMC_AUTOTUNE_CACHE: the first call tunes and
+// stores its choice; a second call on the same batch applies the stored
+// choice and runs the batch once, outputs complete.
+void scenario_autotune_cache() {
+    char path[64];
+    std::snprintf(path, sizeof(path), "/tmp/ces_autotune_%d.txt", (int)getpid());
+    std::remove(path);
+    setenv("CESMLMC_AUTOTUNE_CACHE", path, 1);
+    ces_context ctx = make_ctx((size_t)8 << 30);
+    std::vector<ces_level_desc> ds = {desc(16, false), desc(64, true, CES_PREC_MIXED, CES_FIELD_PAIR, 1),
+                                      desc(128, true, CES_PREC_MIXED, CES_FIELD_PAIR, 2)};
+    std::vector<ces_plan> plans;
+    for (auto& d : ds) {
+        ces_plan p = nullptr;
+        CHECK(ces::plan_create(ctx, &d, ces::default_allocator(), nullptr, &p) == CES_OK);
+        plans.push_back(p);
+    }
+    const int64_t counts[] = {300, 40, 9};
+    std::vector<ces_request> reqs;
+    for (int i = 0; i < 3; ++i) {
+        void* y = nullptr;
+        CHECK(hipMalloc(&y, 8 * (size_t)counts[i]) == hipSuccess);
+        reqs.push_back(ces_request{plans[i], 9, 0, counts[i], (double*)y, nullptr, nullptr, nullptr, nullptr});
+    }
+    auto check_outputs = [&] {
+        for (int i = 0; i < 3; ++i)
+            for (int64_t t = 0; t < counts[i]; ++t) CHECK(reqs[i].y[t] == expected_y(ds[i], 9, (uint64_t)t));
+    };
+    // solves of one plain run of the batch
+    fake_device_reset_counters();
+    CHECK(ces_sample_batch(ctx, reqs.data(), 3, nullptr) == CES_OK);
+    const long long one_run = fake_device_solves();
+    ces_schedule s1{}, s2{};
+    double ms1 = 0.0, ms2 = 0.0;
+    fake_device_reset_counters();
+    CHECK(ces_autotune(ctx, reqs.data(), 3, nullptr, &s1, &ms1) == CES_OK);
+    CHECK(fake_device_solves() > 3 * one_run);   // tuned: many runs
+    check_outputs();
+    for (auto& r : reqs) std::memset(r.y, 0, 8 * (size_t)r.count);
+    ces_schedule def{};
+    def.depth = 2;
+    CHECK(ces_schedule_set(ctx, &def) == CES_OK);
+    fake_device_reset_counters();
+    CHECK(ces_autotune(ctx, reqs.data(), 3, nullptr, &s2, &ms2) == CES_OK);
+    CHECK(fake_device_solves() == one_run);      // stored: one run
+    check_outputs();
+    CHECK(s2.depth == s1.depth && s2.max_lanes == s1.max_lanes && s2.chunk_samples == s1.chunk_samples &&
+          s2.graphs == s1.graphs);
+    CHECK(std::fabs(ms2 - ms1) <= 1e-4 + 1e-6 * ms1);
+    ces_schedule now{};
+    CHECK(ces_schedule_get(ctx, &now) == CES_OK && now.depth == s1.depth && now.chunk_samples == s1.chunk_samples);
+    // another batch (other counts) is not served from the stored choice
+    reqs[0].count = 200;
+    fake_device_reset_counters();
+    CHECK(ces_autotune(ctx, reqs.data(), 3, nullptr, &s2, &ms2) == CES_OK);
+    CHECK(fake_device_solves() > 3 * one_run);
+    FILE* f = std::fopen(path, "r");
+    CHECK(f != nullptr);
+    int lines = 0;
+    char buf[256];
+    while (std::fgets(buf, sizeof(buf), f)) ++lines;
+    std::fclose(f);
+    CHECK(lines == 2);
+    std::remove(path);
+    unsetenv("CESMLMC_AUTOTUNE_CACHE");
+    for (auto& r : reqs) CHECK(hipFree(r.y) == hipSuccess);
     for (ces_plan p : plans) ces_plan_destroy(p);
     CHECK(fake_hip_live_bytes() == 0);
     delete ctx;
@@ -437,6 +512,7 @@ int main(int argc, char** argv) {
         std::_Exit(3);
     }).detach();
     if (sc == "batch") scenario_batch();
+    else if (sc == "autotune_cache") scenario_autotune_cache();
     else if (sc == "serve_mix") scenario_serve_mix();
     else if (sc == "admission") scenario_admission();
     else if (sc == "continuous") scenario_continuous();

@@ -4,7 +4,8 @@ Bars (stated per test): normals bit-exact; eigenvalues to 1e-12 of the
 largest; masks equal up to ties within 1e-12; FP64 fields to 1e-11 of
 max|Z|; mixed fields to 1e-5 of max|Z|; FP64 QoI to 1e-9 relative; mixed
 QoI to 1e-6 relative (field rounding to float dominates; CG runs to
-||r|| <= 1e-10 ||r0|| in double on both paths).
+||r|| <= 1e-10 ||r0|| in double on both paths); the Y of a pair level also
+to 1e-9 (FP64) / 2e-6 (mixed) of max|Y|, floored at 1% of max|Q_f|.
 """
 
 import numpy as np
@@ -204,6 +205,11 @@ def test_level_samples(ctx, ces, name, prec, tol):
     scale = np.abs(ref[:, 1]).max()
     assert np.max(np.abs(yf - ref[:, 1])) <= tol * scale
     assert np.max(np.abs(y - ref[:, 0])) <= tol * scale
+    if w.get("level") == "pair":
+        # Y = Q_f - Q_c on its own scale, floored at 1% of the QoI scale
+        ybar = 2e-6 if prec == "mixed" else 1e-9
+        yscale = max(np.abs(ref[:, 0]).max(), 1e-2 * scale)
+        assert np.max(np.abs(y - ref[:, 0])) <= ybar * yscale
 
 
 def test_batch_independence(ctx, ces):

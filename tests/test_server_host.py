@@ -21,7 +21,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_2306_13493_amd", "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in ("exec.cpp", "server.cpp", "desc.cpp")] + [
     os.path.join(HERE, "host", f) for f in ("fake_hip.cpp", "fake_device.cpp", "server_sim.cpp")]
-SCENARIOS = ["batch", "serve_mix", "admission", "continuous", "overload", "isolation", "loop_error",
+SCENARIOS = ["batch", "autotune_cache", "serve_mix", "admission", "continuous", "overload", "isolation", "loop_error",
              "destroy_pending"]
 
 
