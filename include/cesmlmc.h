@@ -326,6 +326,22 @@ void ces_mlmc_opts_default(ces_mlmc_opts* o);
 int ces_mlmc_run(ces_context ctx, const ces_plan* levels, const ces_plan* finest, int32_t nlevels,
                  const ces_mlmc_opts* opts, void* hip_stream, ces_mlmc_result* out);
 
+/* ces_mlmc_run with a checkpoint (host file `path`, may be NULL): the run's
+ * state after every round -- the level in use, per level the sample count,
+ * Welford mean and sum of squared deviations, planned count, next sample
+ * index and cost, the fitted rates and the stop flags -- is written as JSON
+ * (17 significant digits, written to path.tmp and renamed).  If `path`
+ * exists when the call starts, the run continues from it; a file written
+ * for other options or plans is refused (CES_ERR_ARG).  max_new_rounds > 0
+ * stops the call after that many rounds of its own (0: no limit), leaving
+ * the state in the file.  Since every level sample is a pure function of
+ * (plan, seed, index), a run resumed any number of times gives results bit
+ * for bit those of an uninterrupted one (with cost_model 0: measured costs
+ * are the resumed calls' own). */
+int ces_mlmc_run_checkpointed(ces_context ctx, const ces_plan* levels, const ces_plan* finest, int32_t nlevels,
+                              const ces_mlmc_opts* opts, const char* path, int32_t max_new_rounds,
+                              void* hip_stream, ces_mlmc_result* out);
+
 /* Coarsest mesh rule of Section 3.5, eq. (mlmc-h0-bound-matern-covariance)
  * and eq. (mlmc-h0-bound-exp-covariance): the largest h_0 = 2^-k with
  * h_0 <= sqrt(8 nu) lambda (Matern) or h_0 <= lambda (separable

@@ -349,9 +349,12 @@ class Server:
 
 
 def mlmc_run(ctx, levels, finest=None, eps=1e-3, l_start=2, n_pilot=100, theta=0.5, alpha=0.0, cost_model=0,
-             max_rounds=50, seed=0, stream=None):
+             max_rounds=50, seed=0, stream=None, checkpoint=None, max_new_rounds=0):
     """ces_mlmc_run: adaptive MLMC over the given level plans (level 0
-    single, levels >= 1 pairs); returns a dict of the result fields."""
+    single, levels >= 1 pairs); returns a dict of the result fields.  With
+    `checkpoint` (a file path) ces_mlmc_run_checkpointed: the state is saved
+    after every round and a run found there is continued; max_new_rounds > 0
+    stops after that many rounds of this call."""
     lib = load()
     o = MlmcOpts()
     lib.ces_mlmc_opts_default(ctypes.byref(o))
@@ -361,7 +364,11 @@ def mlmc_run(ctx, levels, finest=None, eps=1e-3, l_start=2, n_pilot=100, theta=0
     lv = (ctypes.c_void_p * n)(*[p.handle.value for p in levels])
     fv = None if finest is None else (ctypes.c_void_p * n)(*[p.handle.value for p in finest])
     r = MlmcResult()
-    check(lib.ces_mlmc_run(ctx.handle, lv, fv, n, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(r)))
+    if checkpoint is None:
+        check(lib.ces_mlmc_run(ctx.handle, lv, fv, n, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(r)))
+    else:
+        check(lib.ces_mlmc_run_checkpointed(ctx.handle, lv, fv, n, ctypes.byref(o), str(checkpoint).encode(),
+                                            int(max_new_rounds), _stream_ptr(stream), ctypes.byref(r)))
     L = r.levels
     return {"estimate": r.estimate, "variance": r.variance, "bias": r.bias, "alpha": r.alpha, "beta": r.beta,
             "gamma": r.gamma, "levels": L, "converged": bool(r.converged), "rounds": r.rounds,

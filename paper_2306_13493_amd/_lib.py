@@ -118,6 +118,9 @@ SIGNATURES = {
     "ces_mlmc_opts_default": (None, [ctypes.POINTER(MlmcOpts)]),
     "ces_mlmc_run": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int32,
                                ctypes.POINTER(MlmcOpts), c_void_p, ctypes.POINTER(MlmcResult)]),
+    "ces_mlmc_run_checkpointed": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int32,
+                                            ctypes.POINTER(MlmcOpts), ctypes.c_char_p, c_int32, c_void_p,
+                                            ctypes.POINTER(MlmcResult)]),
     "ces_mlmc_coarsest_mesh": (c_int32, [ctypes.POINTER(LevelDesc), ctypes.POINTER(c_int32)]),
     "ces_tau_rule": (c_int32, [c_int32, c_double, c_int32, c_int32, c_double, c_double, ctypes.POINTER(c_int64),
                                ctypes.POINTER(c_double)]),

@@ -826,7 +826,6 @@ struct SmallArgs {
 };
 
 constexpr int kSmallMax = 32;   // largest mesh solved by one workgroup
-constexpr int kSmallNpt = 3;    // nodes per thread (256 x 3 >= 17^2, 512 x 3 >= 33^2)
 
 template <typename T>
 size_t small_lds_bytes(int m) {
@@ -834,9 +833,10 @@ size_t small_lds_bytes(int m) {
     return 3 * n0 * sizeof(double) + (5 * (size_t)lds_mg_nodes(m) + n0) * sizeof(T);
 }
 
-template <typename T, int NT>
+// NT threads for meshes with m <= MB: thread t owns nodes t, t + NT, ...
+template <typename T, int NT, int MB>
 __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
-    static_assert(NT * kSmallNpt >= 17 * 17 && (NT < 512 || NT * kSmallNpt >= 33 * 33), "nodes per thread");
+    constexpr int kSmallNpt = ((MB + 1) * (MB + 1) + NT - 1) / NT;   // nodes per thread
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[2 * (NT / 64)];
     __shared__ int off[8];
@@ -1507,8 +1507,8 @@ public:
         for (auto& ev : ev_)
             if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess && small_) {
-            e = cfg_.m > 16 ? allow_lds(k_small_pcg<T, small_threads(32)>, small_lds_bytes<T>(cfg_.m))
-                            : allow_lds(k_small_pcg<T, small_threads(16)>, small_lds_bytes<T>(cfg_.m));
+            e = cfg_.m > 16 ? allow_lds(k_small_pcg<T, small_threads(32), 32>, small_lds_bytes<T>(cfg_.m))
+                            : allow_lds(k_small_pcg<T, small_threads(16), 16>, small_lds_bytes<T>(cfg_.m));
         }
         if (e != hipSuccess) {
             *err = std::string("solver set-up failed: ") + hipGetErrorString(e);
@@ -1549,9 +1549,9 @@ public:
             const size_t lds = small_lds_bytes<T>(cfg_.m);
             launch("small_pcg", nv(0) * (sT + 8.0), S, -1, st, [&](const Profiler::Slot& ps) {
                 if (cfg_.m > 16)
-                    PLAUNCH((k_small_pcg<T, small_threads(32)>), dim3(S), dim3(small_threads(32)), lds, st, a);
+                    PLAUNCH((k_small_pcg<T, small_threads(32), 32>), dim3(S), dim3(small_threads(32)), lds, st, a);
                 else
-                    PLAUNCH((k_small_pcg<T, small_threads(16)>), dim3(S), dim3(small_threads(16)), lds, st, a);
+                    PLAUNCH((k_small_pcg<T, small_threads(16), 16>), dim3(S), dim3(small_threads(16)), lds, st, a);
             });
             done_ = true;
             return hipGetLastError();

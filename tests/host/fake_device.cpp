@@ -5,11 +5,12 @@
 // GPU.
 //
 // Field: sample i of a plan with seed s, level tag t and mesh m writes
-//   fine   k = 3 (i mod 100000) + (s mod 7) + 11 t + m
-//   coarse k =   (i mod 100000) + m / 2
+//   fine   k = 3 (i mod P) + (s mod 7) + 11 t + m
+//   coarse k =   (i mod P) + m / 2
+// (P = 100000, or 16 for seeds of at least 10^6: bounded sample variances)
 // into the first value of its coefficient slot; the solver returns that
-// value as the QoI.  So Y = 2 (i mod 100000) + (s mod 7) + 11 t + m/2 for a
-// pair level and 3 (i mod 100000) + (s mod 7) + 11 t + m for a single one,
+// value as the QoI.  So Y = 2 (i mod P) + (s mod 7) + 11 t + m/2 for a
+// pair level and 3 (i mod P) + (s mod 7) + 11 t + m for a single one,
 // all exact in float.
 //
 // A solve of mesh m takes 2 + m/8 iterations (one per advance call), each
@@ -87,7 +88,7 @@ hipError_t launch_field(const FieldBatch<T>& b, hipStream_t) {
         for (int c = 0; c < (pair ? 2 : 1); ++c) {
             const uint64_t i = pair ? 2 * (b.q0 + u) + c : b.q0 + u;
             const int slot = pair ? 2 * u + c : u;
-            const double im = (double)(i % 100000);
+            const double im = (double)(i % (b.seed >= 1000000 ? 16 : 100000));
             if (b.n_src > 0) {
                 // coarse field of an EMBED pair, written as that plan's
                 // fine field (b.m is the coarse mesh here)

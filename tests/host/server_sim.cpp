@@ -48,7 +48,7 @@ using Clock = std::chrono::steady_clock;
 
 // Y of sample i under the stand-in device layer (see fake_device.cpp)
 double expected_y(const ces_level_desc& d, uint64_t seed, uint64_t i) {
-    const double im = (double)(i % 100000);
+    const double im = (double)(i % (seed >= 1000000 ? 16 : 100000));
     const double fine = 3.0 * im + (double)(seed % 7) + 11.0 * d.stream + d.m_fine;
     return d.level_kind == CES_LEVEL_PAIR ? fine - (im + d.m_fine / 2) : fine;
 }
@@ -241,6 +241,52 @@ void scenario_autotune_cache() {
     std::remove(path);
     unsetenv("CESMLMC_AUTOTUNE_CACHE");
     for (auto& r : reqs) CHECK(hipFree(r.y) == hipSuccess);
+    for (ces_plan p : plans) ces_plan_destroy(p);
+    CHECK(fake_hip_live_bytes() == 0);
+    delete ctx;
+}
+
+// ces_mlmc_run_checkpointed: a run stopped after every round and resumed
+// from its checkpoint file gives the uninterrupted run's result bit for bit;
+// a checkpoint of other options is refused.
+void scenario_mlmc_checkpoint() {
+    ces_context ctx = make_ctx((size_t)8 << 30);
+    std::vector<ces_plan> plans;
+    for (int l = 0; l < 4; ++l) {
+        ces_level_desc d = desc(16 << l, l > 0, CES_PREC_MIXED, CES_FIELD_PAIR, (uint32_t)l);
+        ces_plan p = nullptr;
+        CHECK(ces::plan_create(ctx, &d, ces::default_allocator(), nullptr, &p) == CES_OK);
+        plans.push_back(p);
+    }
+    ces_mlmc_opts o;
+    ces_mlmc_opts_default(&o);
+    o.eps = 2.0;
+    o.l_start = 1;
+    o.n_pilot = 6;
+    o.max_rounds = 12;
+    o.seed = 1000003;   // bounded level variances (fake_device.cpp)
+    ces_mlmc_result a{}, b{};
+    CHECK(ces_mlmc_run(ctx, plans.data(), nullptr, 4, &o, nullptr, &a) == CES_OK);
+    CHECK(a.rounds >= 3);
+    char path[64];
+    std::snprintf(path, sizeof(path), "/tmp/ces_mlmc_ckpt_%d.json", (int)getpid());
+    std::remove(path);
+    int calls = 0, last = -1;
+    for (;;) {
+        std::memset(&b, 0, sizeof(b));
+        CHECK(ces_mlmc_run_checkpointed(ctx, plans.data(), nullptr, 4, &o, path, 1, nullptr, &b) == CES_OK);
+        ++calls;
+        if (b.rounds == last) break;   // nothing left to do
+        last = b.rounds;
+        CHECK(calls < 100);
+    }
+    CHECK(calls == a.rounds + 1);
+    CHECK(std::memcmp(&a, &b, sizeof(a)) == 0);
+    // the finished checkpoint of other options (another seed) is refused
+    ces_mlmc_opts o2 = o;
+    o2.seed = 1000004;
+    CHECK(ces_mlmc_run_checkpointed(ctx, plans.data(), nullptr, 4, &o2, path, 0, nullptr, &b) == CES_ERR_ARG);
+    std::remove(path);
     for (ces_plan p : plans) ces_plan_destroy(p);
     CHECK(fake_hip_live_bytes() == 0);
     delete ctx;
@@ -513,6 +559,7 @@ int main(int argc, char** argv) {
     }).detach();
     if (sc == "batch") scenario_batch();
     else if (sc == "autotune_cache") scenario_autotune_cache();
+    else if (sc == "mlmc_checkpoint") scenario_mlmc_checkpoint();
     else if (sc == "serve_mix") scenario_serve_mix();
     else if (sc == "admission") scenario_admission();
     else if (sc == "continuous") scenario_continuous();

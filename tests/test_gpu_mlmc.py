@@ -111,3 +111,31 @@ def test_estimator_refuses_levels_sharing_a_tag(ctx, ces):
     finest[2] = ctx.plan(ces.level_desc(**dict(fdescs[2], stream=1)))
     with pytest.raises(ces.CesError, match="level tag"):
         ces.mlmc_run(ctx, plans, finest=finest, eps=5e-2, max_rounds=2)
+
+
+def test_checkpointed_run_resumes_bit_for_bit(ctx, ces, tmp_path):
+    # the state saved after every round; a run stopped after each round and
+    # resumed from the file gives the uninterrupted result exactly
+    descs = [level_desc(l, 8, True) for l in range(4)]
+    fdescs = [level_desc(l, 8, True, finest=True) for l in range(4)]
+    plans = [ctx.plan(ces.level_desc(**d)) for d in descs]
+    fplans = [ctx.plan(ces.level_desc(**d)) for d in fdescs]
+    opts = dict(eps=2e-3, l_start=1, n_pilot=40, theta=0.5, max_rounds=20, seed=11)
+    a = ces.mlmc_run(ctx, plans, finest=fplans, **opts)
+    path = tmp_path / "mlmc.json"
+    calls, last = 0, -1
+    while True:
+        b = ces.mlmc_run(ctx, plans, finest=fplans, checkpoint=path, max_new_rounds=1, **opts)
+        calls += 1
+        if b["rounds"] == last:
+            break
+        last = b["rounds"]
+        assert calls < 50
+    assert calls == a["rounds"] + 1 and a["rounds"] >= 2
+    assert b == a
+    import json
+    state = json.loads(path.read_text())
+    assert state["done"] == 1 and state["rounds"] == a["rounds"]
+    assert [lv["n"] for lv in state["levels"][:a["levels"]]] == a["n"]
+    with pytest.raises(ces.CesError, match="another run"):
+        ces.mlmc_run(ctx, plans, finest=fplans, checkpoint=path, **dict(opts, seed=12))

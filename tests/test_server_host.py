@@ -1,6 +1,6 @@
 """The serving loop and the batch scheduler on the host, under ASan and UBSan.
 
-The library's `server.cpp`, `exec.cpp` and `desc.cpp` are compiled unchanged
+The library's `server.cpp`, `exec.cpp`, `desc.cpp` and `mlmc.cpp` are compiled unchanged
 for the host only (no device code) and linked against stand-ins for the
 device layer (`tests/host/fake_device.cpp`: known per-sample results, solves
 of known length, injected device errors) and for the HIP runtime
@@ -19,9 +19,9 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_2306_13493_amd", "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("exec.cpp", "server.cpp", "desc.cpp")] + [
+SOURCES = [os.path.join(CSRC, f) for f in ("exec.cpp", "server.cpp", "desc.cpp", "mlmc.cpp")] + [
     os.path.join(HERE, "host", f) for f in ("fake_hip.cpp", "fake_device.cpp", "server_sim.cpp")]
-SCENARIOS = ["batch", "autotune_cache", "serve_mix", "admission", "continuous", "overload", "isolation", "loop_error",
+SCENARIOS = ["batch", "autotune_cache", "mlmc_checkpoint", "serve_mix", "admission", "continuous", "overload", "isolation", "loop_error",
              "destroy_pending"]
 
 
