@@ -82,31 +82,19 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
     }
 }
 
-// Orders the LDS accesses of one wave (its lanes' writes before its later
-// reads): enough between stages when a wave works on lines of its own.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // One Stockham stage over `lines` lines of length n in buf, line l at
 // buf + l * ld (ld >= n; a padded stride spreads lines over the LDS banks).
-// MB = maximum butterflies per thread (compile time, registers).  WAVE:
-// the calling wave owns these lines alone (its 64 lanes do the stage and
-// synchronise among themselves); otherwise the whole workgroup does.
-template <typename T, int R, int MB, bool WAVE>
+// MB = maximum butterflies per thread (compile time, registers).
+template <typename T, int R, int MB>
 __device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int ld, int lines, int Ns,
                                           const cplx<T>* __restrict__ tw) {
     const int NR = n / R;
     const int total = NR * lines;
     const int stride = n / (Ns * R);
-    const int t0 = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
-    const int nt = WAVE ? 64 : (int)blockDim.x;
     cplx<T> v[MB][R];
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
-        const int g = t0 + b * nt;
+        const int g = threadIdx.x + b * (int)blockDim.x;
         if (g < total) {
             const int line = g / NR;
             const int j = g - line * NR;
@@ -115,11 +103,10 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int ld, int lines
             for (int r = 0; r < R; ++r) v[b][r] = x[j + r * NR];
         }
     }
-    if constexpr (WAVE) wave_lds_sync();
-    else __syncthreads();
+    __syncthreads();
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
-        const int g = t0 + b * nt;
+        const int g = threadIdx.x + b * (int)blockDim.x;
         if (g < total) {
             const int line = g / NR;
             const int j = g - line * NR;
@@ -134,27 +121,24 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int ld, int lines
             for (int r = 0; r < R; ++r) y[r * Ns] = v[b][r];
         }
     }
-    if constexpr (WAVE) wave_lds_sync();
-    else __syncthreads();
+    __syncthreads();
 }
 
 // In-place DFT of `lines` lines of length fp.n in LDS, line l at buf + l * ld.
-// E bounds the complex values per thread: lines * n <= E * (threads taking
-// part: the workgroup, or the wave with WAVE).  With WAVE each wave calls
-// this for lines of its own and no workgroup barrier is taken.
-template <typename T, int E, bool WAVE = false>
+// E bounds the complex values per thread: lines * n <= E * blockDim.x.
+template <typename T, int E>
 __device__ void fft_lines(cplx<T>* buf, int lines, int ld, const FftPlan& fp, const cplx<T>* __restrict__ tw) {
     int Ns = 1;
     for (int s = 0; s < fp.nst; ++s) {
         const int R = fp.rad[s];
         if (R == 8)
-            fft_stage<T, 8, (E + 7) / 8, WAVE>(buf, fp.n, ld, lines, Ns, tw);
+            fft_stage<T, 8, (E + 7) / 8>(buf, fp.n, ld, lines, Ns, tw);
         else if (R == 4)
-            fft_stage<T, 4, (E + 3) / 4, WAVE>(buf, fp.n, ld, lines, Ns, tw);
+            fft_stage<T, 4, (E + 3) / 4>(buf, fp.n, ld, lines, Ns, tw);
         else if (R == 2)
-            fft_stage<T, 2, (E + 1) / 2, WAVE>(buf, fp.n, ld, lines, Ns, tw);
+            fft_stage<T, 2, (E + 1) / 2>(buf, fp.n, ld, lines, Ns, tw);
         else
-            fft_stage<T, 3, (E + 2) / 3, WAVE>(buf, fp.n, ld, lines, Ns, tw);
+            fft_stage<T, 3, (E + 2) / 3>(buf, fp.n, ld, lines, Ns, tw);
         Ns *= R;
     }
 }

@@ -62,9 +62,7 @@ __device__ __forceinline__ double lattice_normal(uint64_t seed, uint32_t stream,
     return normcdfinv(u);
 }
 
-// WAVE (L a multiple of the workgroup's 4 waves): each wave transforms
-// NF * L / 4 of the lines with wave-level synchronisation only.
-template <typename T, int E, int MODE, int NF, bool WAVE>
+template <typename T, int E, int MODE, int NF>
 __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -106,13 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
         }
     }
     __syncthreads();
-    if constexpr (WAVE) {
-        const int lpw = NF * L / (kBlock / 64);
-        fft_lines<T, E, true>(buf + (threadIdx.x >> 6) * lpw * ld, lpw, ld, b.fp, b.tw);
-        __syncthreads();
-    } else {
-        fft_lines<T, E>(buf, NF * L, ld, b.fp, b.tw);
-    }
+    fft_lines<T, E>(buf, NF * L, ld, b.fp, b.tw);
     const int mp1 = b.m + 1;
     for (int t = threadIdx.x; t < NF * mp1 * L; t += blockDim.x) {
         const int line = t % L;
@@ -123,9 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
     }
 }
 
-// WAVE (L a multiple of the workgroup's 4 waves): each wave loads,
-// transforms and writes L / 4 rows of its own, with no workgroup barrier.
-template <typename T, int E, int MODE, int NF, bool ZOUT, bool WAVE>
+template <typename T, int E, int MODE, int NF, bool ZOUT>
 __global__ __launch_bounds__(kBlock) void k_field_x(FieldBatch<T> b, int L) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -135,32 +125,20 @@ __global__ __launch_bounds__(kBlock) void k_field_x(FieldBatch<T> b, int L) {
     const int u = blockIdx.y;
     const int f = blockIdx.z;
     const int lines = min(L, mp1 - p2_0);
-    // rows [l0, l0 + nl) of this workgroup's rows go to this wave (all of
-    // them without WAVE); t0, nt: its first thread and thread count
-    const int lpw = WAVE ? L / (kBlock / 64) : L;
-    const int l0 = WAVE ? (int)(threadIdx.x >> 6) * lpw : 0;
-    const int nl = WAVE ? max(0, min(lpw, lines - l0)) : lines;
-    const int t0 = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
-    const int nt = WAVE ? 64 : (int)blockDim.x;
-    const cplx<T>* src = b.work + ((size_t)(f * b.units + u) * mp1 + p2_0 + l0) * n;
-    for (int t = t0; t < nl * n; t += nt) {
+    const cplx<T>* src = b.work + ((size_t)(f * b.units + u) * mp1 + p2_0) * n;
+    for (int t = threadIdx.x; t < lines * n; t += blockDim.x) {
         const int l = t / n;
-        buf[(l0 + l) * ld + (t - l * n)] = src[t];
+        buf[l * ld + (t - l * n)] = src[t];
     }
-    if constexpr (WAVE) {
-        wave_lds_sync();
-        if (nl > 0) fft_lines<T, E, true>(buf + l0 * ld, nl, ld, b.fp, b.tw);
-    } else {
-        __syncthreads();
-        fft_lines<T, E>(buf, lines, ld, b.fp, b.tw);
-    }
+    __syncthreads();
+    fft_lines<T, E>(buf, lines, ld, b.fp, b.tw);
     const bool fine = (f == 0);
     const bool coarse = b.coarse && (f == NF - 1);
     const int mcp1 = b.m / 2 + 1;
     // adjacent threads write adjacent p1 of one mesh row p2
-    for (int t = t0; t < nl * mp1; t += nt) {
-        const int l = l0 + t / mp1;
-        const int p1 = t - (l - l0) * mp1;
+    for (int t = threadIdx.x; t < lines * mp1; t += blockDim.x) {
+        const int l = t / mp1;
+        const int p1 = t - l * mp1;
         const int p2 = p2_0 + l;
         const cplx<T> v = buf[l * ld + p1];
         const bool even = ((p1 | p2) & 1) == 0;
@@ -268,8 +246,7 @@ template <typename T, int E, int MODE, int NF>
 hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2) {
     const size_t lds1 = (size_t)NF * L1 * (b.n + 1) * sizeof(cplx<T>);
     const size_t lds2 = (size_t)L2 * (b.n + 1) * sizeof(cplx<T>);
-    constexpr int NW = kBlock / 64;
-    auto kr = (NF * L1) % NW == 0 ? k_field_y<T, E, MODE, NF, true> : k_field_y<T, E, MODE, NF, false>;
+    auto kr = k_field_y<T, E, MODE, NF>;
     hipError_t e = allow_lds(kr, lds1);
     if (e != hipSuccess) return e;
     // algorithmic bytes: amplitudes once, the pruned intermediate written
@@ -286,13 +263,12 @@ hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2
     if ((e = hipGetLastError()) != hipSuccess) return e;
     dim3 g2(cdiv(b.m + 1, L2), b.units, NF);
     ps = P.begin();
-    const bool wave2 = L2 % NW == 0;
     if (b.zf) {
-        auto kc = wave2 ? k_field_x<T, E, MODE, NF, true, true> : k_field_x<T, E, MODE, NF, true, false>;
+        auto kc = k_field_x<T, E, MODE, NF, true>;
         if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
         hipExtLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, ps.a, ps.b, 0, b, L2);
     } else {
-        auto kc = wave2 ? k_field_x<T, E, MODE, NF, false, true> : k_field_x<T, E, MODE, NF, false, false>;
+        auto kc = k_field_x<T, E, MODE, NF, false>;
         if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;
         hipExtLaunchKernelGGL(kc, g2, dim3(kBlock), lds2, st, ps.a, ps.b, 0, b, L2);
     }
