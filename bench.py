@@ -36,7 +36,8 @@ KERNEL_SYMBOL = {
     "pcg_dir": "k_pcg_dir<float>",
     "pcg_update": "k_pcg_update<false>",
     "pcg_init": "k_pcg_init<float>",
-    "small_pcg": "k_small_pcg<float, 256, 16>",
+    "small_pcg": "k_small_pcg<float, 512, 32>",
+    "small_direct": "k_small_direct<float>",
     "field_y": "k_field_y<float, 16, 0, 1>",
     "field_x": "k_field_x<float, 16, 0, 1, false>",
     "qoi": "k_qoi<float>",

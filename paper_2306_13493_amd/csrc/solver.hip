@@ -1005,6 +1005,125 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
     }
 }
 
+// ------------------------------------------- direct solve of a tiny mesh
+// Meshes with m <= kDirectMax: one wave per sample factorises the band of
+// the 5-point operator (unknowns numbered x fastest, half-bandwidth
+// bw = m - 1) as L D L^T in double, with the right-hand side eliminated
+// along, then back-substitutes.  The operator is the PCG path's: double
+// conductances from the nodal k, Dirichlet lifting x0, and x = x0 + A^-1
+// (b - A x0).  The band is held in LDS, row i at Bd[i * m] (m = bw + 1, a
+// power of two); elimination is right-looking and in place, so after step
+// j row j holds D(j) and the multipliers' numerators W(j, j + t), which
+// the back substitution reuses.  Exact up to rounding: the solve reports
+// one iteration and never the iteration cap.
+constexpr int kDirectMax = 16;
+
+__host__ __device__ constexpr int direct_unknowns(int m, int bc) {
+    return (m - 1) * (bc == BC_FLOWCELL ? m + 1 : m - 1);
+}
+
+template <typename T>
+size_t direct_lds_bytes(int m, int bc) {
+    const size_t N = (size_t)direct_unknowns(m, bc);
+    const size_t n0 = (size_t)(m + 1) * (m + 1);
+    return (N * (size_t)m + N) * sizeof(double) + ((n0 * sizeof(T) + 7) / 8) * 8;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_small_direct(SmallArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int s = blockIdx.x, lane = threadIdx.x;
+    const int m = a.m, w = m + 1, n0 = w * w, bc = a.bc;
+    const int ylo = bc == BC_FLOWCELL ? 0 : 1, yhi = bc == BC_FLOWCELL ? m : m - 1;
+    const int bw = m - 1, N = bw * (yhi - ylo + 1);
+    double* Bd = reinterpret_cast<double*>(smem);    // band, Bd[i * m + d] = W(i, i + d)
+    double* rv = Bd + (size_t)N * m;                 // b - A x0, then the solution update
+    T* kk = reinterpret_cast<T*>(rv + N);            // nodal k
+    const T* kg = a.k + (size_t)s * a.kss;
+    for (int t = lane; t < n0; t += 64) kk[t] = kg[t];
+    __syncthreads();
+    // band rows (unknown i <-> node (1 + i mod bw, ylo + i / bw)) and the
+    // right-hand side r0 = b - A x0 (x0: the Dirichlet lifting)
+    {
+        auto KD = [&](int gx, int gy) -> double { return (double)kk[gy * w + gx]; };
+        for (int i = lane; i < N; i += 64) {
+            const int yr = ylo + i / bw, xr = 1 + i % bw;
+            const double ce = cond_e<double>(xr, yr, m, KD), cw = cond_e<double>(xr - 1, yr, m, KD);
+            const double cn = cond_n<double>(xr, yr, m, KD), cs = cond_n<double>(xr, yr - 1, m, KD);
+            double* row = Bd + (size_t)i * m;
+            double d = ce + cw;
+            if (yr < m) d += cn;
+            if (yr > 0) d += cs;
+            row[0] = d;
+            for (int dd = 1; dd < m; ++dd) row[dd] = 0.0;
+            if (xr + 1 <= m - 1) row[1] = -ce;
+            if (i + bw < N) row[bw] -= cn;
+            double v = a.f * (double)tri_count(xr, yr, m) * a.h2 * (1.0 / 6.0);
+            if (xr == 1) v += cw * dirichlet_value(0, bc);
+            if (xr == m - 1) v += ce * dirichlet_value(m, bc);
+            if (bc != BC_FLOWCELL) {
+                if (yr == 1) v += cs * dirichlet_value(xr, bc);
+                if (yr == m - 1) v += cn * dirichlet_value(xr, bc);
+            }
+            rv[i] = v;
+        }
+    }
+    __syncthreads();
+    // this lane's entries (a, b), 1 <= a <= b <= bw, of the trailing update:
+    // pair q = lane + 64 i, the b-th row of the triangle holding a = 1 .. b
+    constexpr int NPL = (kDirectMax - 1) * kDirectMax / 2 / 64 + 1;
+    int pa[NPL], pb[NPL];
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+        const int q = lane + 64 * i;
+        int b = 1;
+        while (b * (b + 1) / 2 <= q) ++b;
+        pb[i] = q < bw * (bw + 1) / 2 ? b : 0;
+        pa[i] = q - (b - 1) * b / 2 + 1;
+    }
+    for (int j = 0; j < N; ++j) {
+        const double* rj = Bd + (size_t)j * m;
+        const double inv = 1.0 / rj[0];
+        // W(j+a, j+b) -= W(j, j+a) W(j, j+b) / D(j)
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int aa = pa[i], b = pb[i];
+            if (b == 0 || j + b >= N) continue;
+            Bd[(size_t)(j + aa) * m + (b - aa)] -= rj[aa] * rj[b] * inv;
+        }
+        // elimination of the right-hand side by L(j + t, j) = W(j, j + t) / D(j)
+        if (lane >= 1 && lane <= bw && j + lane < N) rv[j + lane] -= rj[lane] * inv * rv[j];
+        __syncthreads();
+    }
+    // D z = y, then L^T x = z by columns from the last unknown
+    for (int i = lane; i < N; i += 64) rv[i] /= Bd[(size_t)i * m];
+    __syncthreads();
+    for (int j = N - 1; j >= 1; --j) {
+        const double xj = rv[j];
+        if (lane >= 1 && lane <= bw && j - lane >= 0) {
+            const double* ri = Bd + (size_t)(j - lane) * m;
+            rv[j - lane] -= ri[lane] / ri[0] * xj;
+        }
+        __syncthreads();
+    }
+    // x = x0 + update at every node (Dirichlet values on the boundary)
+    double* X = a.X + (size_t)s * a.xss;
+    for (int t = lane; t < n0; t += 64) {
+        const int y = t / w, x = t - y * w;
+        double v = dirichlet_value(x, bc);
+        if (is_unknown(x, y, m, bc)) v = rv[(y - ylo) * bw + (x - 1)];
+        X[t] = v;
+    }
+    if (lane == 0) {
+        Scal& sc = a.scal[s];
+        sc.bb = 0.0;
+        sc.rr = 0.0;
+        sc.it = 1;
+        sc.status = 0;
+        sc.active = 0;
+    }
+}
+
 // ----------------------------------------------------------- PCG (double)
 constexpr int PTX = 64, PTY = 16;
 
@@ -1507,8 +1626,8 @@ public:
         for (auto& ev : ev_)
             if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess && small_) {
-            e = cfg_.m > 16 ? allow_lds(k_small_pcg<T, small_threads(32), 32>, small_lds_bytes<T>(cfg_.m))
-                            : allow_lds(k_small_pcg<T, small_threads(16), 16>, small_lds_bytes<T>(cfg_.m));
+            e = cfg_.m > kDirectMax ? allow_lds(k_small_pcg<T, small_threads(32), 32>, small_lds_bytes<T>(cfg_.m))
+                                    : allow_lds(k_small_direct<T>, direct_lds_bytes<T>(cfg_.m, cfg_.bc));
         }
         if (e != hipSuccess) {
             *err = std::string("solver set-up failed: ") + hipGetErrorString(e);
@@ -1546,13 +1665,16 @@ public:
             a.kss = kss;
             a.X = ptr<double>(o_X_);
             a.scal = ptr<Scal>(o_scal_);
-            const size_t lds = small_lds_bytes<T>(cfg_.m);
-            launch("small_pcg", nv(0) * (sT + 8.0), S, -1, st, [&](const Profiler::Slot& ps) {
-                if (cfg_.m > 16)
+            if (cfg_.m <= kDirectMax) {
+                launch("small_direct", nv(0) * (sT + 8.0), S, -1, st, [&](const Profiler::Slot& ps) {
+                    PLAUNCH(k_small_direct<T>, dim3(S), dim3(64), direct_lds_bytes<T>(cfg_.m, cfg_.bc), st, a);
+                });
+            } else {
+                const size_t lds = small_lds_bytes<T>(cfg_.m);
+                launch("small_pcg", nv(0) * (sT + 8.0), S, -1, st, [&](const Profiler::Slot& ps) {
                     PLAUNCH((k_small_pcg<T, small_threads(32), 32>), dim3(S), dim3(small_threads(32)), lds, st, a);
-                else
-                    PLAUNCH((k_small_pcg<T, small_threads(16), 16>), dim3(S), dim3(small_threads(16)), lds, st, a);
-            });
+                });
+            }
             done_ = true;
             return hipGetLastError();
         }

@@ -148,7 +148,7 @@ def test_busy_plan_in_two_requests_is_serialised(ctx, c3_plans):
     assert_same(got[1], b)
 
 
-@pytest.mark.parametrize("m,level", [(8, "single"), (16, "pair"), (64, "pair")])
+@pytest.mark.parametrize("m,level", [(32, "single"), (32, "pair"), (64, "pair")])
 def test_iteration_cap_reports_nonconvergence(ctx, ces, m, level):
     # small-mesh and tiled solves agree on the status convention
     plan = ctx.plan(ces.level_desc(cov="matern", nu=0.5, lam=0.05, m=m, level=level, cg_max_iter=2))
@@ -156,3 +156,13 @@ def test_iteration_cap_reports_nonconvergence(ctx, ces, m, level):
     torch.cuda.synchronize()
     assert np.all(out["status"].cpu().numpy() == -4)
     assert np.all(out["iters"].cpu().numpy() == -2)
+
+
+@pytest.mark.parametrize("m,level", [(8, "single"), (16, "pair"), (16, "single")])
+def test_direct_solves_ignore_the_iteration_cap(ctx, ces, m, level):
+    # meshes with m <= 16 are solved directly: one "iteration", never capped
+    plan = ctx.plan(ces.level_desc(cov="matern", nu=0.5, lam=0.05, m=m, level=level, cg_max_iter=1))
+    out = plan.sample(0, 0, 6)
+    torch.cuda.synchronize()
+    assert np.all(out["status"].cpu().numpy() == 0)
+    assert np.all(out["iters"].cpu().numpy() == 1)
