@@ -38,6 +38,7 @@ KERNEL_SYMBOL = {
     "pcg_init": "k_pcg_init<float>",
     "small_pcg": "k_small_pcg<float, 512, 32>",
     "small_direct": "k_small_direct<float>",
+    "direct_lin": "k_direct_lin<float, 32, true>",
     "field_y": "k_field_y<float, 16, 0, 1>",
     "field_x": "k_field_x<float, 16, 0, 1, false>",
     "qoi": "k_qoi<float>",

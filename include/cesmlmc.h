@@ -99,8 +99,9 @@ enum { CES_COUPLE_RESTRICT = 0, CES_COUPLE_EMBED = 1 };
  * iteration: faster where a call carries many samples, slower for one
  * sample per call.  AUTO: W1 for SINGLE levels whose length scale (lambda /
  * sqrt(2 nu) for Matern, lambda for SEPEXP) spans at least 8 fine cells, V
- * otherwise.  Meshes with m = 32 solve with their own small-mesh cycle;
- * meshes with m <= 16 are solved directly (banded L D L^T in double). */
+ * otherwise.  Meshes with m <= 16, and with m <= 32 for a QoI linear in
+ * u, are solved directly (banded L D L^T in double); other meshes with
+ * m = 32 solve with their own small-mesh cycle. */
 enum { CES_CYCLE_AUTO = 0, CES_CYCLE_V = 1, CES_CYCLE_W1 = 2 };
 
 typedef struct ces_context_s* ces_context;
@@ -178,8 +179,9 @@ int ces_plan_destroy(ces_plan plan);
 /* Level samples i = first_sample .. first_sample+count-1 (Algorithm 1
  * step 4 per sample, Section 3.4 difference).  y_dev[t] = Y of sample
  * first_sample+t.  q_fine_dev, q_coarse_dev (Q_f, Q_c; Q_c = 0 for SINGLE),
- * iters_dev (CG iterations of the fine solve; meshes with m <= 16 are
- * solved directly and report 1) and status_dev (0, or CES_ERR_NOCONV if
+ * iters_dev (CG iterations of the fine solve; meshes with m <= 16, and
+ * with m <= 32 for a QoI linear in u (every QoI but L2), are solved
+ * directly and report 1) and status_dev (0, or CES_ERR_NOCONV if
  * either solve hit cg_max_iter) may be NULL.
  * Asynchronous on hip_stream; the call returns once the work is enqueued
  * except for a bounded number of convergence polls. */

@@ -823,6 +823,7 @@ struct SmallArgs {
     long long kss;
     double* X;         // nodal solution out (stride L[0].ss)
     Scal* scal;        // per-sample scalars out (it, status, bb, rr)
+    int S;             // samples in the launch
 };
 
 constexpr int kSmallMax = 32;   // largest mesh solved by one workgroup
@@ -1164,6 +1165,196 @@ __device__ __forceinline__ double qoi_weight(const QoiLin& q, int gx, int gy, in
     if (gy == q.pj) w = gx == q.pi ? q.w00 : (gx == q.pi + 1 ? q.w10 : 0.0);
     else if (gy == q.pj + 1) w = gx == q.pi + 1 ? q.w11 : (gx == q.pi ? q.w01 : 0.0);
     return w;
+}
+
+// ------------------------------- direct solve for a linear QoI, m <= 32
+// A QoI linear in u needs no x: with A = L D L^T,
+// w.(x - x0) = w^T A^-1 r0 = (L^-1 w)^T D^-1 (L^-1 r0), and L^-1 r0 and
+// L^-1 w are eliminated along with the factorisation, so nothing behind the
+// pivot is kept.  The band's active window -- rows j .. j + MB - 1 at pivot
+// j, half-bandwidth m - 1 < MB -- lives in registers: 16 lanes per sample
+// (four samples per wave), lane kap holding the columns c = kap + 16 h
+// (h < MB / 16) of every window row, with rows and columns numbered mod MB
+// (a ring: once row j is eliminated its slot takes row j + MB).  Register
+// R[h][rho] holds W(r, r + d) for the window row r = rho (mod MB) and
+// d = (c - rho) mod MB; the update of step j,
+// W(j+a, j+b) -= W(j, j+a) W(j, j+b) / D(j) for 1 <= a <= b <= m - 1, is then
+// register (h, j+a) -= [pivot entry at column j+a, broadcast] x [own pivot
+// entry W(j, j+b)] / D(j), masked to the lanes with b >= a.  A row of 16
+// lanes is one sample, so the broadcasts are DPP row broadcasts: no LDS and
+// no barriers in the elimination.  The ring is renumbered every 16 pivots
+// (for MB = 32 by swapping its halves), so every register index is a
+// compile-time constant.  Exact up to rounding: one iteration, never the cap.
+template <int L>
+__device__ __forceinline__ double row_bcast(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + L, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + L, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int I, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < E) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, E>(f);
+    }
+}
+
+constexpr int kDirectLinMax = 32;
+
+template <typename T>
+size_t direct_lin_lds_bytes(int m) {
+    return 4 * (size_t)(m + 1) * (m + 1) * sizeof(T);
+}
+
+template <typename T, int MB, bool FULL>
+__global__ __launch_bounds__(64) void k_direct_lin(SmallArgs<T> a, QoiLin ql) {
+    static_assert(MB == 16 || MB == 32, "window of 16 or 32 rows");
+    constexpr int C = MB / 16;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x, sub = lane >> 4, kap = lane & 15;
+    const int s = blockIdx.x * 4 + sub;
+    const bool live = s < a.S;
+    const int m = FULL ? MB : a.m, w = m + 1, n0 = w * w, bc = a.bc;
+    const int ylo = bc == BC_FLOWCELL ? 0 : 1, yhi = bc == BC_FLOWCELL ? m : m - 1;
+    const int bw = m - 1, N = bw > 0 ? bw * (yhi - ylo + 1) : 0;
+    T* kk = reinterpret_cast<T*>(smem) + (size_t)sub * n0;
+    {
+        const T* kg = a.k + (size_t)(live ? s : a.S - 1) * a.kss;
+        for (int t = kap; t < n0; t += 16) kk[t] = kg[t];
+    }
+    __syncthreads();
+    auto KD = [&](int gx, int gy) -> double { return (double)kk[gy * w + gx]; };
+    auto node = [&](int r, int& x, int& y) {
+        const int q = r / bw;
+        y = ylo + q;
+        x = 1 + r - q * bw;
+    };
+    // per column: diagonal, right-hand side r0 = b - A x0 and QoI weight of
+    // row J0 + c, the east entry that row J0 + (c - 1 mod MB) has in column
+    // c, and the north entry of row J0 + (c - bw mod MB)
+    double nd[C], ne[C], nn[C], ny[C], nw[C];
+    auto prep = [&](int J0) {
+#pragma unroll
+        for (int h = 0; h < C; ++h) {
+            const int c = kap + 16 * h;
+            nd[h] = 1.0;
+            ny[h] = nw[h] = ne[h] = nn[h] = 0.0;
+            int r = J0 + c, x, y;
+            if (r < N) {
+                node(r, x, y);
+                const double ce = cond_e<double>(x, y, m, KD), cw = cond_e<double>(x - 1, y, m, KD);
+                const double cn = cond_n<double>(x, y, m, KD), cs = cond_n<double>(x, y - 1, m, KD);
+                double d = ce + cw;
+                if (y < m) d += cn;
+                if (y > 0) d += cs;
+                nd[h] = d;
+                double v = a.f * (double)tri_count(x, y, m) * a.h2 * (1.0 / 6.0);
+                if (x == 1) v += cw * dirichlet_value(0, bc);
+                if (x == m - 1) v += ce * dirichlet_value(m, bc);
+                if (bc != BC_FLOWCELL) {
+                    if (y == 1) v += cs * dirichlet_value(x, bc);
+                    if (y == m - 1) v += cn * dirichlet_value(x, bc);
+                }
+                ny[h] = v;
+                nw[h] = qoi_weight(ql, x, y, m, a.h2, ce);
+            }
+            r = J0 + ((c - 1) & (MB - 1));
+            if (r < N) {
+                node(r, x, y);
+                if (x + 1 <= m - 1) ne[h] = -cond_e<double>(x, y, m, KD);
+            }
+            r = J0 + ((c - bw) & (MB - 1));
+            if (r + bw < N) {
+                node(r, x, y);
+                nn[h] = -cond_n<double>(x, y, m, KD);
+            }
+        }
+    };
+    double R[C][MB], Y[C], YW[C];
+    // ring slot RHO takes the prepared row
+    auto load_row = [&](auto rho_ic) {
+        constexpr int RHO = decltype(rho_ic)::value;
+#pragma unroll
+        for (int h = 0; h < C; ++h) {
+            int d = (kap + 16 * h - RHO) & (MB - 1);
+            asm volatile("" : "+v"(d));
+            R[h][RHO] = (d == 0 ? nd[h] : 0.0) + (d == 1 ? ne[h] : 0.0) + (d == bw ? nn[h] : 0.0);
+            if (d == 0) {
+                Y[h] = ny[h];
+                YW[h] = nw[h];
+            }
+        }
+    };
+    prep(0);
+    static_for<0, MB>(load_row);
+    double qacc = 0.0;
+    for (int J = 0; J < N; J += 16) {
+        prep(J + MB);
+        static_for<0, 16>([&](auto rj_ic) {
+            constexpr int RJ = decltype(rj_ic)::value;
+            if (J + RJ >= N) return;
+            // pivot row J + RJ: ring slot RJ, its diagonal in lane RJ of h = 0
+            const double D = row_bcast<RJ>(R[0][RJ]);
+            const double inv = 1.0 / D;
+            const double yj = row_bcast<RJ>(Y[0]), ywj = row_bcast<RJ>(YW[0]);
+            double pm[C];
+            int bp[C];
+#pragma unroll
+            for (int h = 0; h < C; ++h) {
+                bp[h] = (kap + 16 * h - RJ) & (MB - 1);   // own pivot entry is W(j, j + bp)
+                // recomputed at every pivot: hoisted out of the loop over J,
+                // the lane masks of all pivots would not fit in SGPRs
+                asm volatile("" : "+v"(bp[h]));
+                pm[h] = R[h][RJ] * inv;
+            }
+            static_for<1, MB>([&](auto a_ic) {
+                constexpr int A = decltype(a_ic)::value;
+                constexpr int CS = (RJ + A) & (MB - 1);
+                if (!FULL && A > bw) return;
+                const double u = row_bcast<CS & 15>(R[CS >> 4][RJ]);   // W(j, j + A)
+#pragma unroll
+                for (int h = 0; h < C; ++h) {
+                    const double t = fma(-u, pm[h], R[h][CS]);
+                    R[h][CS] = A <= bp[h] ? t : R[h][CS];
+                }
+            });
+#pragma unroll
+            for (int h = 0; h < C; ++h) {
+                if (bp[h] != 0) {
+                    Y[h] = fma(-pm[h], yj, Y[h]);
+                    YW[h] = fma(-pm[h], ywj, YW[h]);
+                }
+            }
+            qacc = fma(yj * ywj, inv, qacc);
+            load_row(rj_ic);
+        });
+        if constexpr (MB == 32) {
+            static_for<0, 16>([&](auto r_ic) {
+                constexpr int r = decltype(r_ic)::value;
+                const double t0 = R[0][r];
+                R[0][r] = R[1][r + 16];
+                R[1][r + 16] = t0;
+                const double t1 = R[0][r + 16];
+                R[0][r + 16] = R[1][r];
+                R[1][r] = t1;
+            });
+            const double ty = Y[0], tw = YW[0];
+            Y[0] = Y[1];
+            Y[1] = ty;
+            YW[0] = YW[1];
+            YW[1] = tw;
+        }
+    }
+    if (live && kap == 0) {
+        Scal& sc = a.scal[s];
+        sc.bb = 0.0;
+        sc.rr = 0.0;
+        sc.qacc = qacc;
+        sc.it = 1;
+        sc.status = 0;
+        sc.active = 0;
+    }
 }
 
 template <typename T>
@@ -1643,7 +1834,7 @@ public:
 
     hipError_t begin(const void* kv, long long kss, int S, hipStream_t st, bool keep_x) override {
         k0_ = reinterpret_cast<const T*>(kv);
-        lin_ = !small_ && !keep_x && cfg_.qoi != Q_L2;
+        lin_ = !keep_x && cfg_.qoi != Q_L2;
         kss_ = kss;
         S_ = S;
         it_next_ = confirmed_ = 0;
@@ -1665,7 +1856,22 @@ public:
             a.kss = kss;
             a.X = ptr<double>(o_X_);
             a.scal = ptr<Scal>(o_scal_);
-            if (cfg_.m <= kDirectMax) {
+            a.S = S;
+            if (lin_) {
+                const QoiLin ql = qoi_lin();
+                const dim3 g((unsigned)cdiv(S, 4));
+                const size_t lds = direct_lin_lds_bytes<T>(cfg_.m);
+                launch("direct_lin", nv(0) * sT, S, -1, st, [&](const Profiler::Slot& ps) {
+                    if (cfg_.m == 16)
+                        PLAUNCH((k_direct_lin<T, 16, true>), g, dim3(64), lds, st, a, ql);
+                    else if (cfg_.m < 16)
+                        PLAUNCH((k_direct_lin<T, 16, false>), g, dim3(64), lds, st, a, ql);
+                    else if (cfg_.m == 32)
+                        PLAUNCH((k_direct_lin<T, 32, true>), g, dim3(64), lds, st, a, ql);
+                    else
+                        PLAUNCH((k_direct_lin<T, 32, false>), g, dim3(64), lds, st, a, ql);
+                });
+            } else if (cfg_.m <= kDirectMax) {
                 launch("small_direct", nv(0) * (sT + 8.0), S, -1, st, [&](const Profiler::Slot& ps) {
                     PLAUNCH(k_small_direct<T>, dim3(S), dim3(64), direct_lds_bytes<T>(cfg_.m, cfg_.bc), st, a);
                 });

@@ -148,20 +148,24 @@ def test_busy_plan_in_two_requests_is_serialised(ctx, c3_plans):
     assert_same(got[1], b)
 
 
-@pytest.mark.parametrize("m,level", [(32, "single"), (32, "pair"), (64, "pair")])
-def test_iteration_cap_reports_nonconvergence(ctx, ces, m, level):
-    # small-mesh and tiled solves agree on the status convention
-    plan = ctx.plan(ces.level_desc(cov="matern", nu=0.5, lam=0.05, m=m, level=level, cg_max_iter=2))
+@pytest.mark.parametrize("m,level,qoi", [(32, "single", "l2"), (32, "pair", "l2"), (64, "pair", "integral")])
+def test_iteration_cap_reports_nonconvergence(ctx, ces, m, level, qoi):
+    # small-mesh and tiled solves agree on the status convention (at m = 32
+    # only a QoI that is not linear in u runs the iterative small-mesh solve)
+    plan = ctx.plan(ces.level_desc(cov="matern", nu=0.5, lam=0.05, m=m, level=level, qoi=qoi, cg_max_iter=2))
     out = plan.sample(0, 0, 6)
     torch.cuda.synchronize()
     assert np.all(out["status"].cpu().numpy() == -4)
     assert np.all(out["iters"].cpu().numpy() == -2)
 
 
-@pytest.mark.parametrize("m,level", [(8, "single"), (16, "pair"), (16, "single")])
-def test_direct_solves_ignore_the_iteration_cap(ctx, ces, m, level):
-    # meshes with m <= 16 are solved directly: one "iteration", never capped
-    plan = ctx.plan(ces.level_desc(cov="matern", nu=0.5, lam=0.05, m=m, level=level, cg_max_iter=1))
+@pytest.mark.parametrize("m,level,qoi", [(8, "single", "integral"), (16, "pair", "l2"), (16, "single", "point"),
+                                         (32, "single", "integral"), (32, "pair", "outflux")])
+def test_direct_solves_ignore_the_iteration_cap(ctx, ces, m, level, qoi):
+    # meshes with m <= 16, and m <= 32 for a QoI linear in u, are solved
+    # directly: one "iteration", never capped
+    bc = "flowcell" if qoi == "outflux" else "dirichlet0"
+    plan = ctx.plan(ces.level_desc(cov="matern", nu=0.5, lam=0.05, m=m, level=level, qoi=qoi, bc=bc, cg_max_iter=1))
     out = plan.sample(0, 0, 6)
     torch.cuda.synchronize()
     assert np.all(out["status"].cpu().numpy() == 0)
