@@ -1187,9 +1187,45 @@ __device__ __forceinline__ double qoi_weight(const QoiLin& q, int gx, int gy, in
 // compile-time constant.  Exact up to rounding: one iteration, never the cap.
 template <int L>
 __device__ __forceinline__ double row_bcast(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + L, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + L, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
+    return __longlong_as_double(__builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + L, 0xF, 0xF, false));
+}
+
+// b on the lanes whose bit of the compile-time lane pattern M is set, a on
+// the others: a v_cndmask with the pattern as a scalar operand.  z is a
+// scalar zero defined where the blend is used, so that the pattern is
+// formed there (as M ^ z) and not hoisted out of the loop: the patterns of
+// all pivots together would not fit in SGPRs.
+template <unsigned long long M>
+__device__ __forceinline__ double lane_blend(double a, double b, unsigned long long z) {
+    if constexpr (M == ~0ull) {
+        return b;
+    } else if constexpr (M == 0ull) {
+        return a;
+    } else {
+        const unsigned long long mz = M ^ z;
+        int lo, hi;
+        asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(lo) : "v"(__double2loint(a)), "v"(__double2loint(b)), "s"(mz));
+        asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(hi) : "v"(__double2hiint(a)), "v"(__double2hiint(b)), "s"(mz));
+        return __hiloint2double(hi, lo);
+    }
+}
+
+__device__ __forceinline__ unsigned long long scalar_zero() {
+    unsigned long long z;
+    asm volatile("s_mov_b64 %0, 0" : "=s"(z));
+    return z;
+}
+
+// lanes (in every row of 16) whose window column c = kap + 16 h has
+// (c - rho) mod MB in [lo, hi]
+template <int MB>
+constexpr unsigned long long ring_lanes(int rho, int h, int lo, int hi) {
+    unsigned long long m = 0;
+    for (int k = 0; k < 16; ++k) {
+        const int d = (k + 16 * h - rho) & (MB - 1);
+        if (d >= lo && d <= hi) m |= 1ull << k;
+    }
+    return m * 0x0001000100010001ull;
 }
 
 template <int I, int E, typename F>
@@ -1271,20 +1307,27 @@ __global__ __launch_bounds__(64) void k_direct_lin(SmallArgs<T> a, QoiLin ql) {
             }
         }
     };
-    double R[C][MB], Y[C], YW[C];
-    // ring slot RHO takes the prepared row
+    double R[C][MB], Y[C] = {}, YW[C] = {};
+    // ring slot RHO takes the prepared row: the diagonal in column RHO, the
+    // east entry in column RHO + 1, the north entry in column RHO + bw
     auto load_row = [&](auto rho_ic) {
         constexpr int RHO = decltype(rho_ic)::value;
-#pragma unroll
-        for (int h = 0; h < C; ++h) {
-            int d = (kap + 16 * h - RHO) & (MB - 1);
-            asm volatile("" : "+v"(d));
-            R[h][RHO] = (d == 0 ? nd[h] : 0.0) + (d == 1 ? ne[h] : 0.0) + (d == bw ? nn[h] : 0.0);
-            if (d == 0) {
-                Y[h] = ny[h];
-                YW[h] = nw[h];
+        const unsigned long long z = scalar_zero();
+        static_for<0, C>([&](auto h_ic) {
+            constexpr int h = decltype(h_ic)::value;
+            constexpr unsigned long long M0 = ring_lanes<MB>(RHO, h, 0, 0), M1 = ring_lanes<MB>(RHO, h, 1, 1);
+            double v = lane_blend<M1>(lane_blend<M0>(0.0, nd[h], z), ne[h], z);
+            if constexpr (FULL) {
+                v = lane_blend<ring_lanes<MB>(RHO, h, MB - 1, MB - 1)>(v, nn[h], z);
+            } else {
+                int d = (kap + 16 * h - RHO) & (MB - 1);
+                asm volatile("" : "+v"(d));
+                if (d == bw) v += nn[h];
             }
-        }
+            R[h][RHO] = v;
+            Y[h] = lane_blend<M0>(Y[h], ny[h], z);
+            YW[h] = lane_blend<M0>(YW[h], nw[h], z);
+        });
     };
     prep(0);
     static_for<0, MB>(load_row);
@@ -1298,34 +1341,29 @@ __global__ __launch_bounds__(64) void k_direct_lin(SmallArgs<T> a, QoiLin ql) {
             const double D = row_bcast<RJ>(R[0][RJ]);
             const double inv = 1.0 / D;
             const double yj = row_bcast<RJ>(Y[0]), ywj = row_bcast<RJ>(YW[0]);
-            double pm[C];
-            int bp[C];
+            const unsigned long long z = scalar_zero();
+            // own pivot entry W(j, j + b), b = (c - RJ) mod MB, over -D(j)
+            double pmn[C];
 #pragma unroll
-            for (int h = 0; h < C; ++h) {
-                bp[h] = (kap + 16 * h - RJ) & (MB - 1);   // own pivot entry is W(j, j + bp)
-                // recomputed at every pivot: hoisted out of the loop over J,
-                // the lane masks of all pivots would not fit in SGPRs
-                asm volatile("" : "+v"(bp[h]));
-                pm[h] = R[h][RJ] * inv;
-            }
+            for (int h = 0; h < C; ++h) pmn[h] = -R[h][RJ] * inv;
             static_for<1, MB>([&](auto a_ic) {
                 constexpr int A = decltype(a_ic)::value;
                 constexpr int CS = (RJ + A) & (MB - 1);
                 if (!FULL && A > bw) return;
                 const double u = row_bcast<CS & 15>(R[CS >> 4][RJ]);   // W(j, j + A)
-#pragma unroll
-                for (int h = 0; h < C; ++h) {
-                    const double t = fma(-u, pm[h], R[h][CS]);
-                    R[h][CS] = A <= bp[h] ? t : R[h][CS];
-                }
+                static_for<0, C>([&](auto h_ic) {
+                    constexpr int h = decltype(h_ic)::value;
+                    // lanes with b >= A take the update
+                    constexpr unsigned long long M = ring_lanes<MB>(RJ, h, A, MB - 1);
+                    if constexpr (M != 0ull) R[h][CS] = fma(u, lane_blend<M>(0.0, pmn[h], z), R[h][CS]);
+                });
             });
-#pragma unroll
-            for (int h = 0; h < C; ++h) {
-                if (bp[h] != 0) {
-                    Y[h] = fma(-pm[h], yj, Y[h]);
-                    YW[h] = fma(-pm[h], ywj, YW[h]);
-                }
-            }
+            static_for<0, C>([&](auto h_ic) {
+                constexpr int h = decltype(h_ic)::value;
+                const double f = lane_blend<ring_lanes<MB>(RJ, h, 1, MB - 1)>(0.0, pmn[h], z);
+                Y[h] = fma(f, yj, Y[h]);
+                YW[h] = fma(f, ywj, YW[h]);
+            });
             qacc = fma(yj * ywj, inv, qacc);
             load_row(rj_ic);
         });
