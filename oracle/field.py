@@ -39,12 +39,16 @@ HARTLEY = 1
 
 
 def xi(seed, q, stream, n, mode):
-    """xi on the n x n embedding (indexed [j2, j1]) for pair / sample q."""
+    """xi on the n x n embedding (indexed [j2, j1]) for pair / sample q.
+
+    PAIR: entry e is g0 + i g1 of draw e.  HARTLEY: entry e is output e & 1
+    of draw e >> 1 (both Box-Muller outputs used, a real normal per entry)."""
     e = np.arange(n * n, dtype=np.uint64)
-    g0, g1 = normals(seed, q, stream, e)
     if mode == PAIR:
+        g0, g1 = normals(seed, q, stream, e)
         return (g0 + 1j * g1).reshape(n, n)
-    return g0.reshape(n, n).astype(np.complex128)
+    g0, g1 = normals(seed, q, stream, e >> np.uint64(1))
+    return np.where((e & np.uint64(1)) == 1, g1, g0).reshape(n, n).astype(np.complex128)
 
 
 def dft_plus(w):

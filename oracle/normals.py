@@ -8,7 +8,9 @@ definition: two 32x32->64 multiplies per round with multipliers
 
 key     = (seed mod 2^32, seed >> 32)
 counter = (e, q mod 2^32, q >> 32, stream)
-  e      element index j1 + n j2 of the embedding
+  e      draw index: the element index j1 + n j2 of the embedding in PAIR
+         mode (one complex normal per element), half of it in HARTLEY
+         mode (elements 2d and 2d+1 take the two outputs of draw d)
   q      pair index (PAIR mode) or sample index (HARTLEY mode)
   stream level tag of the request
 

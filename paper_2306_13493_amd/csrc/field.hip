@@ -52,7 +52,7 @@ __device__ __forceinline__ int src_index(int j, int n, int ns) {
 // is qpt (64-bit fraction), shift r: U = (qpt z + D) mod 2^64 with D from
 // Philox counter (j, r, 2^32-1, stream); u = (floor(U/2^12) + 1/2) 2^-52 in
 // (0,1); the normal is Phi^-1(u).
-__device__ __forceinline__ double lattice_normal(uint64_t seed, uint32_t stream, uint64_t r, uint64_t qpt,
+__device__ __noinline__ double lattice_normal(uint64_t seed, uint32_t stream, uint64_t r, uint64_t qpt,
                                                  uint32_t z, uint32_t j) {
     uint32_t c0 = j, c1 = (uint32_t)r, c2 = 0xFFFFFFFFu, c3 = stream;
     philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -77,30 +77,65 @@ __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
         qsh = q - i * (uint64_t)b.qshifts;
         qpt = __builtin_bitreverse64(i);
     }
-    // adjacent threads take adjacent j1 of one row j2 (coalesced amplitude
-    // reads); line `line` of the LDS buffer is column j1_0 + line
-    for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
-        const int j2 = t / L;
-        const int line = t - j2 * L;
-        const int j1 = j1_0 + line;
-        const uint32_t ia = (uint32_t)j1 + (uint32_t)n * (uint32_t)j2;   // amplitude index
-        uint32_t e = ia;                                                  // normal counter
-        if (b.n_src > 0) e = (uint32_t)src_index(j1, n, b.n_src) + (uint32_t)b.n_src * (uint32_t)src_index(j2, n, b.n_src);
-        double g0, g1;
-        const int jq = (MODE == MODE_HARTLEY && b.qrank) ? b.qrank[e] : -1;
-        if (jq >= 0) {
-            g0 = lattice_normal(b.seed, b.stream, qsh, qpt, b.qz[jq], (uint32_t)jq);
-            g1 = 0.0;
-        } else {
-            normal_pair(b.seed, q, b.stream, e, g0, g1);
-        }
-        const double xr = g0;
-        const double xi = (MODE == MODE_PAIR) ? g1 : 0.0;
+    // scaled normal into line `line`, row j2 of the LDS buffer (and of the
+    // coarse lines when a pair level takes two fields from one xi)
+    auto put = [&](int line, int j2, uint32_t ia, double xr, double xi) {
         const double a = (double)b.af[ia];
         buf[line * ld + j2] = cplx<T>{(T)(a * xr), (T)(a * xi)};
         if constexpr (NF == 2) {
             const double c = (double)b.ac[ia];
             buf[(L + line) * ld + j2] = cplx<T>{(T)(c * xr), (T)(c * xi)};
+        }
+    };
+    auto counter = [&](int j1, int j2) -> uint32_t {
+        if (b.n_src > 0) return (uint32_t)src_index(j1, n, b.n_src) + (uint32_t)b.n_src * (uint32_t)src_index(j2, n, b.n_src);
+        return (uint32_t)j1 + (uint32_t)n * (uint32_t)j2;
+    };
+    if constexpr (MODE == MODE_PAIR) {
+        // adjacent threads take adjacent j1 of one row j2 (coalesced
+        // amplitude reads); line `line` of the LDS buffer is column j1_0 + line
+        for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
+            const int j2 = t / L;
+            const int line = t - j2 * L;
+            const int j1 = j1_0 + line;
+            double g0, g1;
+            normal_pair(b.seed, q, b.stream, counter(j1, j2), g0, g1);
+            put(line, j2, (uint32_t)j1 + (uint32_t)n * (uint32_t)j2, g0, g1);
+        }
+    } else {
+        // real xi: entry e takes output e & 1 of draw e >> 1, or a lattice
+        // coordinate where the plan carries a lattice rule.  A thread takes
+        // two adjacent lines when L >= 2: entries e, e + 1 with e even then
+        // share one draw.
+        const int W = L >= 2 ? 2 : 1;
+        const int per = L / W;
+        for (int t = threadIdx.x; t < per * n; t += blockDim.x) {
+            const int j2 = t / per;
+            const int line = W * (t - j2 * per);
+            const int j1 = j1_0 + line;
+            const uint32_t e0 = counter(j1, j2);
+            const uint32_t e1 = W == 2 ? counter(j1 + 1, j2) : e0;
+            double x0, x1;
+            {
+                double g0, g1;
+                normal_pair(b.seed, q, b.stream, e0 >> 1, g0, g1);
+                x0 = (e0 & 1u) ? g1 : g0;
+                x1 = g1;
+            }
+            if (W == 2 && !((e0 & 1u) == 0u && e1 == e0 + 1u)) {
+                double g0, g1;
+                normal_pair(b.seed, q, b.stream, e1 >> 1, g0, g1);
+                x1 = (e1 & 1u) ? g1 : g0;
+            }
+            if (b.qrank) {
+                const int jq0 = b.qrank[e0];
+                if (jq0 >= 0) x0 = lattice_normal(b.seed, b.stream, qsh, qpt, b.qz[jq0], (uint32_t)jq0);
+                const int jq1 = W == 2 ? b.qrank[e1] : -1;
+                if (jq1 >= 0) x1 = lattice_normal(b.seed, b.stream, qsh, qpt, b.qz[jq1], (uint32_t)jq1);
+            }
+            const uint32_t ia = (uint32_t)j1 + (uint32_t)n * (uint32_t)j2;
+            put(line, j2, ia, x0, 0.0);
+            if (W == 2) put(line + 1, j2, ia + 1u, x1, 0.0);
         }
     }
     __syncthreads();
