@@ -62,11 +62,40 @@ __device__ __noinline__ double lattice_normal(uint64_t seed, uint32_t stream, ui
     return normcdfinv(u);
 }
 
+// Embeddings up to this size keep their twiddle table in LDS behind the
+// lines (n complex values), so that the DFT stages read twiddles at LDS
+// latency; larger ones read the global table.
+constexpr int kTwLds = 1024;
+
+// line stride of the field kernels' LDS buffer (one slot of padding: the
+// odd stride spreads the lines over the banks)
+__host__ __device__ constexpr int field_ld(int n) { return n + 1; }
+
+template <typename T>
+inline size_t field_lds_bytes(int lines, int n) {
+    return (size_t)lines * field_ld(n) * sizeof(cplx<T>) + (n <= kTwLds ? (size_t)n * sizeof(cplx<T>) : 0);
+}
+
+// DFT of the lines in buf, with the twiddles staged into LDS at twl (the
+// workgroup synchronises first: the caller's stores into buf are complete)
+template <typename T, int E>
+__device__ __forceinline__ void field_fft(cplx<T>* buf, int lines, int ld, const FieldBatch<T>& b, cplx<T>* twl) {
+    const int n = b.n;
+    if (n <= kTwLds) {
+        for (int t = threadIdx.x; t < n; t += blockDim.x) twl[t] = b.tw[t];
+        __syncthreads();
+        fft_lines<T, E>(buf, lines, ld, b.fp, twl);
+    } else {
+        __syncthreads();
+        fft_lines<T, E>(buf, lines, ld, b.fp, b.tw);
+    }
+}
+
 template <typename T, int E, int MODE, int NF>
 __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int n = b.n, ld = n + 1;
+    const int n = b.n, ld = field_ld(n);
     const int u = blockIdx.y;
     const uint64_t q = b.q0 + (uint64_t)u;
     const int j1_0 = blockIdx.x * L;
@@ -138,8 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
             if (W == 2) put(line + 1, j2, ia + 1u, x1, 0.0);
         }
     }
-    __syncthreads();
-    fft_lines<T, E>(buf, NF * L, ld, b.fp, b.tw);
+    field_fft<T, E>(buf, NF * L, ld, b, buf + (size_t)NF * L * ld);
     const int mp1 = b.m + 1;
     for (int t = threadIdx.x; t < NF * mp1 * L; t += blockDim.x) {
         const int line = t % L;
@@ -154,19 +182,32 @@ template <typename T, int E, int MODE, int NF, bool ZOUT>
 __global__ __launch_bounds__(kBlock) void k_field_x(FieldBatch<T> b, int L) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int n = b.n, ld = n + 1;
+    const int n = b.n, ld = field_ld(n);
     const int mp1 = b.m + 1;
     const int p2_0 = blockIdx.x * L;
     const int u = blockIdx.y;
     const int f = blockIdx.z;
     const int lines = min(L, mp1 - p2_0);
     const cplx<T>* src = b.work + ((size_t)(f * b.units + u) * mp1 + p2_0) * n;
-    for (int t = threadIdx.x; t < lines * n; t += blockDim.x) {
-        const int l = t / n;
-        buf[l * ld + (t - l * n)] = src[t];
+    // all of the thread's loads are issued before the first LDS store, so
+    // that their latencies overlap (lines * n <= E * kBlock)
+    {
+        cplx<T> v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int t = threadIdx.x + i * kBlock;
+            if (t < lines * n) v[i] = src[t];
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int t = threadIdx.x + i * kBlock;
+            if (t < lines * n) {
+                const int l = t / n;
+                buf[l * ld + (t - l * n)] = v[i];
+            }
+        }
     }
-    __syncthreads();
-    fft_lines<T, E>(buf, lines, ld, b.fp, b.tw);
+    field_fft<T, E>(buf, lines, ld, b, buf + (size_t)L * ld);
     const bool fine = (f == 0);
     const bool coarse = b.coarse && (f == NF - 1);
     const int mcp1 = b.m / 2 + 1;
@@ -279,8 +320,8 @@ __global__ __launch_bounds__(kBlock) void k_convert_d2f(const double* __restrict
 
 template <typename T, int E, int MODE, int NF>
 hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2) {
-    const size_t lds1 = (size_t)NF * L1 * (b.n + 1) * sizeof(cplx<T>);
-    const size_t lds2 = (size_t)L2 * (b.n + 1) * sizeof(cplx<T>);
+    const size_t lds1 = field_lds_bytes<T>(NF * L1, b.n);
+    const size_t lds2 = field_lds_bytes<T>(L2, b.n);
     auto kr = k_field_y<T, E, MODE, NF>;
     hipError_t e = allow_lds(kr, lds1);
     if (e != hipSuccess) return e;
