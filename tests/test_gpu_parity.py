@@ -307,6 +307,33 @@ def test_largest_mesh(ctx, ces):
     assert np.max(np.abs(y - y64)) <= 1e-6 * np.max(np.abs(y64))
 
 
+@pytest.mark.timeout(400)   # the oracle's normals and two DFTs at 4096^2 take about half a minute
+def test_two_field_pair_level_at_4096(ctx, ces):
+    """The largest pair level that draws both fields from one xi (the finest
+    level of the smoothed estimator at 2049^2, embedding 4096^2): its DFT
+    passes run one line per workgroup per field, 32 values per thread.  Both
+    fields of a sample against the oracle's, and converged level samples
+    whose Y agrees between the mixed and the FP64 path to the mixed bar."""
+    w = dict(cov="sepexp", lam=0.05, m=2048, level="pair", tau_fine=0, tau_coarse=-1)
+    p = mkplan(ctx, ces, w)
+    o = oracle_plan(w)
+    assert (p.info.n, p.info.J) == (o.n, o.J) == (4096, 0)
+    zf, zc = p.field(0, 3)
+    rf, rc = o.fields(0, 3)
+    scale = np.abs(rf).max()
+    assert np.max(np.abs(zf.cpu().numpy() - rf)) <= 1e-5 * scale
+    assert np.max(np.abs(zc.cpu().numpy() - rc)) <= 1e-5 * scale
+    del zf, zc, rf, rc, o
+    out = p.sample(0, 0, 2)
+    out64 = mkplan(ctx, ces, dict(w, precision="fp64")).sample(0, 0, 2)
+    torch.cuda.synchronize()
+    for r in (out, out64):
+        assert np.all(r["status"].cpu().numpy() == 0)
+    y, y64 = out["y"].cpu().numpy(), out64["y"].cpu().numpy()
+    yq = out64["q_fine"].cpu().numpy()
+    assert np.max(np.abs(y - y64)) <= 1e-6 * np.max(np.abs(yq))
+
+
 def test_two_field_pair_level_beyond_4096_is_rejected(ctx, ces):
     # the finest level of the smoothed estimator at m = 4096 draws two fields
     w = dict(cov="sepexp", lam=0.05, m=4096, level="pair", tau_fine=0, tau_coarse=-1)
