@@ -482,7 +482,7 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
 // so that no per-level array sits in private memory).
 template <typename T>
 struct LdsMg {
-    T *z, *rhs, *ce, *cn, *id, *tmp;
+    T *z, *rhs, *ce, *cn, *tmp;
     int* off;
     int nl, bc, m0;
     __device__ int m(int l) const { return m0 >> l; }
@@ -513,42 +513,32 @@ __device__ void lds_mg_layout(const LdsMg<T>& g) {
     }
 }
 
-// one red-black half-sweep of colour c (parity of x + y) on one level
+// inverse diagonal of unknown p (x, y) from the edge conductances
 template <typename T>
-__device__ void lds_sweep(T* z, const T* rhs, const T* ce, const T* cn, const T* id, int m, int c) {
+__device__ __forceinline__ T lds_inv_diag(const T* ce, const T* cn, int p, int y, int w) {
+    return T(1) / (ce[p] + ce[p - 1] + cn[p] + (y >= 1 ? cn[p - w] : T(0)));
+}
+
+// one red-black half-sweep of colour c (parity of x + y) on one level; the
+// inverse diagonal is formed where it is used (not stored: the LDS it
+// would take decides how many samples a CU holds)
+template <typename T>
+__device__ void lds_sweep(T* z, const T* rhs, const T* ce, const T* cn, int m, int bc, int c) {
     const int w = m + 1;
     const int half = (w + 1) / 2;
     for (int t = threadIdx.x; t < half * w; t += blockDim.x) {
         const int y = t / half;
         const int x = 2 * (t - y * half) + ((c - y) & 1);
         if (x >= w) continue;
+        if (!is_unknown(x, y, m, bc)) continue;
         const int p = y * w + x;
-        const T d = id[p];
-        if (d == T(0)) continue;
+        const T d = lds_inv_diag(ce, cn, p, y, w);
         T s = rhs[p];
         if (x + 1 < w) s += ce[p] * z[p + 1];
         if (x >= 1) s += ce[p - 1] * z[p - 1];
         if (y + 1 < w) s += cn[p] * z[p + w];
         if (y >= 1) s += cn[p - w] * z[p - w];
         z[p] = z[p] + T(kSorOmega) * (s * d - z[p]);
-    }
-    __syncthreads();
-}
-
-// inverse diagonals of every level (zero off the unknowns)
-template <typename T>
-__device__ void lds_mg_diag(const LdsMg<T>& g) {
-    for (int l = 0; l < g.nl; ++l) {
-        const int m = g.m(l), w = g.w(l), o = g.off[l];
-        for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-            const int y = t / w, x = t - y * w;
-            T v = T(0);
-            if (is_unknown(x, y, m, g.bc)) {
-                const int p = o + t;
-                v = T(1) / (g.ce[p] + g.ce[p - 1] + g.cn[p] + (y >= 1 ? g.cn[p - w] : T(0)));
-            }
-            g.id[o + t] = v;
-        }
     }
     __syncthreads();
 }
@@ -561,11 +551,11 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
     for (int t = threadIdx.x; t < tot; t += blockDim.x) g.z[t] = T(0);
     __syncthreads();
     T *z = g.z, *rhs = g.rhs, *tmp = g.tmp;
-    const T *ce = g.ce, *cn = g.cn, *id = g.id;
+    const T *ce = g.ce, *cn = g.cn;
     // down: pre-smooth, residual, restriction (transpose of bilinear)
     for (int l = 0; l + 1 < g.nl; ++l) {
         const int m = g.m(l), w = g.w(l), o = g.off[l];
-        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, id + o, m, c & 1);
+        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, m, g.bc, c & 1);
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
             const int y = t / w, x = t - y * w;
             T r = T(0);
@@ -606,7 +596,7 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
         for (int j = 0; j < 3; ++j) {
             if (j < ylo || j > yhi) continue;
             const int p = o + j * w + 1;
-            const T d = T(1) / id[p];
+            const T d = T(1) / lds_inv_diag(ce, cn, p, j, w);
             if (j == ylo) {
                 beta[j] = d;
                 yv[j] = rhs[p];
@@ -648,7 +638,7 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
             z[o + t] += p;
         }
         __syncthreads();
-        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, id + o, m, 1 - (c & 1));
+        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, m, g.bc, 1 - (c & 1));
     }
 }
 
@@ -670,13 +660,13 @@ struct BottomArgs {
 template <typename T, int MB, int NT>
 __global__ __launch_bounds__(NT) void k_bottom(BottomArgs<T> a) {
     constexpr int TOT = lds_mg_nodes(MB);
-    __shared__ T z[TOT], rhs[TOT], ce[TOT], cn[TOT], id[TOT];
+    __shared__ T z[TOT], rhs[TOT], ce[TOT], cn[TOT];
     __shared__ T tmp[(MB + 1) * (MB + 1)];
     __shared__ int off[8];
     const int s = blockIdx.x;
     if (!a.scal[s].active) return;
     LdsMg<T> g;
-    g.z = z; g.rhs = rhs; g.ce = ce; g.cn = cn; g.id = id; g.tmp = tmp;
+    g.z = z; g.rhs = rhs; g.ce = ce; g.cn = cn; g.tmp = tmp;
     g.off = off;
     g.nl = a.nl;
     g.bc = a.bc;
@@ -714,7 +704,6 @@ __global__ __launch_bounds__(NT) void k_bottom(BottomArgs<T> a) {
         }
     }
     __syncthreads();
-    lds_mg_diag(g);
     lds_vcycle(g);
     const int m = g.m(0), w = g.w(0);
     for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
@@ -831,7 +820,7 @@ constexpr int kSmallMax = 32;   // largest mesh solved by one workgroup
 template <typename T>
 size_t small_lds_bytes(int m) {
     const size_t n0 = (size_t)(m + 1) * (m + 1);
-    return 3 * n0 * sizeof(double) + (5 * (size_t)lds_mg_nodes(m) + n0) * sizeof(T);
+    return 3 * n0 * sizeof(double) + (4 * (size_t)lds_mg_nodes(m) + n0) * sizeof(T);
 }
 
 // NT threads for meshes with m <= MB: thread t owns nodes t, t + NT, ...
@@ -852,8 +841,7 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
     g.rhs = g.z + tot;
     g.ce = g.rhs + tot;
     g.cn = g.ce + tot;
-    g.id = g.cn + tot;
-    g.tmp = g.id + tot;
+    g.tmp = g.cn + tot;
     g.off = off;
     g.nl = a.nl;
     g.bc = bc;
@@ -901,7 +889,6 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
         }
         __syncthreads();
     }
-    lds_mg_diag(g);
     // x = Dirichlet lifting, r = b - A x at the unknowns
     double xr[kSmallNpt], rr_[kSmallNpt], qr[kSmallNpt];
     double acc = 0.0;
