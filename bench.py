@@ -47,8 +47,9 @@ KERNEL_SYMBOL = {
 # scaled by a plain copy's counters; valid only for the kernel sources it
 # was measured on (their SHA-256 is recorded with the figures).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_mixed_hbm_traffic.md")
+# the kernels and the chunking (exec.cpp sizes the launches)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_13493_amd", "csrc", f)
-                  for f in ("solver.hip", "field.hip", "common.hpp", "fft_lds.hpp", "philox_bm.hpp")]
+                  for f in ("solver.hip", "field.hip", "common.hpp", "fft_lds.hpp", "philox_bm.hpp", "exec.cpp")]
 
 
 def sources_digest():

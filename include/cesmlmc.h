@@ -161,7 +161,7 @@ void ces_level_desc_default(ces_level_desc* d);
 /* Bind to HIP device `device`.  mem_budget_bytes caps the library's own
  * workspace (0 = 90% of free device memory).  A plan's sample workspace,
  * allocated on its first sampling call, holds as many samples as fit in
- * 4.5 GiB or 64 samples, whichever is more (at most 8192; 65536 for
+ * 9 GiB or 64 samples, whichever is more (at most 8192; 65536 for
  * m <= 32), or in the size in MiB given by the environment variable
  * CESMLMC_WORKSPACE_MB, and within the budget.  A
  * request larger than the workspace runs in the fewest chunks that fit,

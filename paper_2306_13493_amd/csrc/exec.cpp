@@ -176,11 +176,13 @@ long long workspace_slots(const ces_plan p, long long max_slots) {
     const int m = p->d.m_fine;
     const bool pair_field = p->d.field_mode == CES_FIELD_PAIR;
     const size_t per_slot = slot_bytes(p);
-    // 4.5 GiB, but room for at least 64 samples: on meshes of about 300 MB
-    // per sample the per-chunk overheads (one host round trip per CG
-    // iteration) dominate small chunks (2049^2 flow cell, 1024 samples per
-    // call: 13 per chunk 781 samples/s, 55 per chunk 845, 138 per chunk 857)
-    size_t target = std::max((size_t)9 << 29, 64 * per_slot);
+    // 9 GiB (3% of the device; 257^2 single level: 2060 samples per chunk,
+    // 4096-sample calls in 2 chunks instead of 4: +1.7% samples/s), but
+    // room for at least 64 samples: on meshes of about 300 MB per sample the
+    // per-chunk overheads (one host round trip per CG iteration) dominate
+    // small chunks (2049^2 flow cell, 1024 samples per call: 13 per chunk
+    // 781 samples/s, 55 per chunk 845, 138 per chunk 857)
+    size_t target = std::max((size_t)9 << 30, 64 * per_slot);
     if (const char* env = std::getenv("CESMLMC_WORKSPACE_MB")) target = (size_t)std::atoll(env) << 20;
     const size_t used = p->ctx->used.load();
     if (p->ctx->budget && p->ctx->budget - std::min(p->ctx->budget, used) < target)
