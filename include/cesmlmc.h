@@ -571,6 +571,13 @@ typedef struct {
  * kernel launch (clearing earlier records); on == 0 stops. */
 int ces_profile_enable(int32_t on);
 
+/* Process-wide.  Restricts the recording to launches of the kernel with
+ * this profile name (as ces_profile_read reports it, e.g. "pcg_dir"), so
+ * that a timed region pays the HIP events of that kernel's launches only;
+ * NULL or "" records every kernel again.  The name is copied.  Kept across
+ * ces_profile_enable calls. */
+int ces_profile_only(const char* name);
+
 /* Synchronises with the recorded launches, writes up to max_entries
  * entries (largest total time first) to host memory and the number of
  * kernels to *n_entries, then clears the records. */

@@ -449,6 +449,11 @@ def profile_enable(on=True):
     check(load().ces_profile_enable(1 if on else 0))
 
 
+def profile_only(name=None):
+    """Record only launches of the kernel with this profile name (None: all)."""
+    check(load().ces_profile_only(name.encode() if name else None))
+
+
 def profile_read(max_entries=64):
     """Per-kernel {name: (launches, total_ms, algorithmic_bytes)}; clears."""
     lib = load()
@@ -459,5 +464,5 @@ def profile_read(max_entries=64):
             for i in range(min(n.value, max_entries))}
 
 
-__all__ = ["Context", "Plan", "Server", "level_desc", "mlmc_run", "mlqmc_run", "lattice_cbc", "coarsest_mesh", "normals", "profile_enable", "profile_read", "CesError", "LevelDesc",
+__all__ = ["Context", "Plan", "Server", "level_desc", "mlmc_run", "mlqmc_run", "lattice_cbc", "coarsest_mesh", "normals", "profile_enable", "profile_only", "profile_read", "CesError", "LevelDesc",
            "PlanInfo", "Request", "Schedule", "load"]

@@ -139,6 +139,7 @@ SIGNATURES = {
     "ces_field": (c_int32, [c_void_p, c_uint64, c_uint64, c_dptr, c_dptr, c_void_p]),
     "ces_solve": (c_int32, [c_void_p, c_int32, c_int64, c_dptr, c_dptr, c_dptr, c_void_p]),
     "ces_profile_enable": (c_int32, [c_int32]),
+    "ces_profile_only": (c_int32, [ctypes.c_char_p]),
     "ces_profile_read": (c_int32, [ctypes.POINTER(ProfileEntry), c_int32, ctypes.POINTER(c_int32)]),
     "ces_last_error": (ctypes.c_char_p, []),
 }

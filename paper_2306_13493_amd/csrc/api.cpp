@@ -251,6 +251,11 @@ int ces_profile_enable(int32_t on) {
     return CES_OK;
 }
 
+int ces_profile_only(const char* name) {
+    Profiler::get().only(name);
+    return CES_OK;
+}
+
 int ces_profile_read(ces_profile_entry* out, int32_t max_entries, int32_t* n_entries) {
     if (max_entries < 0 || (max_entries > 0 && !out)) return fail(CES_ERR_ARG, "profile output buffer");
     std::vector<Profiler::Entry> v;

@@ -333,12 +333,12 @@ hipError_t field_launch_e(const FieldBatch<T>& b, hipStream_t st, int L1, int L2
     const double kout = slots * sT * ((double)(b.m + 1) * (b.m + 1) +
                                       (b.coarse ? (double)(b.m / 2 + 1) * (b.m / 2 + 1) : 0.0));
     Profiler& P = Profiler::get();
-    Profiler::Slot ps = P.begin();
+    Profiler::Slot ps = P.begin("field_y");
     hipExtLaunchKernelGGL(kr, dim3(b.n / L1, b.units), dim3(kBlock), lds1, st, ps.a, ps.b, 0, b, L1);
     P.end(ps, "field_y", (double)NF * b.n * b.n * sT + inter, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     dim3 g2(cdiv(b.m + 1, L2), b.units, NF);
-    ps = P.begin();
+    ps = P.begin("field_x");
     if (b.zf) {
         auto kc = k_field_x<T, E, MODE, NF, true>;
         if ((e = allow_lds(kc, lds2)) != hipSuccess) return e;

@@ -209,7 +209,9 @@ public:
     static Profiler& get();
     bool on() const { return on_.load(std::memory_order_relaxed); }
     void enable(bool on);
-    Slot begin();
+    // record only launches of kernel `name` (null or empty: every kernel)
+    void only(const char* name);
+    Slot begin(const char* name = nullptr);
     void end(const Slot& s, const char* name, double bytes_per_sample, int samples);
     void set_samples(int idx, int samples);
     int read(std::vector<Entry>& out);   // synchronises; clears the records
@@ -223,6 +225,7 @@ private:
     };
     std::atomic<bool> on_{false};
     std::mutex mu_;
+    std::string only_;
     std::vector<Rec> recs_;
     std::vector<hipEvent_t> pool_;
     size_t used_ = 0;

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <string>
 #include <vector>
 
 #include "internal.hpp"
@@ -24,10 +25,11 @@ hipEvent_t Profiler::event() {
     return e;
 }
 
-Profiler::Slot Profiler::begin() {
+Profiler::Slot Profiler::begin(const char* name) {
     Slot s;
     if (!on_) return s;
     std::lock_guard<std::mutex> g(mu_);
+    if (!only_.empty() && (!name || only_ != name)) return s;
     Rec r;
     r.a = event();
     r.b = event();
@@ -51,6 +53,11 @@ void Profiler::end(const Slot& s, const char* name, double bytes_per_sample, int
 void Profiler::set_samples(int idx, int samples) {
     std::lock_guard<std::mutex> g(mu_);
     if (idx >= 0 && idx < (int)recs_.size()) recs_[idx].samples = samples;
+}
+
+void Profiler::only(const char* name) {
+    std::lock_guard<std::mutex> g(mu_);
+    only_ = name ? name : "";
 }
 
 void Profiler::enable(bool on) {

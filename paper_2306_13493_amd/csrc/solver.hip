@@ -2022,7 +2022,7 @@ private:
     template <typename F>
     void launch(const char* name, double bytes_per_sample, int S, int it, hipStream_t st, F&& f) {
         Profiler& P = Profiler::get();
-        const Profiler::Slot ps = P.begin();
+        const Profiler::Slot ps = P.begin(name);
         f(ps);
         if (ps.idx >= 0) {
             P.end(ps, name, bytes_per_sample, S);
