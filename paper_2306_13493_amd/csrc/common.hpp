@@ -96,6 +96,22 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+// Division by a runtime divisor d >= 1 as one multiply-high: with
+// M = ceil(2^32 / d), umulhi(x, M) = floor(x / d) whenever x (M d - 2^32)
+// < 2^32, and M d - 2^32 < d, so every x with x d < 2^32 is exact (d = 1
+// keeps M = 0 and returns x).  Replaces the ~15-instruction integer
+// division sequence in per-element index arithmetic.
+struct FastDiv {
+    unsigned d, M;
+    __host__ __device__ FastDiv() : d(1u), M(0u) {}
+    __host__ __device__ explicit FastDiv(unsigned dv) : d(dv), M(dv <= 1u ? 0u : 0xFFFFFFFFu / dv + 1u) {}
+    __device__ __forceinline__ int div(int x) const { return M ? (int)__umulhi((unsigned)x, M) : x; }
+};
+
+// a * b for 0 <= a, b < 2^24 with a product below 2^31, on the full-rate
+// 24-bit multiplier (a 32-bit integer multiply issues at a quarter rate)
+__device__ __forceinline__ int mul24(int a, int b) { return (int)__umul24((unsigned)a, (unsigned)b); }
+
 // Opt a kernel in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB).
 template <typename KernelT>
 hipError_t allow_lds(KernelT kernel, size_t bytes) {

@@ -18,10 +18,14 @@
 
 namespace ces {
 
+// nr[s], ns[s]: divisions by N / R and by Ns of stage s (the butterfly
+// indices stay below lines * N <= E * blockDim <= 8192 and the divisors
+// below 8192: within FastDiv's exact range)
 struct FftPlan {
     int n;
     int nst;
     int rad[24];
+    FastDiv nr[24], ns[24];
 };
 
 inline FftPlan make_fft_plan(int n) {
@@ -32,7 +36,16 @@ inline FftPlan make_fft_plan(int n) {
     while (r % 4 == 0 && r > 1) { p.rad[p.nst++] = 4; r /= 4; }
     if (r % 2 == 0) { p.rad[p.nst++] = 2; r /= 2; }
     while (r % 3 == 0) { p.rad[p.nst++] = 3; r /= 3; }
-    if (r != 1) p.nst = -1;  // unsupported size
+    if (r != 1) {
+        p.nst = -1;  // unsupported size
+        return p;
+    }
+    int Ns = 1;
+    for (int s = 0; s < p.nst; ++s) {
+        p.nr[s] = FastDiv((unsigned)(n / p.rad[s]));
+        p.ns[s] = FastDiv((unsigned)Ns);
+        Ns *= p.rad[s];
+    }
     return p;
 }
 
@@ -86,21 +99,28 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
 // buf + l * ld (ld >= n; a padded stride spreads lines over the LDS banks).
 // MB = maximum butterflies per thread (compile time, registers).
 template <typename T, int R, int MB>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int ld, int lines, int Ns,
-                                          const cplx<T>* __restrict__ tw) {
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int ld, int lines, int Ns, FastDiv dnr,
+                                          FastDiv dns, const cplx<T>* __restrict__ tw) {
     const int NR = n / R;
     const int total = NR * lines;
     const int stride = n / (Ns * R);
+    // index arithmetic once per butterfly, before the barrier (all indices
+    // and products stay below 2^24: lines * n <= 8192, ld <= 8193)
     cplx<T> v[MB][R];
+    int yo[MB], kt[MB];
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
         const int g = threadIdx.x + b * (int)blockDim.x;
         if (g < total) {
-            const int line = g / NR;
-            const int j = g - line * NR;
-            const cplx<T>* x = buf + line * ld;
+            const int line = dnr.div(g);
+            const int j = g - mul24(line, NR);
+            const int k = j - mul24(dns.div(j), Ns);
+            const int lo = mul24(line, ld);
+            const cplx<T>* x = buf + lo;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = x[j + r * NR];
+            for (int r = 0; r < R; ++r) v[b][r] = x[j + mul24(r, NR)];
+            yo[b] = lo + (j - k) * R + k;
+            kt[b] = mul24(k, stride);
         }
     }
     __syncthreads();
@@ -108,17 +128,14 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int ld, int lines
     for (int b = 0; b < MB; ++b) {
         const int g = threadIdx.x + b * (int)blockDim.x;
         if (g < total) {
-            const int line = g / NR;
-            const int j = g - line * NR;
-            const int k = j % Ns;
             if (Ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * stride]);
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[mul24(r, kt[b])]);
             }
             dft_small<T, R>(v[b]);
-            cplx<T>* y = buf + line * ld + (j - k) * R + k;
+            cplx<T>* y = buf + yo[b];
 #pragma unroll
-            for (int r = 0; r < R; ++r) y[r * Ns] = v[b][r];
+            for (int r = 0; r < R; ++r) y[mul24(r, Ns)] = v[b][r];
         }
     }
     __syncthreads();
@@ -132,13 +149,13 @@ __device__ void fft_lines(cplx<T>* buf, int lines, int ld, const FftPlan& fp, co
     for (int s = 0; s < fp.nst; ++s) {
         const int R = fp.rad[s];
         if (R == 8)
-            fft_stage<T, 8, (E + 7) / 8>(buf, fp.n, ld, lines, Ns, tw);
+            fft_stage<T, 8, (E + 7) / 8>(buf, fp.n, ld, lines, Ns, fp.nr[s], fp.ns[s], tw);
         else if (R == 4)
-            fft_stage<T, 4, (E + 3) / 4>(buf, fp.n, ld, lines, Ns, tw);
+            fft_stage<T, 4, (E + 3) / 4>(buf, fp.n, ld, lines, Ns, fp.nr[s], fp.ns[s], tw);
         else if (R == 2)
-            fft_stage<T, 2, (E + 1) / 2>(buf, fp.n, ld, lines, Ns, tw);
+            fft_stage<T, 2, (E + 1) / 2>(buf, fp.n, ld, lines, Ns, fp.nr[s], fp.ns[s], tw);
         else
-            fft_stage<T, 3, (E + 2) / 3>(buf, fp.n, ld, lines, Ns, tw);
+            fft_stage<T, 3, (E + 2) / 3>(buf, fp.n, ld, lines, Ns, fp.nr[s], fp.ns[s], tw);
         Ns *= R;
     }
 }

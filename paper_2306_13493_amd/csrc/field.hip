@@ -108,28 +108,30 @@ __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
     }
     // scaled normal into line `line`, row j2 of the LDS buffer (and of the
     // coarse lines when a pair level takes two fields from one xi)
+    // (index products below 2^24 throughout: n <= 8192, L <= 16)
     auto put = [&](int line, int j2, uint32_t ia, double xr, double xi) {
         const double a = (double)b.af[ia];
-        buf[line * ld + j2] = cplx<T>{(T)(a * xr), (T)(a * xi)};
+        buf[mul24(line, ld) + j2] = cplx<T>{(T)(a * xr), (T)(a * xi)};
         if constexpr (NF == 2) {
             const double c = (double)b.ac[ia];
-            buf[(L + line) * ld + j2] = cplx<T>{(T)(c * xr), (T)(c * xi)};
+            buf[mul24(L + line, ld) + j2] = cplx<T>{(T)(c * xr), (T)(c * xi)};
         }
     };
     auto counter = [&](int j1, int j2) -> uint32_t {
         if (b.n_src > 0) return (uint32_t)src_index(j1, n, b.n_src) + (uint32_t)b.n_src * (uint32_t)src_index(j2, n, b.n_src);
-        return (uint32_t)j1 + (uint32_t)n * (uint32_t)j2;
+        return (uint32_t)(j1 + mul24(n, j2));
     };
     if constexpr (MODE == MODE_PAIR) {
         // adjacent threads take adjacent j1 of one row j2 (coalesced
         // amplitude reads); line `line` of the LDS buffer is column j1_0 + line
+        const FastDiv dL((unsigned)L);
         for (int t = threadIdx.x; t < L * n; t += blockDim.x) {
-            const int j2 = t / L;
+            const int j2 = dL.div(t);
             const int line = t - j2 * L;
             const int j1 = j1_0 + line;
             double g0, g1;
             normal_pair(b.seed, q, b.stream, counter(j1, j2), g0, g1);
-            put(line, j2, (uint32_t)j1 + (uint32_t)n * (uint32_t)j2, g0, g1);
+            put(line, j2, (uint32_t)(j1 + mul24(n, j2)), g0, g1);
         }
     } else {
         // real xi: entry e takes output e & 1 of draw e >> 1, or a lattice
@@ -138,8 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
         // share one draw.
         const int W = L >= 2 ? 2 : 1;
         const int per = L / W;
+        const FastDiv dper((unsigned)per);
         for (int t = threadIdx.x; t < per * n; t += blockDim.x) {
-            const int j2 = t / per;
+            const int j2 = dper.div(t);
             const int line = W * (t - j2 * per);
             const int j1 = j1_0 + line;
             const uint32_t e0 = counter(j1, j2);
@@ -162,19 +165,21 @@ __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
                 const int jq1 = W == 2 ? b.qrank[e1] : -1;
                 if (jq1 >= 0) x1 = lattice_normal(b.seed, b.stream, qsh, qpt, b.qz[jq1], (uint32_t)jq1);
             }
-            const uint32_t ia = (uint32_t)j1 + (uint32_t)n * (uint32_t)j2;
+            const uint32_t ia = (uint32_t)(j1 + mul24(n, j2));
             put(line, j2, ia, x0, 0.0);
             if (W == 2) put(line + 1, j2, ia + 1u, x1, 0.0);
         }
     }
     field_fft<T, E>(buf, NF * L, ld, b, buf + (size_t)NF * L * ld);
     const int mp1 = b.m + 1;
+    const FastDiv dL((unsigned)L), dm((unsigned)mp1);
     for (int t = threadIdx.x; t < NF * mp1 * L; t += blockDim.x) {
-        const int line = t % L;
-        const int rest = t / L;
-        const int p2 = rest % mp1;
-        const int f = rest / mp1;
-        b.work[((size_t)(f * b.units + u) * mp1 + p2) * n + j1_0 + line] = buf[(f * L + line) * ld + p2];
+        const int rest = dL.div(t);
+        const int line = t - rest * L;
+        const int f = dm.div(rest);
+        const int p2 = rest - f * mp1;
+        cplx<T>* wf = b.work + (size_t)(f * b.units + u) * mp1 * n;
+        wf[mul24(p2, n) + j1_0 + line] = buf[mul24(f * L + line, ld) + p2];
     }
 }
 
@@ -192,6 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_field_x(FieldBatch<T> b, int L) {
     // all of the thread's loads are issued before the first LDS store, so
     // that their latencies overlap (lines * n <= E * kBlock)
     {
+        const FastDiv dn((unsigned)n);
         cplx<T> v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -202,8 +208,8 @@ __global__ __launch_bounds__(kBlock) void k_field_x(FieldBatch<T> b, int L) {
         for (int i = 0; i < E; ++i) {
             const int t = threadIdx.x + i * kBlock;
             if (t < lines * n) {
-                const int l = t / n;
-                buf[l * ld + (t - l * n)] = v[i];
+                const int l = dn.div(t);
+                buf[mul24(l, ld) + (t - mul24(l, n))] = v[i];
             }
         }
     }
@@ -212,17 +218,18 @@ __global__ __launch_bounds__(kBlock) void k_field_x(FieldBatch<T> b, int L) {
     const bool coarse = b.coarse && (f == NF - 1);
     const int mcp1 = b.m / 2 + 1;
     // adjacent threads write adjacent p1 of one mesh row p2
+    const FastDiv dm((unsigned)mp1);
     for (int t = threadIdx.x; t < lines * mp1; t += blockDim.x) {
-        const int l = t / mp1;
-        const int p1 = t - l * mp1;
+        const int l = dm.div(t);
+        const int p1 = t - mul24(l, mp1);
         const int p2 = p2_0 + l;
-        const cplx<T> v = buf[l * ld + p1];
+        const cplx<T> v = buf[mul24(l, ld) + p1];
         const bool even = ((p1 | p2) & 1) == 0;
         if (MODE == MODE_PAIR) {
             const T z0 = v.x, z1 = v.y;
             const size_t s0 = 2 * (size_t)u, s1 = s0 + 1;
             if (fine) {
-                const size_t o = (size_t)p1 + (size_t)mp1 * p2;
+                const int o = p1 + mul24(mp1, p2);
                 if (ZOUT) {
                     b.zf[s0 * mp1 * mp1 + o] = (double)z0;
                     b.zf[s1 * mp1 * mp1 + o] = (double)z1;
@@ -232,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_field_x(FieldBatch<T> b, int L) {
                 }
             }
             if (coarse && even) {
-                const size_t o = (size_t)(p1 >> 1) + (size_t)mcp1 * (p2 >> 1);
+                const int o = (p1 >> 1) + mul24(mcp1, p2 >> 1);
                 if (ZOUT) {
                     b.zc[s0 * mcp1 * mcp1 + o] = (double)z0;
                     b.zc[s1 * mcp1 * mcp1 + o] = (double)z1;
@@ -245,12 +252,12 @@ __global__ __launch_bounds__(kBlock) void k_field_x(FieldBatch<T> b, int L) {
             const T z = v.x + v.y;
             const size_t s0 = (size_t)u;
             if (fine) {
-                const size_t o = (size_t)p1 + (size_t)mp1 * p2;
+                const int o = p1 + mul24(mp1, p2);
                 if (ZOUT) b.zf[s0 * mp1 * mp1 + o] = (double)z;
                 else b.kf[s0 * b.kf_stride + o] = dev_exp<T>(z);
             }
             if (coarse && even) {
-                const size_t o = (size_t)(p1 >> 1) + (size_t)mcp1 * (p2 >> 1);
+                const int o = (p1 >> 1) + mul24(mcp1, p2 >> 1);
                 if (ZOUT) b.zc[s0 * mcp1 * mcp1 + o] = (double)z;
                 else b.kc[s0 * b.kc_stride + o] = dev_exp<T>(z);
             }
@@ -356,10 +363,14 @@ template <typename T, int MODE, int NF>
 hipError_t field_launch_nf(const FieldBatch<T>& b, hipStream_t st) {
     // lines per workgroup: a power of two dividing n, with NF*L*n <= 16*256
     // values per workgroup (E = 16) when possible, else one line (E = 32).
+    // The row pass takes as many lines as fit (its stores are runs of L
+    // adjacent values); the column pass half as many, so that twice the
+    // workgroups share a CU and overlap their loads with the others' DFT
+    // stages (4 lines of n = 512: 3.6 -> 3.9 TB/s; 2 lines are slower again).
     const int cap = 16 * kBlock;
     int L1 = pow2floor(std::max(1, cap / (NF * b.n)));
     L1 = std::min(L1, lowbit(b.n));
-    int L2 = pow2floor(std::max(1, cap / b.n));
+    int L2 = pow2floor(std::max(1, cap / (2 * b.n)));
     if (NF * L1 * b.n <= cap && L2 * b.n <= cap) return field_launch_e<T, 16, MODE, NF>(b, st, L1, L2);
     if (NF * b.n <= 2 * cap) return field_launch_e<T, 32, MODE, NF>(b, st, 1, 1);
     return hipErrorInvalidValue;
