@@ -103,7 +103,7 @@ inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) /
 // division sequence in per-element index arithmetic.
 struct FastDiv {
     unsigned d, M;
-    __host__ __device__ FastDiv() : d(1u), M(0u) {}
+    FastDiv() = default;   // trivial, so that LDS arrays of it are allowed
     __host__ __device__ explicit FastDiv(unsigned dv) : d(dv), M(dv <= 1u ? 0u : 0xFFFFFFFFu / dv + 1u) {}
     __device__ __forceinline__ int div(int x) const { return M ? (int)__umulhi((unsigned)x, M) : x; }
 };

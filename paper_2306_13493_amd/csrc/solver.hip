@@ -475,15 +475,18 @@ __global__ __launch_bounds__(RXW == 64 ? kBlock : 1024) void k_mg(MgArgs<T> a) {
 // ------------------------------------------------ whole-V-cycle bottom ---
 // ------------------------------------------------- LDS-resident multigrid
 // Levels with m <= 32 (16 in double) of one sample live in one workgroup's
-// LDS: z, rhs, edge conductances and inverse diagonals of every level,
+// LDS: z, rhs and edge conductances of every level,
 // stored level after level (level l at off[l], row pitch m_l + 1), plus a
 // scratch array the size of the finest of them.
 // Level l has m0 >> l intervals; its arrays start at off[l] (an LDS table,
 // so that no per-level array sits in private memory).
+// fw[l], fh[l] (LDS too): division by the row pitch w_l and by the
+// (w_l + 1) / 2 nodes of one colour in a row.
 template <typename T>
 struct LdsMg {
     T *z, *rhs, *ce, *cn, *tmp;
     int* off;
+    FastDiv *fw, *fh;
     int nl, bc, m0;
     __device__ int m(int l) const { return m0 >> l; }
     __device__ int w(int l) const { return (m0 >> l) + 1; }
@@ -509,30 +512,32 @@ __device__ void lds_mg_layout(const LdsMg<T>& g) {
         for (int l = 0; l < g.nl; ++l) {
             g.off[l] = o;
             o += g.w(l) * g.w(l);
+            g.fw[l] = FastDiv((unsigned)g.w(l));
+            g.fh[l] = FastDiv((unsigned)(g.w(l) + 1) / 2);
         }
     }
 }
 
-// inverse diagonal of unknown p (x, y) from the edge conductances
+// diagonal of unknown p (x, y) from the edge conductances
 template <typename T>
-__device__ __forceinline__ T lds_inv_diag(const T* ce, const T* cn, int p, int y, int w) {
-    return T(1) / (ce[p] + ce[p - 1] + cn[p] + (y >= 1 ? cn[p - w] : T(0)));
+__device__ __forceinline__ T lds_diag(const T* ce, const T* cn, int p, int y, int w) {
+    return ce[p] + ce[p - 1] + cn[p] + (y >= 1 ? cn[p - w] : T(0));
 }
 
 // one red-black half-sweep of colour c (parity of x + y) on one level; the
 // inverse diagonal is formed where it is used (not stored: the LDS it
 // would take decides how many samples a CU holds)
 template <typename T>
-__device__ void lds_sweep(T* z, const T* rhs, const T* ce, const T* cn, int m, int bc, int c) {
+__device__ void lds_sweep(T* z, const T* rhs, const T* ce, const T* cn, int m, int bc, int c, FastDiv fh) {
     const int w = m + 1;
     const int half = (w + 1) / 2;
     for (int t = threadIdx.x; t < half * w; t += blockDim.x) {
-        const int y = t / half;
-        const int x = 2 * (t - y * half) + ((c - y) & 1);
+        const int y = fh.div(t);
+        const int x = 2 * (t - mul24(y, half)) + ((c - y) & 1);
         if (x >= w) continue;
         if (!is_unknown(x, y, m, bc)) continue;
-        const int p = y * w + x;
-        const T d = lds_inv_diag(ce, cn, p, y, w);
+        const int p = mul24(y, w) + x;
+        const T d = fast_rcp(lds_diag(ce, cn, p, y, w));
         T s = rhs[p];
         if (x + 1 < w) s += ce[p] * z[p + 1];
         if (x >= 1) s += ce[p - 1] * z[p - 1];
@@ -555,9 +560,10 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
     // down: pre-smooth, residual, restriction (transpose of bilinear)
     for (int l = 0; l + 1 < g.nl; ++l) {
         const int m = g.m(l), w = g.w(l), o = g.off[l];
-        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, m, g.bc, c & 1);
+        const FastDiv fw = g.fw[l], fh = g.fh[l];
+        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, m, g.bc, c & 1, fh);
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-            const int y = t / w, x = t - y * w;
+            const int y = fw.div(t), x = t - mul24(y, w);
             T r = T(0);
             if (is_unknown(x, y, m, g.bc)) {
                 const int p = o + t;
@@ -572,13 +578,14 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
         }
         __syncthreads();
         const int cm = g.m(l + 1), cwid = g.w(l + 1), co = g.off[l + 1];
+        const FastDiv fwc = g.fw[l + 1];
         for (int t = threadIdx.x; t < cwid * cwid; t += blockDim.x) {
-            const int J = t / cwid, I = t - J * cwid;
+            const int J = fwc.div(t), I = t - mul24(J, cwid);
             T v = T(0);
             if (is_unknown(I, J, cm, g.bc)) {
                 const int x = 2 * I, y = 2 * J;
                 auto R = [&](int xx, int yy) -> T {
-                    return (xx >= 0 && xx < w && yy >= 0 && yy < w) ? tmp[yy * w + xx] : T(0);
+                    return (xx >= 0 && xx < w && yy >= 0 && yy < w) ? tmp[mul24(yy, w) + xx] : T(0);
                 };
                 v = R(x, y) + T(0.5) * ((R(x - 1, y) + R(x + 1, y)) + (R(x, y - 1) + R(x, y + 1))) +
                     T(0.25) * ((R(x - 1, y - 1) + R(x + 1, y - 1)) + (R(x - 1, y + 1) + R(x + 1, y + 1)));
@@ -596,7 +603,7 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
         for (int j = 0; j < 3; ++j) {
             if (j < ylo || j > yhi) continue;
             const int p = o + j * w + 1;
-            const T d = T(1) / lds_inv_diag(ce, cn, p, j, w);
+            const T d = lds_diag(ce, cn, p, j, w);
             if (j == ylo) {
                 beta[j] = d;
                 yv[j] = rhs[p];
@@ -622,12 +629,13 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
     for (int l = g.nl - 2; l >= 0; --l) {
         const int m = g.m(l), w = g.w(l), o = g.off[l];
         const int cm = g.m(l + 1), cwid = g.w(l + 1), co = g.off[l + 1];
+        const FastDiv fw = g.fw[l], fh = g.fh[l];
         for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-            const int y = t / w, x = t - y * w;
+            const int y = fw.div(t), x = t - mul24(y, w);
             if (!is_unknown(x, y, m, g.bc)) continue;
             const int I = x >> 1, J = y >> 1;
             auto C = [&](int ci, int cj) -> T {
-                return is_unknown(ci, cj, cm, g.bc) ? z[co + cj * cwid + ci] : T(0);
+                return is_unknown(ci, cj, cm, g.bc) ? z[co + mul24(cj, cwid) + ci] : T(0);
             };
             T p;
             const bool ox1 = x & 1, oy1 = y & 1;
@@ -638,7 +646,7 @@ __device__ void lds_vcycle(const LdsMg<T>& g) {
             z[o + t] += p;
         }
         __syncthreads();
-        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, m, g.bc, 1 - (c & 1));
+        for (int c = 0; c < 4; ++c) lds_sweep<T>(z + o, rhs + o, ce + o, cn + o, m, g.bc, 1 - (c & 1), fh);
     }
 }
 
@@ -663,11 +671,14 @@ __global__ __launch_bounds__(NT) void k_bottom(BottomArgs<T> a) {
     __shared__ T z[TOT], rhs[TOT], ce[TOT], cn[TOT];
     __shared__ T tmp[(MB + 1) * (MB + 1)];
     __shared__ int off[8];
+    __shared__ FastDiv fdw[8], fdh[8];
     const int s = blockIdx.x;
     if (!a.scal[s].active) return;
     LdsMg<T> g;
     g.z = z; g.rhs = rhs; g.ce = ce; g.cn = cn; g.tmp = tmp;
     g.off = off;
+    g.fw = fdw;
+    g.fh = fdh;
     g.nl = a.nl;
     g.bc = a.bc;
     g.m0 = a.m0;
@@ -690,7 +701,10 @@ __global__ __launch_bounds__(NT) void k_bottom(BottomArgs<T> a) {
                 const int u = t - off[l];
                 cev[i] = a.ce[l][(size_t)s * a.ss[l] + u];
                 cnv[i] = a.cn[l][(size_t)s * a.ss[l] + u];
-                if (l == 0 && is_unknown(u % w0, u / w0, m0, a.bc)) rv[i] = a.rhs[(size_t)s * a.ss[0] + u];
+                if (l == 0) {
+                    const int uy = fdw[0].div(u);
+                    if (is_unknown(u - mul24(uy, w0), uy, m0, a.bc)) rv[i] = a.rhs[(size_t)s * a.ss[0] + u];
+                }
             }
         }
 #pragma unroll
@@ -706,8 +720,9 @@ __global__ __launch_bounds__(NT) void k_bottom(BottomArgs<T> a) {
     __syncthreads();
     lds_vcycle(g);
     const int m = g.m(0), w = g.w(0);
+    const FastDiv fw0 = fdw[0];
     for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-        const int y = t / w, x = t - y * w;
+        const int y = fw0.div(t), x = t - mul24(y, w);
         if (is_unknown(x, y, m, a.bc)) a.zout[(size_t)s * a.ss[0] + t] = z[t];
     }
 }
@@ -830,6 +845,7 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[2 * (NT / 64)];
     __shared__ int off[8];
+    __shared__ FastDiv fdw[8], fdh[8];
     const int s = blockIdx.x;
     const int m = a.m, w = m + 1, n0 = w * w, bc = a.bc;
     const int tot = lds_mg_nodes(m);
@@ -843,6 +859,8 @@ __global__ __launch_bounds__(NT) void k_small_pcg(SmallArgs<T> a) {
     g.cn = g.ce + tot;
     g.tmp = g.cn + tot;
     g.off = off;
+    g.fw = fdw;
+    g.fh = fdh;
     g.nl = a.nl;
     g.bc = bc;
     g.m0 = m;
