@@ -119,7 +119,8 @@ __global__ __launch_bounds__(kBlock) void k_field_y(FieldBatch<T> b, int L) {
     }
     // scaled normal into line `line`, row j2 of the LDS buffer (and of the
     // coarse lines when a pair level takes two fields from one xi)
-    // (index products below 2^24 throughout: n <= 8192, L <= 16)
+    // (mul24 operands below 2^24 and products below 2^31 throughout:
+    // n <= 8192, L <= 16)
     auto put = [&](int line, int j2, uint32_t ia, double xr, double xi) {
         const double a = (double)b.af[ia];
         buf[mul24(line, ld) + j2] = cplx<T>{(T)(a * xr), (T)(a * xi)};

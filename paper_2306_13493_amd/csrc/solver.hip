@@ -735,58 +735,89 @@ __global__ __launch_bounds__(NT) void k_bottom(BottomArgs<T> a) {
 // (also on boundary lines, whose missing neighbour counts as zero where the
 // fine boundary edge has half the interior conductance).  Computed from
 // level 0's nodal k or from a stored level.
-__device__ __forceinline__ double hmean2(double a, double b) {
-    const double s = a + b;
-    return s > 0.0 ? 2.0 * a * b / s : 0.0;
+// harmonic mean 2ab/(a+b), zero when both conductances vanish; in float
+// (the mixed path's coarse operators) with the hardware reciprocal
+template <typename V>
+__device__ __forceinline__ V hmean2(V a, V b) {
+    const V s = a + b;
+    if constexpr (sizeof(V) == 4) return s > V(0) ? V(2) * a * b * fast_rcp(s) : V(0);
+    else return s > V(0) ? V(2) * a * b / s : V(0);
 }
 
-// E(x, y), N(x, y): fine east / north edge conductances, zero outside the mesh
+// E(x, y), N(x, y): fine east / north edge conductances, zero outside the
+// mesh; the arithmetic takes their value type
 template <typename EF>
-__device__ __forceinline__ double coarse_e(int I, int J, const EF& E) {
+__device__ __forceinline__ auto coarse_e(int I, int J, const EF& E) -> decltype(E(0, 0)) {
+    using V = decltype(E(0, 0));
     const int x = 2 * I, y = 2 * J;
-    return 0.5 * hmean2(E(x, y), E(x + 1, y)) +
-           0.25 * (hmean2(E(x, y - 1), E(x + 1, y - 1)) + hmean2(E(x, y + 1), E(x + 1, y + 1)));
+    return V(0.5) * hmean2(E(x, y), E(x + 1, y)) +
+           V(0.25) * (hmean2(E(x, y - 1), E(x + 1, y - 1)) + hmean2(E(x, y + 1), E(x + 1, y + 1)));
 }
 template <typename NF>
-__device__ __forceinline__ double coarse_n(int I, int J, const NF& N) {
+__device__ __forceinline__ auto coarse_n(int I, int J, const NF& N) -> decltype(N(0, 0)) {
+    using V = decltype(N(0, 0));
     const int x = 2 * I, y = 2 * J;
-    return 0.5 * hmean2(N(x, y), N(x, y + 1)) +
-           0.25 * (hmean2(N(x - 1, y), N(x - 1, y + 1)) + hmean2(N(x + 1, y), N(x + 1, y + 1)));
+    return V(0.5) * hmean2(N(x, y), N(x, y + 1)) +
+           V(0.25) * (hmean2(N(x - 1, y), N(x - 1, y + 1)) + hmean2(N(x + 1, y), N(x + 1, y + 1)));
 }
 
-// Coarse nodes in tiles of CCX x CCY per workgroup; the fine k they read
-// (fine nodes 2I-2 .. 2I+2 by 2J-2 .. 2J+2) is staged in LDS first.
+// Coarse nodes in tiles of at most CCX x CCY per workgroup; the fine k
+// they read (fine nodes 2I-2 .. 2I+2 by 2J-2 .. 2J+2) is staged in LDS
+// first.  The tile width ctw <= CCX splits the coarse rows into equal
+// parts (129 coarse columns: 5 tiles of 26, not 5 of 32).  The level-1
+// operator is computed in T (float on the mixed path, which stores it in
+// float anyway).
 constexpr int CCX = 32, CCY = kBlock / CCX;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarsen_k(const T* __restrict__ kf, long long kfss, Lvl F,
                                                       T* __restrict__ cec, T* __restrict__ cnc, Lvl C,
-                                                      int tiles_x) {
+                                                      int tiles_x, int ntiles, int ctw) {
     constexpr int KX = 2 * CCX + 3, KY = 2 * CCY + 3;
     __shared__ T kt[KY * KX];
-    const int s = blockIdx.y;
-    const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
-    const int I0 = tx * CCX, J0 = ty * CCY;
+    // one sample's tiles on one XCD: their overlapping fine rows share its L2
+    const int wi = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = wi / ntiles, tile = wi - s * ntiles;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int I0 = tx * ctw, J0 = ty * CCY;
     const int fx0 = 2 * I0 - 2, fy0 = 2 * J0 - 2;
     const T* k = kf + (size_t)s * kfss;
     const int m = F.m, w = F.w;
-    for (int t = threadIdx.x; t < KX * KY; t += blockDim.x) {
-        const int y = t / KX, x = t - y * KX;
-        const int gx = fx0 + x, gy = fy0 + y;
-        kt[t] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? k[(size_t)gy * w + gx] : T(0);
+    const int kx = 2 * ctw + 3;   // fine columns the tile reads
+    // fine rows of the tile, 64 lanes along each; every load of the tile
+    // (address clamped into the mesh) is issued before the first is stored
+    constexpr int NW = kBlock / 64, NYP = (KY + NW - 1) / NW, NXP = (KX + 63) / 64;
+    const int ly = (int)threadIdx.x >> 6, lx = (int)threadIdx.x & 63;
+    T v[NYP][NXP];
+#pragma unroll
+    for (int i = 0; i < NYP; ++i) {
+        const int gy = min(max(fy0 + ly + NW * i, 0), m);
+#pragma unroll
+        for (int c = 0; c < NXP; ++c) {
+            const int x = lx + 64 * c;
+            v[i][c] = (ly + NW * i < KY && x < kx) ? k[(size_t)gy * w + min(max(fx0 + x, 0), m)] : T(0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NYP; ++i) {
+        const int y = ly + NW * i, gy = fy0 + y;
+#pragma unroll
+        for (int c = 0; c < NXP; ++c) {
+            const int x = lx + 64 * c, gx = fx0 + x;
+            if (y < KY && x < kx) kt[y * KX + x] = (gx >= 0 && gx <= m && gy >= 0 && gy <= m) ? v[i][c] : T(0);
+        }
     }
     __syncthreads();
-    const int I = I0 + (int)threadIdx.x % CCX, J = J0 + (int)threadIdx.x / CCX;
-    if (I >= C.w || J >= C.w) return;
+    const int ix = (int)threadIdx.x % CCX;
+    const int I = I0 + ix, J = J0 + (int)threadIdx.x / CCX;
+    if (ix >= ctw || I >= C.w || J >= C.w) return;
     // the conductance formulas read only nodes inside the mesh
-    auto K = [&](int gx, int gy) -> double { return (double)kt[(gy - fy0) * KX + (gx - fx0)]; };
-    auto E = [&](int x, int y) -> double { return cond_e<double>(x, y, m, K); };
-    auto N = [&](int x, int y) -> double { return cond_n<double>(x, y, m, K); };
-    const double e = coarse_e(I, J, E);
-    const double n = coarse_n(I, J, N);
+    auto K = [&](int gx, int gy) -> T { return kt[(gy - fy0) * KX + (gx - fx0)]; };
+    auto E = [&](int x, int y) -> T { return cond_e<T>(x, y, m, K); };
+    auto N = [&](int x, int y) -> T { return cond_n<T>(x, y, m, K); };
     const size_t t = (size_t)J * C.w + I;
-    cec[(size_t)s * C.ss + t] = (T)e;
-    cnc[(size_t)s * C.ss + t] = (T)n;
+    cec[(size_t)s * C.ss + t] = coarse_e(I, J, E);
+    cnc[(size_t)s * C.ss + t] = coarse_n(I, J, N);
 }
 
 template <typename T>
@@ -1933,11 +1964,13 @@ public:
         // coefficient hierarchy
         for (int l = 0; l + 1 < nlev_; ++l) {
             const int ctx = (int)cdiv(lv_[l + 1].w, CCX), cty = (int)cdiv(lv_[l + 1].w, CCY);
-            const dim3 g(l == 0 ? (unsigned)(ctx * cty) : (unsigned)cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S);
+            const int ctw = (int)cdiv(lv_[l + 1].w, ctx);
+            const dim3 g = l == 0 ? dim3((unsigned)(ctx * cty * S))
+                                  : dim3((unsigned)cdiv((long long)lv_[l + 1].w * lv_[l + 1].w, kBlock), S);
             launch("coarsen", (l == 0 ? nv(0) : 2.0 * nv(l)) * sT + 2.0 * nv(l + 1) * sT, S, -1, st, [&](const Profiler::Slot& ps) {
                 if (l == 0)
                     PLAUNCH(k_coarsen_k<T>, g, dim3(kBlock), 0, st, k0_, kss, lv_[0], ptr<T>(o_ce_[0]),
-                                       ptr<T>(o_cn_[0]), lv_[1], ctx);
+                                       ptr<T>(o_cn_[0]), lv_[1], ctx, ctx * cty, ctw);
                 else
                     PLAUNCH(k_coarsen_c<T>, g, dim3(kBlock), 0, st, ptr<T>(o_ce_[l - 1]),
                                        ptr<T>(o_cn_[l - 1]), lv_[l], ptr<T>(o_ce_[l]), ptr<T>(o_cn_[l]), lv_[l + 1]);
