@@ -761,13 +761,14 @@ __device__ __forceinline__ auto coarse_n(int I, int J, const NF& N) -> decltype(
            V(0.25) * (hmean2(N(x - 1, y), N(x - 1, y + 1)) + hmean2(N(x + 1, y), N(x + 1, y + 1)));
 }
 
-// Coarse nodes in tiles of at most CCX x CCY per workgroup; the fine k
+// Coarse nodes in tiles of at most CCX x CCY per workgroup (each thread
+// takes two rows of a column); the fine k
 // they read (fine nodes 2I-2 .. 2I+2 by 2J-2 .. 2J+2) is staged in LDS
 // first.  The tile width ctw <= CCX splits the coarse rows into equal
 // parts (129 coarse columns: 5 tiles of 26, not 5 of 32).  The level-1
 // operator is computed in T (float on the mixed path, which stores it in
 // float anyway).
-constexpr int CCX = 32, CCY = kBlock / CCX;
+constexpr int CCX = 32, CCR = kBlock / CCX, CCY = 2 * CCR;   // CCR rows per pass, two passes
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarsen_k(const T* __restrict__ kf, long long kfss, Lvl F,
@@ -809,15 +810,20 @@ __global__ __launch_bounds__(kBlock) void k_coarsen_k(const T* __restrict__ kf, 
     }
     __syncthreads();
     const int ix = (int)threadIdx.x % CCX;
-    const int I = I0 + ix, J = J0 + (int)threadIdx.x / CCX;
-    if (ix >= ctw || I >= C.w || J >= C.w) return;
+    const int I = I0 + ix;
+    if (ix >= ctw || I >= C.w) return;
     // the conductance formulas read only nodes inside the mesh
     auto K = [&](int gx, int gy) -> T { return kt[(gy - fy0) * KX + (gx - fx0)]; };
     auto E = [&](int x, int y) -> T { return cond_e<T>(x, y, m, K); };
     auto N = [&](int x, int y) -> T { return cond_n<T>(x, y, m, K); };
-    const size_t t = (size_t)J * C.w + I;
-    cec[(size_t)s * C.ss + t] = coarse_e(I, J, E);
-    cnc[(size_t)s * C.ss + t] = coarse_n(I, J, N);
+#pragma unroll
+    for (int r = 0; r < CCY / CCR; ++r) {
+        const int J = J0 + (int)threadIdx.x / CCX + r * CCR;
+        if (J >= C.w) break;
+        const size_t t = (size_t)J * C.w + I;
+        cec[(size_t)s * C.ss + t] = coarse_e(I, J, E);
+        cnc[(size_t)s * C.ss + t] = coarse_n(I, J, N);
+    }
 }
 
 template <typename T>
@@ -830,14 +836,19 @@ __global__ __launch_bounds__(kBlock) void k_coarsen_c(const T* __restrict__ cef,
     const T* ce = cef + (size_t)s * F.ss;
     const T* cn = cnf + (size_t)s * F.ss;
     const int m = F.m, w = F.w;
-    auto E = [&](int x, int y) -> double {
-        return (x >= 0 && y >= 0 && x <= m && y <= m) ? (double)ce[(size_t)y * w + x] : 0.0;
+    // loads clamped into the mesh and masked afterwards, so that all twelve
+    // are issued before the first is used; the arithmetic is in T, as in
+    // k_coarsen_k
+    auto E = [&](int x, int y) -> T {
+        const T v = ce[min(max(y, 0), m) * w + min(max(x, 0), m)];
+        return (x >= 0 && y >= 0 && x <= m && y <= m) ? v : T(0);
     };
-    auto N = [&](int x, int y) -> double {
-        return (x >= 0 && y >= 0 && x <= m && y <= m) ? (double)cn[(size_t)y * w + x] : 0.0;
+    auto N = [&](int x, int y) -> T {
+        const T v = cn[min(max(y, 0), m) * w + min(max(x, 0), m)];
+        return (x >= 0 && y >= 0 && x <= m && y <= m) ? v : T(0);
     };
-    cec[(size_t)s * C.ss + t] = (T)coarse_e(I, J, E);
-    cnc[(size_t)s * C.ss + t] = (T)coarse_n(I, J, N);
+    cec[(size_t)s * C.ss + t] = coarse_e(I, J, E);
+    cnc[(size_t)s * C.ss + t] = coarse_n(I, J, N);
 }
 
 // ------------------------------------------- whole solve of a small mesh
